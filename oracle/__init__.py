@@ -1,0 +1,230 @@
+"""CPU oracle for the hydro step -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path (the HIP library and
+its Python binding) never touches it, and the two share no code.
+
+The arithmetic lives in ``hydro_ref.c`` (plain C, FP64, -ffp-contract=off);
+this module builds and loads it with ctypes and marshals numpy arrays.
+The functions follow the method described in Sec. II ("Solvers"): PPM
+reconstruction at 26 quadrature points, central-upwind (Kurganov-Tadmor)
+face flux with Newton-Cotes (Simpson) quadrature, finite-volume divergence.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hydro_ref.c")
+_LIB = os.path.join(_HERE, "libhydro_ref.so")
+
+CFLAGS = ["-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+          "-fno-fast-math", "-Wall", "-Wextra"]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc into ``oracle/libhydro_ref.so``."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("de_switch", ctypes.c_double),
+                ("dt", ctypes.c_double), ("flags", ctypes.c_uint32)]
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [("n_sub", ctypes.c_int32), ("fstride", ctypes.c_int32),
+                ("offset", ctypes.POINTER(ctypes.c_int64)),
+                ("h", ctypes.POINTER(ctypes.c_double)),
+                ("n_species", ctypes.POINTER(ctypes.c_int32))]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int32)
+        lp = ctypes.POINTER(ctypes.c_int64)
+        P, B = ctypes.POINTER(Params), ctypes.POINTER(Batch)
+        L.hydro_ref_ppm1d.argtypes = [dp, dp, dp]
+        L.hydro_ref_state_flux.argtypes = [P, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, dp, ip]
+        L.hydro_ref_face.argtypes = [P, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, ip]
+        L.hydro_ref_reconstruct.argtypes = [P, B, dp, dp, lp]
+        L.hydro_ref_flux.argtypes = [P, B, dp, lp, dp, lp, dp, ip]
+        L.hydro_ref_divergence.argtypes = [P, B, dp, lp, dp, dp]
+        L.hydro_ref_step.argtypes = [P, B, dp, dp, dp, ip]
+        L.hydro_ref_q_elems.argtypes = [ctypes.c_int]
+        L.hydro_ref_q_elems.restype = ctypes.c_int64
+        L.hydro_ref_f_elems.argtypes = [ctypes.c_int]
+        L.hydro_ref_f_elems.restype = ctypes.c_int64
+        for name in ("hydro_ref_ppm1d", "hydro_ref_state_flux", "hydro_ref_face",
+                     "hydro_ref_reconstruct", "hydro_ref_flux", "hydro_ref_divergence",
+                     "hydro_ref_step"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def params(gamma=5.0 / 3.0, de_switch=1e-3, dt=0.0):
+    return Params(float(gamma), float(de_switch), float(dt), 0)
+
+
+class _BatchArgs:
+    """Keeps the metadata arrays alive while a call runs."""
+
+    def __init__(self, offset, h, n_species, fstride):
+        self.offset = np.ascontiguousarray(offset, dtype=np.int64)
+        self.h = np.ascontiguousarray(h, dtype=np.float64)
+        self.n_species = np.ascontiguousarray(n_species, dtype=np.int32)
+        n = len(self.offset)
+        self.struct = Batch(n, int(fstride),
+                            self.offset.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                            self.h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                            self.n_species.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+
+
+def ppm1d(u):
+    """PPM on five values u_{-2..2}; returns (q+, q-) of the middle cell."""
+    u = _f64(u)
+    assert u.shape == (5,)
+    qp, qm = ctypes.c_double(), ctypes.c_double()
+    rc = lib().hydro_ref_ppm1d(_dp(u), ctypes.byref(qp), ctypes.byref(qm))
+    assert rc == 0
+    return qp.value, qm.value
+
+
+def state_flux(V, axis, gamma=5.0 / 3.0, de_switch=1e-3):
+    """Physical flux F(V) along axis, normal velocity, sound speed, pressure, status."""
+    V = _f64(V)
+    nf = V.shape[0]
+    F = np.zeros(nf)
+    un, cs, p = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    st = ctypes.c_int32()
+    prm = params(gamma, de_switch)
+    rc = lib().hydro_ref_state_flux(ctypes.byref(prm), nf, axis, _dp(V), _dp(F),
+                                    ctypes.byref(un), ctypes.byref(cs), ctypes.byref(p),
+                                    ctypes.byref(st))
+    assert rc == 0
+    return F, un.value, cs.value, p.value, st.value
+
+
+def face(VL, VR, axis, gamma=5.0 / 3.0, de_switch=1e-3):
+    """Central-upwind Simpson-averaged flux of one face from [9][nf] states."""
+    VL, VR = _f64(VL), _f64(VR)
+    assert VL.shape == VR.shape and VL.shape[0] == 9
+    nf = VL.shape[1]
+    Fbar = np.zeros(nf)
+    a = ctypes.c_double()
+    st = ctypes.c_int32()
+    prm = params(gamma, de_switch)
+    rc = lib().hydro_ref_face(ctypes.byref(prm), nf, axis, _dp(VL), _dp(VR), _dp(Fbar),
+                              ctypes.byref(a), ctypes.byref(st))
+    assert rc == 0
+    return Fbar, a.value, st.value
+
+
+def q_elems(n_species):
+    return int(lib().hydro_ref_q_elems(int(n_species)))
+
+
+def f_elems(n_species):
+    return int(lib().hydro_ref_f_elems(int(n_species)))
+
+
+def packed_offsets(sizes):
+    off = np.zeros(len(sizes), dtype=np.int64)
+    if len(sizes) > 1:
+        off[1:] = np.cumsum(np.asarray(sizes[:-1], dtype=np.int64))
+    return off
+
+
+def reconstruct(U, offset, h, n_species, fstride, gamma=5.0 / 3.0, de_switch=1e-3):
+    """Q for every subgrid, packed; returns (Q, q_offset)."""
+    U = _f64(U)
+    ba = _BatchArgs(offset, h, n_species, fstride)
+    q_off = packed_offsets([q_elems(ns) for ns in ba.n_species])
+    total = int(q_off[-1] + q_elems(ba.n_species[-1])) if len(q_off) else 0
+    Q = np.zeros(total)
+    prm = params(gamma, de_switch)
+    rc = lib().hydro_ref_reconstruct(ctypes.byref(prm), ctypes.byref(ba.struct), _dp(U), _dp(Q),
+                                     q_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    assert rc == 0, rc
+    return Q, q_off
+
+
+def flux(Q, q_offset, offset, h, n_species, fstride, gamma=5.0 / 3.0, de_switch=1e-3):
+    """Face fluxes; returns (F, f_offset, amax, status)."""
+    Q = _f64(Q)
+    q_offset = np.ascontiguousarray(q_offset, dtype=np.int64)
+    ba = _BatchArgs(offset, h, n_species, fstride)
+    f_off = packed_offsets([f_elems(ns) for ns in ba.n_species])
+    total = int(f_off[-1] + f_elems(ba.n_species[-1])) if len(f_off) else 0
+    F = np.zeros(total)
+    amax = np.zeros(len(ba.offset))
+    status = np.zeros(len(ba.offset), dtype=np.int32)
+    prm = params(gamma, de_switch)
+    rc = lib().hydro_ref_flux(ctypes.byref(prm), ctypes.byref(ba.struct), _dp(Q),
+                              q_offset.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(F),
+                              f_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(amax),
+                              status.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    assert rc == 0, rc
+    return F, f_off, amax, status
+
+
+def divergence(F, f_offset, U_in, offset, h, n_species, fstride, dt,
+               gamma=5.0 / 3.0, de_switch=1e-3):
+    """U_out from face fluxes; ghosts of U_out are copied from U_in."""
+    F, U_in = _f64(F), _f64(U_in)
+    f_offset = np.ascontiguousarray(f_offset, dtype=np.int64)
+    ba = _BatchArgs(offset, h, n_species, fstride)
+    U_out = U_in.copy()
+    prm = params(gamma, de_switch, dt)
+    rc = lib().hydro_ref_divergence(ctypes.byref(prm), ctypes.byref(ba.struct), _dp(F),
+                                    f_offset.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                    _dp(U_in), _dp(U_out))
+    assert rc == 0, rc
+    return U_out
+
+
+def step(U_in, offset, h, n_species, fstride, dt, gamma=5.0 / 3.0, de_switch=1e-3):
+    """One forward-Euler hydro stage; returns (U_out, amax, status).
+
+    Ghost cells of U_out are copies of U_in (the step never writes them)."""
+    U_in = _f64(U_in)
+    ba = _BatchArgs(offset, h, n_species, fstride)
+    U_out = U_in.copy()
+    n = len(ba.offset)
+    amax = np.zeros(n)
+    status = np.zeros(n, dtype=np.int32)
+    prm = params(gamma, de_switch, dt)
+    rc = lib().hydro_ref_step(ctypes.byref(prm), ctypes.byref(ba.struct), _dp(U_in),
+                              _dp(U_out), _dp(amax),
+                              status.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    assert rc == 0, rc
+    return U_out, amax, status
+
+
+def raw_call(name, *args):
+    """Direct access for argument-validation tests."""
+    return getattr(lib(), name)(*args)

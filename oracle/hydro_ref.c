@@ -1,0 +1,443 @@
+/*
+ * hydro_ref.c -- CPU oracle for the finite-volume hydro step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, single-threaded
+ * FP64 definition that the GPU library is checked against.  Only the test
+ * suite, the smoke check and the CPU-baseline leg of the benchmark may load
+ * it.  It shares no code, header, table or constant with the GPU path.
+ *
+ * What it computes (Sec. II, "Solvers"): the hydro solver evolves the
+ * inviscid Euler equations with finite volumes; a `reconstruct` step uses the
+ * piecewise-parabolic method to compute the evolved variables at 26
+ * quadrature points of every cell, and a `flux` step turns those values into
+ * face fluxes integrated with Newton-Cotes quadrature (the central-upwind
+ * scheme of Kurganov and Tadmor).  The paper names the kernels and the
+ * methods but prints no formulas, so the step list below is the textbook
+ * reading of each named method:
+ *
+ *   O1  the 26 directions d in {-1,0,1}^3 \ {0}; the 13 "lines" are the
+ *       directions with n(d) = 9(dz+1) + 3(dy+1) + (dx+1) > 13.
+ *   O2  Colella-Woodward (1984) PPM along the line of cell centres c + m d,
+ *       m = -2..2: monotonised-central slopes, 4th-order interface values,
+ *       CW84 monotonicity.  q+ is the value at c + d/2, q- at c - d/2.
+ *   O3  ideal-gas state with a dual-energy switch (entropy tracer tau,
+ *       tau^gamma = internal energy density).
+ *   O4  central-upwind flux with one-sided speeds a+/a- taken per face
+ *       over the face's 9 surface points, integrated with the tensor
+ *       Simpson (3-point closed Newton-Cotes) rule.
+ *   O5  divergence and forward-Euler update of the 8^3 interior.
+ *
+ * Floating point: IEEE binary64, compiled with -ffp-contract=off; every
+ * operation is written in the order that is evaluated.
+ *
+ * Parity pins: every function here is pinned by the CPU tests against
+ * closed forms, hand-computed cases, exactness and symmetry invariants,
+ * conservation and an exact Riemann solution; none is "parity unpinned".
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- the boundary's data contract, restated for the host ---------------- */
+
+typedef struct {
+    double gamma;      /* ratio of specific heats                             */
+    double de_switch;  /* dual-energy switch: use tau^gamma if e_i < eps * E  */
+    double dt;         /* time step of the forward-Euler stage                */
+    uint32_t flags;    /* reserved, must be 0                                 */
+} hydro_ref_params;
+
+typedef struct {
+    int32_t n_sub;              /* number of subgrids                          */
+    int32_t fstride;            /* elements between fields of one subgrid      */
+    const int64_t *offset;      /* [n_sub] element offset of field 0           */
+    const double *h;            /* [n_sub] cell size                           */
+    const int32_t *n_species;   /* [n_sub] passive species, 0..5               */
+} hydro_ref_batch;
+
+enum { REF_OK = 0, REF_EINVAL = -1 };
+
+#define NB 14            /* cells per dimension incl. 3 ghost layers each side */
+#define NC (NB * NB * NB)
+#define QN 10            /* reconstructed cells per dimension: [2,12)          */
+#define QC (QN * QN * QN)
+#define NFACE 576        /* faces per axis: 9 x 8 x 8                          */
+
+static const int F_RHO = 0, F_SX = 1, F_EGAS = 4, F_TAU = 5;
+
+static int cell_index(int i, int j, int k) { return (k * NB + j) * NB + i; }
+
+/* O1: direction slot of d, 0..25 (the centre n = 13 is skipped). */
+static int dir_slot(int dx, int dy, int dz)
+{
+    int n = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1);
+    return n < 13 ? n : n - 1;
+}
+
+static int q_index(int f, int slot, int i, int j, int k)
+{
+    return (f * 26 + slot) * QC + ((k - 2) * QN + (j - 2)) * QN + (i - 2);
+}
+
+/* ---- O2: one-dimensional PPM ------------------------------------------- */
+
+/* Monotonised-central limited slope at the middle of (ul, uc, ur). */
+static double mc_slope(double ul, double uc, double ur)
+{
+    double dm = uc - ul;             /* Delta^- */
+    double dp = ur - uc;             /* Delta^+ */
+    double d = 0.5 * (dp + dm);
+    if (dp * dm > 0.0) {
+        double lim = fmin(2.0 * fabs(dm), 2.0 * fabs(dp));
+        return copysign(fmin(fabs(d), lim), d);
+    }
+    return 0.0;
+}
+
+/*
+ * PPM on the five values u[0..4] = u_{-2..2} of one line; returns the value
+ * at the +half face (q+) and at the -half face (q-) of the middle cell.
+ */
+int hydro_ref_ppm1d(const double *u, double *qp_out, double *qm_out)
+{
+    const double sixth = 1.0 / 6.0;
+    double s_m = mc_slope(u[0], u[1], u[2]);   /* slope at m = -1 */
+    double s_0 = mc_slope(u[1], u[2], u[3]);   /* slope at m =  0 */
+    double s_p = mc_slope(u[2], u[3], u[4]);   /* slope at m = +1 */
+    double u0 = u[2];
+    double qp = 0.5 * (u0 + u[3]) - (s_p - s_0) * sixth;
+    double qm = 0.5 * (u[1] + u0) - (s_0 - s_m) * sixth;
+    if ((qp - u0) * (u0 - qm) <= 0.0) {
+        /* u0 is a local extremum: the parabola is flattened */
+        qp = u0;
+        qm = u0;
+    } else {
+        double dq = qp - qm;
+        double m6 = 6.0 * (u0 - 0.5 * (qm + qp));
+        if (dq * m6 > dq * dq) {
+            qm = 3.0 * u0 - 2.0 * qp;          /* overshoot near the - face */
+        } else if (-(dq * dq) > dq * m6) {
+            qp = 3.0 * u0 - 2.0 * qm;          /* overshoot near the + face */
+        }
+    }
+    *qp_out = qp;
+    *qm_out = qm;
+    return REF_OK;
+}
+
+/* ---- O3: state and physical flux at one quadrature point ---------------- */
+
+typedef struct {
+    double un;    /* normal velocity                                          */
+    double cs;    /* sound speed                                              */
+    double p;     /* pressure                                                 */
+} point_state;
+
+/*
+ * Primitive state of the nf conserved values V and the physical flux F along
+ * `axis`.  Returns the status bits (1: rho <= 0, 2: p <= 0).
+ */
+static int state_and_flux(const hydro_ref_params *prm, int nf, int axis,
+                          const double *V, double *F, point_state *st)
+{
+    double gamma = prm->gamma;
+    double rho = V[F_RHO];
+    double r = 1.0 / rho;
+    double vx = V[F_SX + 0] * r;
+    double vy = V[F_SX + 1] * r;
+    double vz = V[F_SX + 2] * r;
+    double ek = 0.5 * ((V[F_SX + 0] * vx + V[F_SX + 1] * vy) + V[F_SX + 2] * vz);
+    double E = V[F_EGAS];
+    double ei = E - ek;
+    if (ei < prm->de_switch * E) {
+        ei = pow(V[F_TAU], gamma);     /* dual energy: tau^gamma = e_i */
+    }
+    double p = (gamma - 1.0) * ei;
+    double cs = sqrt((gamma * p) * r);
+    double un = axis == 0 ? vx : (axis == 1 ? vy : vz);
+    int bits = 0;
+    if (rho <= 0.0) bits |= 1;
+    if (p <= 0.0) bits |= 2;
+
+    if (F) {
+        F[F_RHO] = V[F_SX + axis];
+        for (int b = 0; b < 3; b++) {
+            F[F_SX + b] = V[F_SX + b] * un;
+            if (b == axis) F[F_SX + b] = F[F_SX + b] + p;
+        }
+        F[F_EGAS] = (E + p) * un;
+        F[F_TAU] = V[F_TAU] * un;
+        for (int f = 6; f < nf; f++) F[f] = V[f] * un;
+    }
+    st->un = un;
+    st->cs = cs;
+    st->p = p;
+    return bits;
+}
+
+int hydro_ref_state_flux(const hydro_ref_params *prm, int nf, int axis,
+                         const double *V, double *F, double *un, double *cs,
+                         double *p, int32_t *status)
+{
+    if (!prm || !V || nf < 6 || nf > 11 || axis < 0 || axis > 2) return REF_EINVAL;
+    point_state st;
+    int bits = state_and_flux(prm, nf, axis, V, F, &st);
+    if (un) *un = st.un;
+    if (cs) *cs = st.cs;
+    if (p) *p = st.p;
+    if (status) *status = bits;
+    return REF_OK;
+}
+
+/* ---- O4: central-upwind flux of one face, tensor Simpson average -------- */
+
+/*
+ * VL, VR: [9][nf] states left and right of the face at the tangential
+ * offsets t = (tb, tb2), stored at index (tb2 + 1) * 3 + (tb + 1), where b
+ * and b2 are the two other axes in increasing order.  Writes the averaged
+ * flux Fbar[nf] and the face speed max(a+, -a-).  Returns status bits.
+ */
+static int face_flux(const hydro_ref_params *prm, int nf, int axis,
+                     const double *VL, const double *VR,
+                     double *Fbar, double *amax_face)
+{
+    double FL[9][11], FR[9][11];
+    point_state sl[9], sr[9];
+    int bits = 0;
+    double lam_p = -INFINITY, lam_m = INFINITY;
+    for (int t = 0; t < 9; t++) {
+        bits |= state_and_flux(prm, nf, axis, VL + t * nf, FL[t], &sl[t]);
+        bits |= state_and_flux(prm, nf, axis, VR + t * nf, FR[t], &sr[t]);
+        lam_p = fmax(lam_p, fmax(sl[t].un + sl[t].cs, sr[t].un + sr[t].cs));
+        lam_m = fmin(lam_m, fmin(sl[t].un - sl[t].cs, sr[t].un - sr[t].cs));
+    }
+    double ap = fmax(0.0, lam_p);
+    double am = fmin(0.0, lam_m);
+    double inv = 1.0 / (ap - am);
+    double apam = ap * am;
+
+    const double sixth = 1.0 / 6.0;
+    const double two_thirds = 4.0 / 6.0;
+    for (int f = 0; f < nf; f++) {
+        double H[9];
+        for (int t = 0; t < 9; t++) {
+            double vl = VL[t * nf + f], vr = VR[t * nf + f];
+            H[t] = (((ap * FL[t][f]) - (am * FR[t][f])) + (apam * (vr - vl))) * inv;
+        }
+        double r[3];
+        for (int t2 = 0; t2 < 3; t2++) {
+            const double *row = H + t2 * 3;       /* row[0]: tb=-1, row[2]: tb=+1 */
+            r[t2] = sixth * (row[0] + row[2]) + two_thirds * row[1];
+        }
+        Fbar[f] = sixth * (r[0] + r[2]) + two_thirds * r[1];
+    }
+    *amax_face = fmax(ap, -am);
+    return bits;
+}
+
+int hydro_ref_face(const hydro_ref_params *prm, int nf, int axis,
+                   const double *VL, const double *VR, double *Fbar,
+                   double *amax_face, int32_t *status)
+{
+    if (!prm || !VL || !VR || !Fbar || nf < 6 || nf > 11 || axis < 0 || axis > 2)
+        return REF_EINVAL;
+    double a = 0.0;
+    int bits = face_flux(prm, nf, axis, VL, VR, Fbar, &a);
+    if (amax_face) *amax_face = a;
+    if (status) *status = bits;
+    return REF_OK;
+}
+
+/* ---- argument checks ----------------------------------------------------- */
+
+static int check_batch(const hydro_ref_batch *b)
+{
+    if (!b || b->n_sub < 0 || b->fstride < NC) return REF_EINVAL;
+    if (b->n_sub > 0 && (!b->offset || !b->h || !b->n_species)) return REF_EINVAL;
+    for (int s = 0; s < b->n_sub; s++) {
+        if (b->n_species[s] < 0 || b->n_species[s] > 5) return REF_EINVAL;
+        if (b->offset[s] < 0) return REF_EINVAL;
+    }
+    return REF_OK;
+}
+
+/* ---- per-subgrid stages ------------------------------------------------- */
+
+/* O2 over one subgrid: Q for cells [2,12)^3, all 26 directions, nf fields. */
+static void reconstruct_subgrid(const double *U, int fstride, int nf, double *Q)
+{
+    for (int f = 0; f < nf; f++) {
+        const double *Uf = U + (int64_t)f * fstride;
+        for (int dz = -1; dz <= 1; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+        for (int dx = -1; dx <= 1; dx++) {
+            int n = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1);
+            if (n <= 13) continue;                   /* only the 13 lines */
+            int sp = dir_slot(dx, dy, dz), sm = dir_slot(-dx, -dy, -dz);
+            for (int k = 2; k < 12; k++)
+            for (int j = 2; j < 12; j++)
+            for (int i = 2; i < 12; i++) {
+                double u[5];
+                for (int m = -2; m <= 2; m++)
+                    u[m + 2] = Uf[cell_index(i + m * dx, j + m * dy, k + m * dz)];
+                double qp, qm;
+                hydro_ref_ppm1d(u, &qp, &qm);
+                Q[q_index(f, sp, i, j, k)] = qp;
+                Q[q_index(f, sm, i, j, k)] = qm;
+            }
+        }
+    }
+}
+
+/* Index of the face with left cell (i,j,k) on `axis` inside its 576-box. */
+static int face_index(int axis, int i, int j, int k)
+{
+    if (axis == 0) return ((k - 3) * 8 + (j - 3)) * 9 + (i - 2);
+    if (axis == 1) return ((k - 3) * 9 + (j - 2)) * 8 + (i - 3);
+    return ((k - 2) * 8 + (j - 3)) * 8 + (i - 3);
+}
+
+/* O4 over one subgrid: F[f][axis][576] and the subgrid's max face speed. */
+static int flux_subgrid(const hydro_ref_params *prm, const double *Q, int nf,
+                        double *F, double *amax_out)
+{
+    int bits = 0;
+    double amax = 0.0;
+    double VL[9 * 11], VR[9 * 11], Fbar[11];
+    for (int axis = 0; axis < 3; axis++) {
+        int b = axis == 0 ? 1 : 0;                  /* tangential axes, b < b2 */
+        int b2 = axis == 2 ? 1 : 2;
+        int lo[3] = {3, 3, 3}, hi[3] = {11, 11, 11};
+        lo[axis] = 2;                               /* left cells 2..10 */
+        hi[axis] = 11;
+        for (int k = lo[2]; k < hi[2]; k++)
+        for (int j = lo[1]; j < hi[1]; j++)
+        for (int i = lo[0]; i < hi[0]; i++) {
+            int cl[3] = {i, j, k};
+            int cr[3] = {i, j, k};
+            cr[axis] += 1;
+            for (int t2 = -1; t2 <= 1; t2++)
+            for (int t1 = -1; t1 <= 1; t1++) {
+                int dl[3] = {0, 0, 0}, dr[3] = {0, 0, 0};
+                dl[axis] = 1;
+                dr[axis] = -1;
+                dl[b] = t1; dr[b] = t1;
+                dl[b2] = t2; dr[b2] = t2;
+                int sl = dir_slot(dl[0], dl[1], dl[2]);
+                int sr = dir_slot(dr[0], dr[1], dr[2]);
+                int t = (t2 + 1) * 3 + (t1 + 1);
+                for (int f = 0; f < nf; f++) {
+                    VL[t * nf + f] = Q[q_index(f, sl, cl[0], cl[1], cl[2])];
+                    VR[t * nf + f] = Q[q_index(f, sr, cr[0], cr[1], cr[2])];
+                }
+            }
+            double af;
+            bits |= face_flux(prm, nf, axis, VL, VR, Fbar, &af);
+            int fi = face_index(axis, i, j, k);
+            for (int f = 0; f < nf; f++) {
+                F[(f * 3 + axis) * NFACE + fi] = Fbar[f];
+                if (!isfinite(Fbar[f])) bits |= 4;
+            }
+            amax = fmax(amax, af);
+        }
+    }
+    if (!isfinite(amax)) bits |= 4;
+    *amax_out = amax;
+    return bits;
+}
+
+/* O5 over one subgrid: U_out = U - (dt/h) ((dFx + dFy) + dFz) on [3,11)^3. */
+static int divergence_subgrid(const double *F, const double *U, double *Uo,
+                              int fstride, int nf, double dt, double h)
+{
+    int bits = 0;
+    double lam = dt / h;
+    for (int f = 0; f < nf; f++) {
+        const double *Uf = U + (int64_t)f * fstride;
+        double *Of = Uo + (int64_t)f * fstride;
+        for (int k = 3; k < 11; k++)
+        for (int j = 3; j < 11; j++)
+        for (int i = 3; i < 11; i++) {
+            const double *Fx = F + (f * 3 + 0) * NFACE;
+            const double *Fy = F + (f * 3 + 1) * NFACE;
+            const double *Fz = F + (f * 3 + 2) * NFACE;
+            double dfx = Fx[face_index(0, i, j, k)] - Fx[face_index(0, i - 1, j, k)];
+            double dfy = Fy[face_index(1, i, j, k)] - Fy[face_index(1, i, j - 1, k)];
+            double dfz = Fz[face_index(2, i, j, k)] - Fz[face_index(2, i, j, k - 1)];
+            int c = cell_index(i, j, k);
+            double v = Uf[c] - lam * ((dfx + dfy) + dfz);
+            Of[c] = v;
+            if (!isfinite(v)) bits |= 4;
+        }
+    }
+    return bits;
+}
+
+/* ---- the four entry points ------------------------------------------------ */
+
+int64_t hydro_ref_q_elems(int n_species) { return (int64_t)26 * (6 + n_species) * QC; }
+int64_t hydro_ref_f_elems(int n_species) { return (int64_t)3 * (6 + n_species) * NFACE; }
+
+int hydro_ref_reconstruct(const hydro_ref_params *prm, const hydro_ref_batch *b,
+                          const double *U, double *Q, const int64_t *q_offset)
+{
+    if (!prm || check_batch(b) != REF_OK) return REF_EINVAL;
+    if (b->n_sub > 0 && (!U || !Q || !q_offset)) return REF_EINVAL;
+    for (int s = 0; s < b->n_sub; s++)
+        reconstruct_subgrid(U + b->offset[s], b->fstride, 6 + b->n_species[s],
+                            Q + q_offset[s]);
+    return REF_OK;
+}
+
+int hydro_ref_flux(const hydro_ref_params *prm, const hydro_ref_batch *b,
+                   const double *Q, const int64_t *q_offset, double *F,
+                   const int64_t *f_offset, double *amax, int32_t *status)
+{
+    if (!prm || check_batch(b) != REF_OK) return REF_EINVAL;
+    if (b->n_sub > 0 && (!Q || !q_offset || !F || !f_offset || !amax)) return REF_EINVAL;
+    for (int s = 0; s < b->n_sub; s++) {
+        double a;
+        int bits = flux_subgrid(prm, Q + q_offset[s], 6 + b->n_species[s],
+                                F + f_offset[s], &a);
+        amax[s] = a;
+        if (status) status[s] = bits;
+    }
+    return REF_OK;
+}
+
+int hydro_ref_divergence(const hydro_ref_params *prm, const hydro_ref_batch *b,
+                         const double *F, const int64_t *f_offset,
+                         const double *U_in, double *U_out)
+{
+    if (!prm || check_batch(b) != REF_OK) return REF_EINVAL;
+    if (b->n_sub > 0 && (!F || !f_offset || !U_in || !U_out)) return REF_EINVAL;
+    for (int s = 0; s < b->n_sub; s++)
+        divergence_subgrid(F + f_offset[s], U_in + b->offset[s], U_out + b->offset[s],
+                           b->fstride, 6 + b->n_species[s], prm->dt, b->h[s]);
+    return REF_OK;
+}
+
+int hydro_ref_step(const hydro_ref_params *prm, const hydro_ref_batch *b,
+                   const double *U_in, double *U_out, double *amax, int32_t *status)
+{
+    if (!prm || check_batch(b) != REF_OK) return REF_EINVAL;
+    if (b->n_sub > 0 && (!U_in || !U_out || !amax)) return REF_EINVAL;
+    double *Q = (double *)malloc(sizeof(double) * hydro_ref_q_elems(5));
+    double *F = (double *)malloc(sizeof(double) * hydro_ref_f_elems(5));
+    if (!Q || !F) { free(Q); free(F); return REF_EINVAL; }
+    for (int s = 0; s < b->n_sub; s++) {
+        int nf = 6 + b->n_species[s];
+        const double *U = U_in + b->offset[s];
+        reconstruct_subgrid(U, b->fstride, nf, Q);
+        double a;
+        int bits = flux_subgrid(prm, Q, nf, F, &a);
+        bits |= divergence_subgrid(F, U, U_out + b->offset[s], b->fstride, nf,
+                                   prm->dt, b->h[s]);
+        amax[s] = a;
+        if (status) status[s] = bits;
+    }
+    free(Q);
+    free(F);
+    return REF_OK;
+}
