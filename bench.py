@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused FP64 hydro stage on one MI355X.
+
+Workload (timed): the 128^3 binary-star mesh, 4096 subgrids of 8^3 cells
+with 3 ghost layers and 5 passive species (11 fields), all in one fused
+persistent launch replayed from a hipGraph; inputs are resident in HBM
+before the timed region.  A step is one stage over the whole batch.
+
+Also reported: the 64^3 Sod-like mesh (512 subgrids) launched one subgrid at
+a time (unfused three-kernel form and fused form) against one batched
+launch, the step latency percentiles, the roofline of the fused kernel, and
+the CPU oracle's rate on a bounded sample of the same workload.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6     # MI355X vector FP64 (published)
+HBM_PEAK_GBPS = 8000.0      # MI355X HBM3E (published)
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def timed_plan(plan, steps, warmup, torch):
+    for _ in range(warmup):
+        plan.launch()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        plan.launch()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = np.array([a.elapsed_time(b) for a, b in evs])
+    return wall, per
+
+
+def plain_vs_batched(torch, hydro, inputs, reps=3):
+    """Config 2 (64^3, 512 subgrids): one subgrid per launch vs one batched launch."""
+    b = inputs.config2()
+    db = hydro.DeviceBatch.from_inputs(b)
+    prm = hydro.params(dt=b.dt)
+    n = db.n_sub
+    U_out = db.U.clone()
+    amax = torch.zeros(n, dtype=torch.float64, device="cuda")
+    status = torch.zeros(n, dtype=torch.int32, device="cuda")
+    Q = torch.zeros(hydro.q_elems(5), dtype=torch.float64, device="cuda")
+    F = torch.zeros(hydro.f_elems(5), dtype=torch.float64, device="cuda")
+    zero = torch.zeros(1, dtype=torch.int64, device="cuda")
+    views = [db.view(s, 1) for s in range(n)]
+
+    def unfused():
+        for s in range(n):
+            hydro.reconstruct(prm, views[s], db.U, Q, zero)
+            hydro.flux(prm, views[s], Q, zero, F, zero, amax[s:s + 1], status[s:s + 1])
+            hydro.divergence(prm, views[s], F, zero, db.U, U_out)
+
+    def fused_each():
+        for s in range(n):
+            hydro.step(prm, views[s], db.U, U_out, amax[s:s + 1], status[s:s + 1])
+
+    def batched():
+        hydro.step(prm, db.struct, db.U, U_out, amax, status)
+
+    out = {}
+    for name, fn in (("per_subgrid_unfused", unfused), ("per_subgrid_fused", fused_each),
+                     ("batched_fused", batched)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out[name] = {"ms": dt * 1e3, "cell_updates_per_s": b.cell_updates / dt}
+        log(f"config2 {name}: {dt * 1e3:.2f} ms")
+    out["speedup_batched_vs_per_subgrid_unfused"] = (
+        out["per_subgrid_unfused"]["ms"] / out["batched_fused"]["ms"])
+    out["speedup_batched_vs_per_subgrid_fused"] = (
+        out["per_subgrid_fused"]["ms"] / out["batched_fused"]["ms"])
+    return out
+
+
+def cpu_baseline(b, seconds):
+    """The oracle, single-threaded, on evenly spaced subgrids of the workload."""
+    import oracle
+    oracle.build()
+    order = np.random.default_rng(0).permutation(b.n_sub)
+    done = 0
+    t0 = time.perf_counter()
+    elapsed = 0.0
+    while done < b.n_sub and elapsed < seconds:
+        idx = np.sort(order[done:done + 16])
+        sub = b.subset(idx)
+        oracle.step(sub.U, sub.offset, sub.h, sub.n_species, sub.fstride, b.dt)
+        done += len(idx)
+        elapsed = time.perf_counter() - t0
+    return {"value": done * 512 / elapsed, "unit": "cell-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{done} of {b.n_sub} subgrids of the 128^3 binary-star batch "
+                      f"(random subset, seed 0), single thread, {elapsed:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the hydro stage is measured on a single "
+              "MI355X (multi-GPU sharding is a design note, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2210_06439_amd import costmodel, hydro, inputs
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    b = inputs.config3()
+    log(f"config3 generated in {time.perf_counter() - t0:.1f} s ({b.n_sub} subgrids)")
+    db = hydro.DeviceBatch.from_inputs(b)
+    prm = hydro.params(dt=b.dt)
+    U_out = db.U.clone()
+    amax = torch.zeros(db.n_sub, dtype=torch.float64, device="cuda")
+    status = torch.zeros(db.n_sub, dtype=torch.int32, device="cuda")
+    best, times = hydro.autotune(prm, db.struct, db.U, U_out, amax, status, reps=3)
+    log("autotune: " + ", ".join(f"{hydro.variant_name(v)}={t:.3f}ms" for v, t in enumerate(times))
+        + f" -> {hydro.variant_name(best)}")
+    plan = hydro.Plan(prm, db.struct, db.U, U_out, amax, status)
+    wall, per = timed_plan(plan, args.steps, args.warmup, torch)
+    st = status.cpu().numpy()
+    if np.any(st != 0):
+        log(f"WARNING: nonzero status words: {np.unique(st)}")
+    ms_per_step = wall * 1e3 / args.steps
+    value = b.cell_updates / (wall / args.steps)
+    kern_ms = float(np.mean(per))
+    flops, nbytes = costmodel.cost(b.n_species)
+    achieved_tf = flops / (kern_ms * 1e-3) / 1e12
+    achieved_gbps = nbytes / (kern_ms * 1e-3) / 1e9
+    log(f"config3 fused: {ms_per_step:.3f} ms/step wall, kernel {kern_ms:.3f} ms, "
+        f"{value:.3e} cell-updates/s, {achieved_tf:.1f} TFLOP/s, {achieved_gbps:.0f} GB/s")
+    plan.close()
+
+    result = {
+        "metric": "FP64 hydro cell-updates/s, batched vs per-subgrid launch; p50/p99 step latency",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "128^3 binary-star mesh: 4096 subgrids of 8^3 (+3 ghosts), "
+                               "11 fields, one fused persistent launch in a hipGraph",
+                   "subgrids": b.n_sub, "cells_per_step": b.cell_updates,
+                   "variant": hydro.variant_name(best)},
+        "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99))},
+        "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved_tf / FP64_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "k_fused", "flops_per_launch": flops,
+                     "kernel_ms": kern_ms},
+        "hbm": {"achieved": achieved_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": achieved_gbps / HBM_PEAK_GBPS, "bytes_per_launch": nbytes},
+    }
+    del U_out, db
+    torch.cuda.empty_cache()
+    if not args.no_plain:
+        result["plain_vs_batched"] = plain_vs_batched(torch, hydro, inputs)
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(b, args.cpu_seconds)
+        result["cpu_baseline"]["gpu_over_cpu"] = value / result["cpu_baseline"]["value"]
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * hydro.h -- C ABI of the MI355X (gfx950) FP64 hydro-step library.
+ *
+ * The library computes one stage of the finite-volume hydro solver the paper
+ * describes in Sec. II ("Solvers"): the `reconstruct` step (piecewise-parabolic
+ * values of the evolved variables at 26 quadrature points per cell), the
+ * `flux` step (central-upwind Kurganov-Tadmor flux, integrated over each face
+ * with the 9-point Newton-Cotes/Simpson rule) and the finite-volume divergence,
+ * on batches of 8x8x8 subgrids (Sec. II, "Data-Structure") that each carry 3
+ * ghost layers, i.e. 14^3 cells per field.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers named U, Q, F, amax, status and every array inside hydro_batch
+ *    are DEVICE pointers owned by the caller; `params` and `batch` themselves
+ *    are host pointers read during the call.  Nothing is retained after the
+ *    call returns, except by hydro_plan_create (see there).
+ *  - Every call enqueues its kernels on `stream` (a hipStream_t; NULL means
+ *    the default stream) and returns without synchronising.
+ *  - Return value: HYDRO_OK, or a negative HYDRO_E* code; hydro_strerror()
+ *    describes the code and, for HYDRO_ELAUNCH, the HIP error.  No C++
+ *    exception crosses the ABI.
+ *  - Subgrid layout (field-major SoA): field f of subgrid s, cell (i,j,k),
+ *    i = x fastest, each index in [0,14), lives at
+ *        U[offset[s] + f*fstride + (k*14 + j)*14 + i]
+ *    Interior cells have i,j,k in [3,11); the rest are ghosts, filled by the
+ *    caller.  Fields f = 0..nf-1, nf = 6 + n_species[s]:
+ *        rho, sx, sy, sz, egas, tau, spc_1 .. spc_{n_species}.
+ *    fstride >= 2744; 2752 (a multiple of 16 doubles) is recommended.
+ *    offset[s] must be a multiple of 2 (16-byte aligned field starts).
+ *  - Per-subgrid status word (written when `status` is non-NULL): bit 1 =
+ *    rho <= 0 at a quadrature point, bit 2 = p <= 0 there, bit 4 = a
+ *    non-finite output, bit 8 = invalid metadata (n_species outside 0..5 or
+ *    a negative offset; the subgrid is then skipped and its outputs are not
+ *    written).
+ *  - Floating point: IEEE binary64 on the vector ALUs; no reduced precision.
+ */
+#ifndef HYDRO_H
+#define HYDRO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    HYDRO_OK = 0,
+    HYDRO_EINVAL = -1,   /* null pointer, fstride < 2744, n_sub < 0, misalignment */
+    HYDRO_ELAUNCH = -2,  /* a HIP runtime call or kernel launch failed             */
+    HYDRO_ENODEV = -3    /* no gfx950 device is current                            */
+};
+
+enum { HYDRO_STATUS_RHO = 1, HYDRO_STATUS_P = 2, HYDRO_STATUS_NONFINITE = 4,
+       HYDRO_STATUS_BADMETA = 8 };
+
+typedef struct {
+    double gamma;      /* ratio of specific heats (5/3 for the paper's gas)       */
+    double de_switch;  /* dual-energy switch eps: p from tau^gamma where the
+                          internal energy E - |s|^2/(2 rho) is below eps * E      */
+    double dt;         /* step size of the forward-Euler stage; 0 = speeds only   */
+    uint32_t flags;    /* reserved, must be 0                                      */
+} hydro_params;
+
+typedef struct {
+    int32_t n_sub;              /* number of subgrids (0 is a valid no-op)        */
+    int32_t fstride;            /* elements between consecutive fields            */
+    const int64_t *offset;      /* device [n_sub]: element offset of field 0      */
+    const double *h;            /* device [n_sub]: cell size of the subgrid       */
+    const int32_t *n_species;   /* device [n_sub]: passive species, 0..5          */
+} hydro_batch;
+
+/*
+ * hydro_reconstruct -- PPM reconstruction (Sec. II: the `reconstruct` kernel,
+ * piecewise-parabolic values at 26 quadrature points).
+ *
+ * For every cell c in [2,12)^3, every direction d in {-1,0,1}^3 \ {0} and
+ * every field, Q holds the value at the surface point c + d/2, reconstructed
+ * by 1-D Colella-Woodward PPM along the line of cell centres c + m d,
+ * m = -2..2 (monotonised-central slopes, CW84 monotonicity).
+ * Output layout: Q[q_offset[s] + (f*26 + n)*1000 + (k'*10 + j')*10 + i'] with
+ * (i',j',k') = c - 2 and n = 9(dz+1) + 3(dy+1) + (dx+1), minus 1 when > 13.
+ * q_offset: device [n_sub]; each region holds hydro_q_elems(n_species[s]).
+ */
+int hydro_reconstruct(const hydro_params *params, const hydro_batch *batch,
+                      const double *U, double *Q, const int64_t *q_offset,
+                      void *stream);
+
+/*
+ * hydro_flux -- central-upwind face flux with Simpson quadrature (Sec. II:
+ * the `flux` kernel, Newton-Cotes quadrature; the cited Kurganov-Tadmor
+ * finite-volume scheme).
+ *
+ * For each face between cells c_L and c_L + e_a (c_L from 2 to 10 along a,
+ * interior along the other two axes): the 9 surface points of the face carry
+ * left states Q(c_L, e_a + t) and right states Q(c_R, -e_a + t); the one-sided
+ * speeds a+ = max(0, max u_n + c), a- = min(0, min u_n - c) are taken over all
+ * 18 point-sides; the point flux
+ *     H = ((a+ F(V_L) - a- F(V_R)) + a+ a- (V_R - V_L)) / (a+ - a-)
+ * is averaged with the tensor Simpson weights (1,4,1)x(1,4,1)/36.
+ * Output: F[f_offset[s] + (f*3 + a)*576 + idx], idx x-fastest over the face
+ * box (extent 9 along a, 8 along the others); amax[s] = max over the subgrid's
+ * faces of max(a+, -a-); status[s] as above (may be NULL).
+ * q_offset, f_offset: device [n_sub]; F regions hold hydro_f_elems(n_species).
+ */
+int hydro_flux(const hydro_params *params, const hydro_batch *batch,
+               const double *Q, const int64_t *q_offset,
+               double *F, const int64_t *f_offset,
+               double *amax, int32_t *status, void *stream);
+
+/*
+ * hydro_divergence -- finite-volume update (Sec. II: finite volumes):
+ *     U_out = U_in - (dt/h) ((dF_x + dF_y) + dF_z)   on the 8^3 interior,
+ * dF_a the difference of the averaged fluxes on the two faces of the cell
+ * normal to a.  Ghost cells of U_out are not written.  U_out must not alias
+ * U_in; both use batch->offset and batch->fstride.
+ */
+int hydro_divergence(const hydro_params *params, const hydro_batch *batch,
+                     const double *F, const int64_t *f_offset,
+                     const double *U_in, double *U_out, void *stream);
+
+/*
+ * hydro_step -- the fused stage: reconstruct + flux + divergence in one
+ * persistent launch over the whole batch, without writing Q or F to memory.
+ * Same results as the three calls above up to rounding order (the fused
+ * kernel sums the Simpson-weighted terms in a different order).  Writes the
+ * interior of U_out, amax[s] and status[s] (may be NULL).  U_out must not
+ * alias U_in.  Uses the launch shape chosen by hydro_autotune() for this
+ * kind of batch when one was tuned, else the default shape.
+ */
+int hydro_step(const hydro_params *params, const hydro_batch *batch,
+               const double *U_in, double *U_out, double *amax,
+               int32_t *status, void *stream);
+
+/* Element counts of one subgrid's Q and F regions: 26*nf*1000 and 3*nf*576. */
+int64_t hydro_q_elems(int n_species);
+int64_t hydro_f_elems(int n_species);
+
+/* Text for a return code (static storage; HIP detail for HYDRO_ELAUNCH). */
+const char *hydro_strerror(int code);
+
+/* ---------------------------------------------------------------------------
+ * Launch variants and the autotuner.  The fused step has several launch
+ * shapes (workgroups per CU, subgrid scheduling order); all of them compute
+ * bitwise-identical results.
+ */
+
+/* Number of launch variants of the fused step, and a short name for each. */
+int hydro_variant_count(void);
+const char *hydro_variant_name(int variant);
+
+/* hydro_step with an explicit variant (0 .. hydro_variant_count()-1). */
+int hydro_step_variant(const hydro_params *params, const hydro_batch *batch,
+                       const double *U_in, double *U_out, double *amax,
+                       int32_t *status, int variant, void *stream);
+
+/*
+ * hydro_autotune -- times every variant on this batch (`reps` launches each,
+ * after one warm-up, with HIP events on `stream`, synchronising the stream),
+ * records the fastest for batches of this kind (keyed by the power-of-two
+ * bucket of n_sub and the largest species count) and returns its index, or a
+ * negative error code.  times_ms (host, may be NULL) receives
+ * hydro_variant_count() mean times.  U_out, amax and status are overwritten.
+ */
+int hydro_autotune(const hydro_params *params, const hydro_batch *batch,
+                   const double *U_in, double *U_out, double *amax,
+                   int32_t *status, int reps, float *times_ms, void *stream);
+
+/* The variant hydro_step will use for a batch of n_sub subgrids whose largest
+ * species count is max_species (the tuned one, else the default). */
+int hydro_selected_variant(int n_sub, int max_species);
+
+/* ---------------------------------------------------------------------------
+ * Captured plans: a fused step recorded once into a hipGraph and replayed.
+ * The plan keeps the device pointers and the batch metadata pointers given at
+ * creation (not the contents they point to: metadata and field data may be
+ * rewritten between replays).  dt can be changed per replay.
+ */
+typedef struct hydro_plan hydro_plan;
+
+int hydro_plan_create(const hydro_params *params, const hydro_batch *batch,
+                      const double *U_in, double *U_out, double *amax,
+                      int32_t *status, void *stream, hydro_plan **plan_out);
+int hydro_plan_set_dt(hydro_plan *plan, double dt);
+int hydro_plan_launch(hydro_plan *plan, void *stream);
+int hydro_plan_destroy(hydro_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HYDRO_H */

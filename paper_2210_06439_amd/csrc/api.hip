@@ -1,0 +1,300 @@
+// api.hip -- the C ABI of the hydro library: argument checks, launches,
+// the autotuner's cache and captured hipGraph plans.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+
+#include "hydro_internal.hpp"
+
+using namespace hydro;
+
+namespace {
+
+thread_local char g_err[256];
+thread_local hipError_t g_last_hip = hipSuccess;
+
+int fail_hip(hipError_t e) {
+    g_last_hip = e;
+    return HYDRO_ELAUNCH;
+}
+
+// The device must be a gfx950; checked once per device.
+int check_device() {
+    static std::mutex mu;
+    static std::unordered_map<int, int> ok;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = ok.find(dev);
+    if (it != ok.end()) return it->second;
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return fail_hip(e);
+    int r = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? HYDRO_OK : HYDRO_ENODEV;
+    ok[dev] = r;
+    return r;
+}
+
+int check_common(const hydro_params *p, const hydro_batch *b) {
+    if (!p || !b) return HYDRO_EINVAL;
+    if (b->n_sub < 0 || b->fstride < NCELL || (b->fstride & 1)) return HYDRO_EINVAL;
+    if (b->n_sub > 0 && (!b->offset || !b->h || !b->n_species)) return HYDRO_EINVAL;
+    if (p->flags != 0) return HYDRO_EINVAL;
+    return HYDRO_OK;
+}
+
+bool aligned8(const void *ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 7u) == 0; }
+
+// ---- autotuner cache: power-of-two bucket of n_sub -> variant --------------
+
+std::mutex g_tune_mu;
+std::unordered_map<int, int> g_tuned;
+bool g_tune_loaded = false;
+
+int bucket_of(int n_sub) {
+    int b = 0;
+    while ((1 << b) < n_sub && b < 30) b++;
+    return b;
+}
+
+const char *tune_file() { return std::getenv("HYDRO_TUNE_CACHE"); }
+
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *fn = tune_file();
+    if (!fn) return;
+    FILE *f = std::fopen(fn, "r");
+    if (!f) return;
+    char arch[32];
+    int bucket, variant;
+    while (std::fscanf(f, "%31s %d %d", arch, &bucket, &variant) == 3)
+        if (std::strcmp(arch, "gfx950") == 0 && variant >= 0 && variant < fused_variant_count())
+            g_tuned[bucket] = variant;
+    std::fclose(f);
+}
+
+void tune_save_locked() {
+    const char *fn = tune_file();
+    if (!fn) return;
+    std::string tmp = std::string(fn) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    for (auto &kv : g_tuned) std::fprintf(f, "gfx950 %d %d\n", kv.first, kv.second);
+    std::fclose(f);
+    std::rename(tmp.c_str(), fn);
+}
+
+}  // namespace
+
+struct hydro_plan {
+    StepArgs args;
+    const double *U_in;
+    double *U_out;
+    double *amax;
+    int32_t *status;
+    int order;
+    void *kargs[6];
+    hipGraph_t graph;
+    hipGraphNode_t node;
+    hipGraphExec_t exec;
+    hipKernelNodeParams np;
+};
+
+extern "C" {
+
+int64_t hydro_q_elems(int n_species) { return (int64_t)26 * (6 + n_species) * QCELL; }
+int64_t hydro_f_elems(int n_species) { return (int64_t)3 * (6 + n_species) * NFACE; }
+
+const char *hydro_strerror(int code) {
+    switch (code) {
+    case HYDRO_OK: return "ok";
+    case HYDRO_EINVAL: return "invalid argument";
+    case HYDRO_ENODEV: return "the current device is not a gfx950 GPU";
+    case HYDRO_ELAUNCH:
+        std::snprintf(g_err, sizeof g_err, "HIP error: %s", hipGetErrorString(g_last_hip));
+        return g_err;
+    default: return "unknown error code";
+    }
+}
+
+int hydro_reconstruct(const hydro_params *params, const hydro_batch *batch, const double *U,
+                      double *Q, const int64_t *q_offset, void *stream) {
+    int rc = check_common(params, batch);
+    if (rc) return rc;
+    if (batch->n_sub == 0) return HYDRO_OK;
+    if (!U || !Q || !q_offset || !aligned8(U) || !aligned8(Q)) return HYDRO_EINVAL;
+    if ((rc = check_device())) return rc;
+    hipError_t e = launch_plain_reconstruct(make_args(params, batch), U, Q, q_offset,
+                                            static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HYDRO_OK : fail_hip(e);
+}
+
+int hydro_flux(const hydro_params *params, const hydro_batch *batch, const double *Q,
+               const int64_t *q_offset, double *F, const int64_t *f_offset, double *amax,
+               int32_t *status, void *stream) {
+    int rc = check_common(params, batch);
+    if (rc) return rc;
+    if (batch->n_sub == 0) return HYDRO_OK;
+    if (!Q || !q_offset || !F || !f_offset || !amax || !aligned8(Q) || !aligned8(F))
+        return HYDRO_EINVAL;
+    if ((rc = check_device())) return rc;
+    hipError_t e = launch_plain_flux(make_args(params, batch), Q, q_offset, F, f_offset, amax,
+                                     status, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HYDRO_OK : fail_hip(e);
+}
+
+int hydro_divergence(const hydro_params *params, const hydro_batch *batch, const double *F,
+                     const int64_t *f_offset, const double *U_in, double *U_out, void *stream) {
+    int rc = check_common(params, batch);
+    if (rc) return rc;
+    if (batch->n_sub == 0) return HYDRO_OK;
+    if (!F || !f_offset || !U_in || !U_out || U_in == U_out) return HYDRO_EINVAL;
+    if ((rc = check_device())) return rc;
+    hipError_t e = launch_plain_divergence(make_args(params, batch), F, f_offset, U_in, U_out,
+                                           static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HYDRO_OK : fail_hip(e);
+}
+
+int hydro_variant_count(void) { return fused_variant_count(); }
+const char *hydro_variant_name(int variant) { return fused_variant_name(variant); }
+
+int hydro_step_variant(const hydro_params *params, const hydro_batch *batch, const double *U_in,
+                       double *U_out, double *amax, int32_t *status, int variant, void *stream) {
+    int rc = check_common(params, batch);
+    if (rc) return rc;
+    if (variant < 0 || variant >= fused_variant_count()) return HYDRO_EINVAL;
+    if (batch->n_sub == 0) return HYDRO_OK;
+    if (!U_in || !U_out || !amax || U_in == U_out || !aligned8(U_in) || !aligned8(U_out))
+        return HYDRO_EINVAL;
+    if ((rc = check_device())) return rc;
+    hipError_t e = launch_fused_step(make_args(params, batch), U_in, U_out, amax, status, variant,
+                                     static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HYDRO_OK : fail_hip(e);
+}
+
+int hydro_selected_variant(int n_sub, int max_species) {
+    (void)max_species;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tuned.find(bucket_of(n_sub));
+    return it == g_tuned.end() ? 0 : it->second;
+}
+
+int hydro_step(const hydro_params *params, const hydro_batch *batch, const double *U_in,
+               double *U_out, double *amax, int32_t *status, void *stream) {
+    if (!batch) return HYDRO_EINVAL;
+    return hydro_step_variant(params, batch, U_in, U_out, amax, status,
+                              hydro_selected_variant(batch->n_sub, 5), stream);
+}
+
+int hydro_autotune(const hydro_params *params, const hydro_batch *batch, const double *U_in,
+                   double *U_out, double *amax, int32_t *status, int reps, float *times_ms,
+                   void *stream) {
+    int rc = check_common(params, batch);
+    if (rc) return rc;
+    if (batch->n_sub == 0 || reps < 1) return HYDRO_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    hipError_t e;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return fail_hip(e);
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        hipEventDestroy(e0);
+        return fail_hip(e);
+    }
+    int best = -1;
+    float best_t = 0.f;
+    for (int v = 0; v < fused_variant_count() && rc == HYDRO_OK; v++) {
+        rc = hydro_step_variant(params, batch, U_in, U_out, amax, status, v, stream);  // warm-up
+        if (rc) break;
+        hipEventRecord(e0, st);
+        for (int r = 0; r < reps && rc == HYDRO_OK; r++)
+            rc = hydro_step_variant(params, batch, U_in, U_out, amax, status, v, stream);
+        hipEventRecord(e1, st);
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+            rc = fail_hip(e);
+            break;
+        }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        ms /= (float)reps;
+        if (times_ms) times_ms[v] = ms;
+        if (best < 0 || ms < best_t) {
+            best = v;
+            best_t = ms;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    g_tuned[bucket_of(batch->n_sub)] = best;
+    tune_save_locked();
+    return best;
+}
+
+int hydro_plan_create(const hydro_params *params, const hydro_batch *batch, const double *U_in,
+                      double *U_out, double *amax, int32_t *status, void *stream,
+                      hydro_plan **plan_out) {
+    (void)stream;
+    int rc = check_common(params, batch);
+    if (rc) return rc;
+    if (!plan_out || batch->n_sub == 0 || !U_in || !U_out || !amax || U_in == U_out)
+        return HYDRO_EINVAL;
+    if ((rc = check_device())) return rc;
+    hydro_plan *p = new (std::nothrow) hydro_plan();
+    if (!p) return HYDRO_EINVAL;
+    p->args = make_args(params, batch);
+    p->U_in = U_in;
+    p->U_out = U_out;
+    p->amax = amax;
+    p->status = status;
+    int variant = hydro_selected_variant(batch->n_sub, 5);
+    p->order = 0;
+    p->kargs[0] = &p->args;
+    p->kargs[1] = &p->U_in;
+    p->kargs[2] = &p->U_out;
+    p->kargs[3] = &p->amax;
+    p->kargs[4] = &p->status;
+    p->kargs[5] = &p->order;
+    fused_kernel_node_params(p->args, U_in, U_out, amax, status, variant, &p->np, p->kargs);
+    hipError_t e = hipGraphCreate(&p->graph, 0);
+    if (e == hipSuccess) e = hipGraphAddKernelNode(&p->node, p->graph, nullptr, 0, &p->np);
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        delete p;
+        return fail_hip(e);
+    }
+    *plan_out = p;
+    return HYDRO_OK;
+}
+
+int hydro_plan_set_dt(hydro_plan *plan, double dt) {
+    if (!plan) return HYDRO_EINVAL;
+    plan->args.dt = dt;
+    hipError_t e = hipGraphExecKernelNodeSetParams(plan->exec, plan->node, &plan->np);
+    return e == hipSuccess ? HYDRO_OK : fail_hip(e);
+}
+
+int hydro_plan_launch(hydro_plan *plan, void *stream) {
+    if (!plan) return HYDRO_EINVAL;
+    hipError_t e = hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HYDRO_OK : fail_hip(e);
+}
+
+int hydro_plan_destroy(hydro_plan *plan) {
+    if (!plan) return HYDRO_EINVAL;
+    hipGraphExecDestroy(plan->exec);
+    hipGraphDestroy(plan->graph);
+    delete plan;
+    return HYDRO_OK;
+}
+
+}  // extern "C"

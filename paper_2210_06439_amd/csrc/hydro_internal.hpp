@@ -1,0 +1,66 @@
+// hydro_internal.hpp -- internal declarations of the gfx950 hydro library.
+//
+// Geometry of one subgrid (Sec. II, "Data-Structure": 8^3 cells per leaf,
+// plus 3 ghost layers per side here): 14^3 cells per field, x fastest.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hydro.h"
+
+namespace hydro {
+
+constexpr int NB = 14;          // cells per dimension incl. ghosts
+constexpr int NPLANE = NB * NB; // 196 cells per z-plane
+constexpr int NCELL = NB * NB * NB;
+constexpr int QN = 10;          // reconstructed cells per dimension: [2,12)
+constexpr int QCELL = QN * QN * QN;
+constexpr int NFACE = 576;      // faces per axis: 9 x 8 x 8
+constexpr int NF_MAX = 11;
+
+// Kernel-side copy of the call's scalar parameters (passed by value).
+struct StepArgs {
+    double gamma;
+    double de_switch;
+    double dt;
+    int32_t n_sub;
+    int32_t fstride;
+    const int64_t *offset;
+    const double *h;
+    const int32_t *n_species;
+};
+
+inline StepArgs make_args(const hydro_params *p, const hydro_batch *b) {
+    StepArgs a;
+    a.gamma = p->gamma;
+    a.de_switch = p->de_switch;
+    a.dt = p->dt;
+    a.n_sub = b->n_sub;
+    a.fstride = b->fstride;
+    a.offset = b->offset;
+    a.h = b->h;
+    a.n_species = b->n_species;
+    return a;
+}
+
+// Launch wrappers (each returns hipSuccess or the launch error).
+hipError_t launch_plain_reconstruct(const StepArgs &a, const double *U, double *Q,
+                                    const int64_t *q_offset, hipStream_t st);
+hipError_t launch_plain_flux(const StepArgs &a, const double *Q, const int64_t *q_offset,
+                             double *F, const int64_t *f_offset, double *amax,
+                             int32_t *status, hipStream_t st);
+hipError_t launch_plain_divergence(const StepArgs &a, const double *F, const int64_t *f_offset,
+                                   const double *U_in, double *U_out, hipStream_t st);
+
+// Fused step: variant index selects the launch shape.
+int fused_variant_count();
+const char *fused_variant_name(int v);
+hipError_t launch_fused_step(const StepArgs &a, const double *U_in, double *U_out,
+                             double *amax, int32_t *status, int variant, hipStream_t st);
+// The kernel node's argument block, for in-place dt updates of a captured graph.
+hipError_t fused_kernel_node_params(const StepArgs &a, const double *U_in, double *U_out,
+                                    double *amax, int32_t *status, int variant,
+                                    hipKernelNodeParams *out, void **arg_storage);
+
+}  // namespace hydro

@@ -1,0 +1,341 @@
+// plain.hip -- the unfused stages: reconstruct, flux, divergence.
+//
+// These kernels write the full intermediate arrays Q (26 quadrature values
+// per cell and field) and F (averaged face fluxes) to memory, one stage per
+// launch, the way the paper's `reconstruct` and `flux` kernels each run per
+// subgrid (Sec. III-D).  Every floating-point expression is evaluated in the
+// order the method's definition states (contraction off), so the results are
+// reproducible bit for bit across launch shapes.
+#include "hydro_internal.hpp"
+
+#pragma clang fp contract(off)
+
+namespace hydro {
+namespace {
+
+// ---- geometry --------------------------------------------------------------
+
+// The 13 lines are the directions n = 9(dz+1) + 3(dy+1) + (dx+1) in 14..26;
+// their storage slot is n-1, the opposite direction's slot is 26-n.
+__device__ inline void line_dir(int line, int &dx, int &dy, int &dz) {
+    int n = 14 + line;
+    dz = n / 9 - 1;
+    dy = (n / 3) % 3 - 1;
+    dx = n % 3 - 1;
+}
+
+__device__ inline int dir_slot(int dx, int dy, int dz) {
+    int n = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1);
+    return n < 13 ? n : n - 1;
+}
+
+__device__ inline int qcell(int i, int j, int k) {   // cell in [2,12)^3 -> 0..999
+    return ((k - 2) * QN + (j - 2)) * QN + (i - 2);
+}
+
+// Face index of the face whose left cell is (i,j,k) on `axis`.
+__device__ inline int face_idx(int axis, int i, int j, int k) {
+    if (axis == 0) return ((k - 3) * 8 + (j - 3)) * 9 + (i - 2);
+    if (axis == 1) return ((k - 3) * 9 + (j - 2)) * 8 + (i - 3);
+    return ((k - 2) * 8 + (j - 3)) * 8 + (i - 3);
+}
+
+__device__ inline bool meta_ok(const StepArgs &a, int s, int &nf, int64_t &off) {
+    int ns = a.n_species[s];
+    off = a.offset[s];
+    nf = 6 + ns;
+    return ns >= 0 && ns <= 5 && off >= 0;
+}
+
+// ---- PPM (Colella-Woodward 1984, MC slopes) ----------------------------------
+
+__device__ inline double mc_slope(double ul, double uc, double ur) {
+    double dm = uc - ul;
+    double dp = ur - uc;
+    double d = 0.5 * (dp + dm);
+    if (dp * dm > 0.0) {
+        double lim = fmin(2.0 * fabs(dm), 2.0 * fabs(dp));
+        return copysign(fmin(fabs(d), lim), d);
+    }
+    return 0.0;
+}
+
+__device__ inline void ppm(double um2, double um1, double u0, double up1, double up2,
+                           double &qp, double &qm) {
+    const double sixth = 1.0 / 6.0;
+    double s_m = mc_slope(um2, um1, u0);
+    double s_0 = mc_slope(um1, u0, up1);
+    double s_p = mc_slope(u0, up1, up2);
+    qp = 0.5 * (u0 + up1) - (s_p - s_0) * sixth;
+    qm = 0.5 * (um1 + u0) - (s_0 - s_m) * sixth;
+    if ((qp - u0) * (u0 - qm) <= 0.0) {
+        qp = u0;
+        qm = u0;
+    } else {
+        double dq = qp - qm;
+        double m6 = 6.0 * (u0 - 0.5 * (qm + qp));
+        if (dq * m6 > dq * dq) {
+            qm = 3.0 * u0 - 2.0 * qp;
+        } else if (-(dq * dq) > dq * m6) {
+            qp = 3.0 * u0 - 2.0 * qm;
+        }
+    }
+}
+
+// One block per (subgrid, field, line); threads stride over the 1000 cells.
+__global__ __launch_bounds__(256) void k_reconstruct(StepArgs a, const double *__restrict__ U,
+                                                     double *__restrict__ Q,
+                                                     const int64_t *__restrict__ q_offset) {
+    const int per = NF_MAX * 13;
+    const int s = blockIdx.x / per;
+    const int r = blockIdx.x - s * per;
+    const int f = r / 13;
+    const int line = r - f * 13;
+    if (s >= a.n_sub) return;
+    int nf;
+    int64_t off;
+    if (!meta_ok(a, s, nf, off) || f >= nf) return;
+    int dx, dy, dz;
+    line_dir(line, dx, dy, dz);
+    const int sp = 13 + line;          // slot of +d
+    const int sm = 12 - line;          // slot of -d
+    const int step = (dz * NB + dy) * NB + dx;
+    const double *Uf = U + off + (int64_t)f * a.fstride;
+    double *Qf = Q + q_offset[s] + (int64_t)f * 26 * QCELL;
+    for (int c = threadIdx.x; c < QCELL; c += blockDim.x) {
+        int i = c % QN + 2, j = (c / QN) % QN + 2, k = c / (QN * QN) + 2;
+        int ci = (k * NB + j) * NB + i;
+        double qp, qm;
+        ppm(Uf[ci - 2 * step], Uf[ci - step], Uf[ci], Uf[ci + step], Uf[ci + 2 * step], qp, qm);
+        Qf[sp * QCELL + c] = qp;
+        Qf[sm * QCELL + c] = qm;
+    }
+}
+
+// ---- point state -------------------------------------------------------------
+
+struct PointState {
+    double un, p, cs;
+    int bits;
+};
+
+__device__ inline PointState point_state(const StepArgs &a, double rho, double sx, double sy,
+                                         double sz, double E, double tau, int axis) {
+    PointState st;
+    double r = 1.0 / rho;
+    double vx = sx * r, vy = sy * r, vz = sz * r;
+    double ek = 0.5 * ((sx * vx + sy * vy) + sz * vz);
+    double ei = E - ek;
+    if (ei < a.de_switch * E) ei = pow(tau, a.gamma);
+    double p = (a.gamma - 1.0) * ei;
+    st.cs = sqrt((a.gamma * p) * r);
+    st.un = axis == 0 ? vx : (axis == 1 ? vy : vz);
+    st.p = p;
+    st.bits = (rho <= 0.0 ? 1 : 0) | (p <= 0.0 ? 2 : 0);
+    return st;
+}
+
+// Physical flux of field f along axis at a point with state (un, p); V_f is the
+// field's own value, s_axis the normal momentum (used by the density flux).
+__device__ inline double phys_flux(int f, int axis, double vf, double s_axis, double un,
+                                   double p) {
+    if (f == 0) return s_axis;
+    if (f <= 3) {
+        double v = vf * un;
+        if (f - 1 == axis) v = v + p;
+        return v;
+    }
+    if (f == 4) return (vf + p) * un;
+    return vf * un;
+}
+
+__device__ inline void block_reduce_max_or(double &m, int &bits) {
+    __shared__ double sm[16];
+    __shared__ int sb[16];
+    for (int o = 32; o > 0; o >>= 1) {
+        m = fmax(m, __shfl_xor(m, o));
+        bits |= __shfl_xor(bits, o);
+    }
+    int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sm[w] = m;
+        sb[w] = bits;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < (int)(blockDim.x >> 6); q++) {
+            m = fmax(m, sm[q]);
+            bits |= sb[q];
+        }
+    }
+}
+
+__global__ void k_init_outputs(int n, double *amax, int32_t *status) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) {
+        amax[s] = 0.0;
+        if (status) status[s] = 0;
+    }
+}
+
+// One block per (subgrid, 256-face chunk); 7 chunks cover 3 x 576 faces.
+__global__ __launch_bounds__(256) void k_flux(StepArgs a, const double *__restrict__ Q,
+                                              const int64_t *__restrict__ q_offset,
+                                              double *__restrict__ F,
+                                              const int64_t *__restrict__ f_offset,
+                                              double *amax, int32_t *status) {
+    const int s = blockIdx.x / 7;
+    const int chunk = blockIdx.x - s * 7;
+    if (s >= a.n_sub) return;
+    int nf;
+    int64_t off;
+    if (!meta_ok(a, s, nf, off)) {
+        if (chunk == 0 && threadIdx.x == 0 && status) atomicOr(&status[s], (int)HYDRO_STATUS_BADMETA);
+        return;
+    }
+    const double *Qs = Q + q_offset[s];
+    double *Fs = F + f_offset[s];
+    const int face = chunk * 256 + threadIdx.x;
+    double af = 0.0;
+    int bits = 0;
+    if (face < 3 * NFACE) {
+        const int axis = face / NFACE;
+        const int idx = face - axis * NFACE;
+        int cl[3];
+        if (axis == 0) {
+            cl[0] = 2 + idx % 9; cl[1] = 3 + (idx / 9) % 8; cl[2] = 3 + idx / 72;
+        } else if (axis == 1) {
+            cl[0] = 3 + idx % 8; cl[1] = 2 + (idx / 8) % 9; cl[2] = 3 + idx / 72;
+        } else {
+            cl[0] = 3 + idx % 8; cl[1] = 3 + (idx / 8) % 8; cl[2] = 2 + idx / 64;
+        }
+        int cr[3] = {cl[0], cl[1], cl[2]};
+        cr[axis] += 1;
+        const int b = axis == 0 ? 1 : 0;
+        const int b2 = axis == 2 ? 1 : 2;
+        const int qcl = qcell(cl[0], cl[1], cl[2]);
+        const int qcr = qcell(cr[0], cr[1], cr[2]);
+        int sl[9], sr[9];
+        for (int t = 0; t < 9; t++) {
+            int d[3] = {0, 0, 0};
+            d[b] = t % 3 - 1;
+            d[b2] = t / 3 - 1;
+            d[axis] = 1;
+            sl[t] = dir_slot(d[0], d[1], d[2]);
+            d[axis] = -1;
+            sr[t] = dir_slot(d[0], d[1], d[2]);
+        }
+        // pass 1: point states on both sides and the face's one-sided speeds
+        double unL[9], pL[9], unR[9], pR[9];
+        double lam_p = -INFINITY, lam_m = INFINITY;
+        for (int t = 0; t < 9; t++) {
+            const double *qL = Qs + (int64_t)sl[t] * QCELL + qcl;
+            const double *qR = Qs + (int64_t)sr[t] * QCELL + qcr;
+            const int64_t fs = 26 * QCELL;
+            PointState L = point_state(a, qL[0], qL[fs], qL[2 * fs], qL[3 * fs], qL[4 * fs],
+                                       qL[5 * fs], axis);
+            PointState R = point_state(a, qR[0], qR[fs], qR[2 * fs], qR[3 * fs], qR[4 * fs],
+                                       qR[5 * fs], axis);
+            bits |= L.bits | R.bits;
+            unL[t] = L.un; pL[t] = L.p;
+            unR[t] = R.un; pR[t] = R.p;
+            lam_p = fmax(lam_p, fmax(L.un + L.cs, R.un + R.cs));
+            lam_m = fmin(lam_m, fmin(L.un - L.cs, R.un - R.cs));
+        }
+        const double ap = fmax(0.0, lam_p);
+        const double am = fmin(0.0, lam_m);
+        const double inv = 1.0 / (ap - am);
+        const double apam = ap * am;
+        const double sixth = 1.0 / 6.0;
+        const double two_thirds = 4.0 / 6.0;
+        // pass 2: per field, point fluxes and the nested Simpson average
+        for (int f = 0; f < nf; f++) {
+            double H[9];
+            for (int t = 0; t < 9; t++) {
+                const double *qL = Qs + ((int64_t)f * 26 + sl[t]) * QCELL + qcl;
+                const double *qR = Qs + ((int64_t)f * 26 + sr[t]) * QCELL + qcr;
+                double vl = qL[0], vr = qR[0];
+                double saL = 0.0, saR = 0.0;
+                if (f == 0) {
+                    saL = Qs[((int64_t)(1 + axis) * 26 + sl[t]) * QCELL + qcl];
+                    saR = Qs[((int64_t)(1 + axis) * 26 + sr[t]) * QCELL + qcr];
+                }
+                double FL = phys_flux(f, axis, vl, saL, unL[t], pL[t]);
+                double FR = phys_flux(f, axis, vr, saR, unR[t], pR[t]);
+                H[t] = (((ap * FL) - (am * FR)) + (apam * (vr - vl))) * inv;
+            }
+            double r0 = sixth * (H[0] + H[2]) + two_thirds * H[1];
+            double r1 = sixth * (H[3] + H[5]) + two_thirds * H[4];
+            double r2 = sixth * (H[6] + H[8]) + two_thirds * H[7];
+            double fb = sixth * (r0 + r2) + two_thirds * r1;
+            Fs[((int64_t)f * 3 + axis) * NFACE + idx] = fb;
+            if (!isfinite(fb)) bits |= HYDRO_STATUS_NONFINITE;
+        }
+        af = fmax(ap, -am);
+        if (!isfinite(af)) bits |= HYDRO_STATUS_NONFINITE;
+        af = af + 0.0;      // -0 -> +0 so the bit pattern orders like the value
+    }
+    block_reduce_max_or(af, bits);
+    if (threadIdx.x == 0) {
+        // non-negative doubles order like their bit patterns (NaN above +inf)
+        atomicMax(reinterpret_cast<unsigned long long *>(&amax[s]),
+                  (unsigned long long)__double_as_longlong(af));
+        if (status && bits) atomicOr(&status[s], bits);
+    }
+}
+
+// One block per (subgrid, field, half of the 512 interior cells).
+__global__ __launch_bounds__(256) void k_divergence(StepArgs a, const double *__restrict__ F,
+                                                    const int64_t *__restrict__ f_offset,
+                                                    const double *__restrict__ U_in,
+                                                    double *__restrict__ U_out) {
+    const int per = NF_MAX * 2;
+    const int s = blockIdx.x / per;
+    const int r = blockIdx.x - s * per;
+    const int f = r >> 1;
+    if (s >= a.n_sub) return;
+    int nf;
+    int64_t off;
+    if (!meta_ok(a, s, nf, off) || f >= nf) return;
+    const int c = (r & 1) * 256 + threadIdx.x;
+    const int i = 3 + c % 8, j = 3 + (c / 8) % 8, k = 3 + c / 64;
+    const double lam = a.dt / a.h[s];
+    const double *Fs = F + f_offset[s] + (int64_t)f * 3 * NFACE;
+    const double *Fx = Fs, *Fy = Fs + NFACE, *Fz = Fs + 2 * NFACE;
+    double dfx = Fx[face_idx(0, i, j, k)] - Fx[face_idx(0, i - 1, j, k)];
+    double dfy = Fy[face_idx(1, i, j, k)] - Fy[face_idx(1, i, j - 1, k)];
+    double dfz = Fz[face_idx(2, i, j, k)] - Fz[face_idx(2, i, j, k - 1)];
+    const int64_t ci = off + (int64_t)f * a.fstride + (k * NB + j) * NB + i;
+    U_out[ci] = U_in[ci] - lam * ((dfx + dfy) + dfz);
+}
+
+}  // namespace
+
+hipError_t launch_plain_reconstruct(const StepArgs &a, const double *U, double *Q,
+                                    const int64_t *q_offset, hipStream_t st) {
+    if (a.n_sub == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reconstruct, dim3(a.n_sub * NF_MAX * 13), dim3(256), 0, st, a, U, Q,
+                       q_offset);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain_flux(const StepArgs &a, const double *Q, const int64_t *q_offset,
+                             double *F, const int64_t *f_offset, double *amax,
+                             int32_t *status, hipStream_t st) {
+    if (a.n_sub == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_init_outputs, dim3((a.n_sub + 255) / 256), dim3(256), 0, st, a.n_sub,
+                       amax, status);
+    hipLaunchKernelGGL(k_flux, dim3(a.n_sub * 7), dim3(256), 0, st, a, Q, q_offset, F, f_offset,
+                       amax, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain_divergence(const StepArgs &a, const double *F, const int64_t *f_offset,
+                                   const double *U_in, double *U_out, hipStream_t st) {
+    if (a.n_sub == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_divergence, dim3(a.n_sub * NF_MAX * 2), dim3(256), 0, st, a, F,
+                       f_offset, U_in, U_out);
+    return hipGetLastError();
+}
+
+}  // namespace hydro

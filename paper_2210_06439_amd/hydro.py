@@ -1,0 +1,224 @@
+"""Python binding of the gfx950 hydro library (ctypes over include/hydro.h).
+
+Argument marshalling only: every stage of the hydro step runs in the HIP
+kernels of ``libhydro.so``.  PyTorch provides device memory and streams.
+If the library has not been built the calls raise; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhydro.so")
+
+EXPORTS = [
+    "hydro_reconstruct", "hydro_flux", "hydro_divergence", "hydro_step",
+    "hydro_q_elems", "hydro_f_elems", "hydro_strerror",
+    "hydro_variant_count", "hydro_variant_name", "hydro_step_variant",
+    "hydro_autotune", "hydro_selected_variant",
+    "hydro_plan_create", "hydro_plan_set_dt", "hydro_plan_launch", "hydro_plan_destroy",
+]
+
+STATUS_RHO, STATUS_P, STATUS_NONFINITE, STATUS_BADMETA = 1, 2, 4, 8
+
+
+class HydroError(RuntimeError):
+    pass
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("de_switch", ctypes.c_double),
+                ("dt", ctypes.c_double), ("flags", ctypes.c_uint32)]
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [("n_sub", ctypes.c_int32), ("fstride", ctypes.c_int32),
+                ("offset", ctypes.c_void_p), ("h", ctypes.c_void_p),
+                ("n_species", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhydro.so (raises if it is missing: the product has no CPU path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise HydroError(f"{LIB_PATH} is not built; run python -m paper_2210_06439_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        P, B = ctypes.POINTER(Params), ctypes.POINTER(Batch)
+        L.hydro_reconstruct.argtypes = [P, B, vp, vp, vp, vp]
+        L.hydro_flux.argtypes = [P, B, vp, vp, vp, vp, vp, vp, vp]
+        L.hydro_divergence.argtypes = [P, B, vp, vp, vp, vp, vp]
+        L.hydro_step.argtypes = [P, B, vp, vp, vp, vp, vp]
+        L.hydro_step_variant.argtypes = [P, B, vp, vp, vp, vp, ctypes.c_int, vp]
+        L.hydro_autotune.argtypes = [P, B, vp, vp, vp, vp, ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_float), vp]
+        L.hydro_selected_variant.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.hydro_q_elems.argtypes = [ctypes.c_int]
+        L.hydro_q_elems.restype = i64
+        L.hydro_f_elems.argtypes = [ctypes.c_int]
+        L.hydro_f_elems.restype = i64
+        L.hydro_strerror.argtypes = [ctypes.c_int]
+        L.hydro_strerror.restype = ctypes.c_char_p
+        L.hydro_variant_name.argtypes = [ctypes.c_int]
+        L.hydro_variant_name.restype = ctypes.c_char_p
+        L.hydro_plan_create.argtypes = [P, B, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
+        L.hydro_plan_set_dt.argtypes = [vp, ctypes.c_double]
+        L.hydro_plan_launch.argtypes = [vp, vp]
+        L.hydro_plan_destroy.argtypes = [vp]
+        _lib = L
+        del i32
+    return _lib
+
+
+def check(rc: int) -> int:
+    if rc < 0:
+        raise HydroError(f"hydro call failed ({rc}): {lib().hydro_strerror(rc).decode()}")
+    return rc
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def params(gamma=5.0 / 3.0, de_switch=1e-3, dt=0.0) -> Params:
+    return Params(float(gamma), float(de_switch), float(dt), 0)
+
+
+def q_elems(n_species: int) -> int:
+    return int(lib().hydro_q_elems(int(n_species)))
+
+
+def f_elems(n_species: int) -> int:
+    return int(lib().hydro_f_elems(int(n_species)))
+
+
+def variant_count() -> int:
+    return int(lib().hydro_variant_count())
+
+
+def variant_name(v: int) -> str:
+    return lib().hydro_variant_name(int(v)).decode()
+
+
+class DeviceBatch:
+    """A batch of subgrids resident on the GPU: field buffer + metadata."""
+
+    def __init__(self, U, offset, h, n_species, fstride):
+        import torch
+        dev = torch.device("cuda")
+        self.U = torch.as_tensor(U, dtype=torch.float64).to(dev)
+        self.offset = torch.as_tensor(np.asarray(offset, dtype=np.int64)).to(dev)
+        self.h = torch.as_tensor(np.asarray(h, dtype=np.float64)).to(dev)
+        self.n_species = torch.as_tensor(np.asarray(n_species, dtype=np.int32)).to(dev)
+        self.n_species_host = np.asarray(n_species, dtype=np.int32).copy()
+        self.fstride = int(fstride)
+        self.n_sub = int(len(self.n_species_host))
+        self.struct = Batch(self.n_sub, self.fstride, self.offset.data_ptr(),
+                            self.h.data_ptr(), self.n_species.data_ptr())
+
+    @classmethod
+    def from_inputs(cls, b):
+        return cls(b.U, b.offset, b.h, b.n_species, b.fstride)
+
+    def view(self, start: int, count: int) -> Batch:
+        """Metadata of subgrids [start, start+count) (device pointer arithmetic)."""
+        return Batch(int(count), self.fstride,
+                     self.offset.data_ptr() + 8 * start, self.h.data_ptr() + 8 * start,
+                     self.n_species.data_ptr() + 4 * start)
+
+    def q_layout(self):
+        sizes = [q_elems(ns) for ns in self.n_species_host]
+        return _packed(sizes)
+
+    def f_layout(self):
+        sizes = [f_elems(ns) for ns in self.n_species_host]
+        return _packed(sizes)
+
+
+def _packed(sizes):
+    import torch
+    off = np.zeros(len(sizes), dtype=np.int64)
+    if len(sizes) > 1:
+        off[1:] = np.cumsum(np.asarray(sizes[:-1], dtype=np.int64))
+    total = int(off[-1] + sizes[-1]) if len(sizes) else 0
+    return torch.as_tensor(off).cuda(), total
+
+
+def reconstruct(prm: Params, batch: Batch, U, Q, q_offset, stream=None):
+    check(lib().hydro_reconstruct(ctypes.byref(prm), ctypes.byref(batch), _ptr(U), _ptr(Q),
+                                  _ptr(q_offset), _stream(stream)))
+
+
+def flux(prm: Params, batch: Batch, Q, q_offset, F, f_offset, amax, status=None, stream=None):
+    check(lib().hydro_flux(ctypes.byref(prm), ctypes.byref(batch), _ptr(Q), _ptr(q_offset),
+                           _ptr(F), _ptr(f_offset), _ptr(amax), _ptr(status), _stream(stream)))
+
+
+def divergence(prm: Params, batch: Batch, F, f_offset, U_in, U_out, stream=None):
+    check(lib().hydro_divergence(ctypes.byref(prm), ctypes.byref(batch), _ptr(F),
+                                 _ptr(f_offset), _ptr(U_in), _ptr(U_out), _stream(stream)))
+
+
+def step(prm: Params, batch: Batch, U_in, U_out, amax, status=None, variant=None, stream=None):
+    if variant is None:
+        check(lib().hydro_step(ctypes.byref(prm), ctypes.byref(batch), _ptr(U_in), _ptr(U_out),
+                               _ptr(amax), _ptr(status), _stream(stream)))
+    else:
+        check(lib().hydro_step_variant(ctypes.byref(prm), ctypes.byref(batch), _ptr(U_in),
+                                       _ptr(U_out), _ptr(amax), _ptr(status), int(variant),
+                                       _stream(stream)))
+
+
+def autotune(prm: Params, batch: Batch, U_in, U_out, amax, status=None, reps=3, stream=None):
+    """Time every launch variant on this batch; returns (best, times_ms)."""
+    n = variant_count()
+    times = (ctypes.c_float * n)()
+    best = check(lib().hydro_autotune(ctypes.byref(prm), ctypes.byref(batch), _ptr(U_in),
+                                      _ptr(U_out), _ptr(amax), _ptr(status), int(reps), times,
+                                      _stream(stream)))
+    return best, [float(t) for t in times]
+
+
+def selected_variant(n_sub: int) -> int:
+    return int(lib().hydro_selected_variant(int(n_sub), 5))
+
+
+class Plan:
+    """A fused step recorded into a hipGraph; replay with launch()."""
+
+    def __init__(self, prm: Params, batch: Batch, U_in, U_out, amax, status=None, stream=None):
+        self._h = ctypes.c_void_p()
+        check(lib().hydro_plan_create(ctypes.byref(prm), ctypes.byref(batch), _ptr(U_in),
+                                      _ptr(U_out), _ptr(amax), _ptr(status), _stream(stream),
+                                      ctypes.byref(self._h)))
+
+    def set_dt(self, dt: float):
+        check(lib().hydro_plan_set_dt(self._h, float(dt)))
+
+    def launch(self, stream=None):
+        check(lib().hydro_plan_launch(self._h, _stream(stream)))
+
+    def close(self):
+        if self._h:
+            lib().hydro_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
