@@ -2,18 +2,20 @@
 // flux with Simpson quadrature and the finite-volume update in one persistent
 // launch, with no intermediate array in HBM.
 //
-// Mapping (one workgroup of 4 waves per subgrid, looping over subgrids):
+// Mapping (one workgroup of 8 waves per subgrid, looping over subgrids):
 //   * The subgrid is swept plane by plane along z.  LDS holds a rolling
 //     window of 5 z-planes of every field (planes k-2..k+2 around the current
 //     plane k); the next plane is prefetched into registers one step ahead.
-//   * Waves 0, 1, 2 own the x-, y- and z-faces of the 8x8 interior cells of
-//     plane k (lane = cell).  The 13 PPM lines of a cell are split between
-//     the three waves (4, 4 and 5 lines; every line is computed once); each
-//     line yields the reconstructed state at two opposite surface points,
-//     which go through LDS to every wave whose faces contain them.
-//   * Wave 3 handles the 32 "ring" cells just outside the interior in x and
-//     y (2 lanes each); they need only the 9 points of the one face they
-//     share with the interior.
+//   * Four roles, each split over two waves by field group: the "hydro" wave
+//     (density, momenta, energy, tau and the point states) and the "species"
+//     wave (the passive scalars).  Roles 0, 1, 2 own the x-, y- and z-faces
+//     of the 8x8 interior cells of plane k (lane = cell); the 13 PPM lines of
+//     a cell are split between them (4, 4 and 5 lines, each computed once),
+//     and every line's two surface points go through LDS to each role whose
+//     faces contain them.  Role 3 handles the 32 "ring" cells just outside
+//     the interior in x and y (2 lanes each), which only need the 9 points of
+//     the face they share with the interior.  The hydro and species waves of
+//     a role sit on the same SIMD, which keeps two waves per SIMD.
 //   * The flux of a face is linear in the Simpson-weighted point terms once
 //     its speeds a+, a- are known, so each side accumulates
 //         S_V = sum w V,  S_F = sum w F(V),  lambda+- = max/min u_n +- c
@@ -27,45 +29,34 @@
 namespace hydro {
 namespace {
 
-constexpr int NT = 256;
-constexpr int SLOTS = 5;               // window planes
-constexpr int PT = 16;                 // doubles per exchanged point
-constexpr int PV = 11;                 // point slots: V[0..10], then
-constexpr int P_VX = 11, P_P = 14, P_CS = 15;   // vx vy vz, p, cs
-constexpr int NACC = 24;               // doubles per face-side partial
+constexpr int NT = 512;                 // 8 waves
+constexpr int SLOTS = 5;                // window planes
+constexpr int PT = 16;                  // doubles per exchanged point
+constexpr int P_VX = 11, P_P = 14, P_CS = 15;   // point slots after V[0..10]
+constexpr int NH = 14;                  // hydro partial: sv[0..5] sf[1..5] sp lp lm
+constexpr int NACC = NH + 10;           // one face side in LDS (+ species sv, sf)
+constexpr int H_SP = 11, H_LP = 12, H_LM = 13;
 
 // LDS layout, in doubles
-constexpr int WIN_D = SLOTS * NF_MAX * NPLANE;       // 10780
+constexpr int SLOT_D = NF_MAX * NPLANE + 2;          // one window plane, + a dummy word
+constexpr int WIN_D = SLOTS * SLOT_D;                // 10790
 constexpr int XCH_D = 3 * 2 * PT * 64;               // 6144
 constexpr int ZL_D = NACC * 64;                      // 1536
 constexpr int KEEP_D = 2 * NF_MAX * 64;              // 1408
-constexpr int LDS_D = WIN_D + XCH_D + ZL_D + KEEP_D + 8;
-static_assert(LDS_D * 8 + 32 <= 163840, "LDS budget");
+constexpr int RUN_D = 6 * 64;                        // ring lanes: u_n and 5 species
+constexpr int LDS_D = WIN_D + XCH_D + ZL_D + KEEP_D + RUN_D + 16;
+static_assert(LDS_D * 8 <= 163840, "LDS budget");
 
 // combine-phase sub-regions of XCH
-constexpr int XR_OFF = 0;                            // [24][2][8][9]
-constexpr int XF_OFF = NACC * 2 * 8 * 9;             // [11][2][8][9]
+constexpr int RST = 2 * 8 * 9;                       // stride of one component
+constexpr int XR_OFF = 0;                            // [24][2][8][9] right partials
+constexpr int XF_OFF = NACC * RST;                   // [11][2][8][9] face fluxes
+constexpr int LL_OFF = XF_OFF + NF_MAX * RST;        // [2][2][8][9] left speeds
+constexpr int ZB_OFF = LL_OFF + 2 * RST;             // [4][64] z-face speeds
 constexpr int DX_OFF = 0;                            // [2][11][64] (aliases XR)
-static_assert(XF_OFF + NF_MAX * 2 * 8 * 9 <= XCH_D, "combine layout");
-
-// Accumulator layout inside NACC: sv[0..10], sf[1..10] at 11..20, sp, lp, lm.
-struct Acc {
-    double sv[NF_MAX];
-    double sf[NF_MAX];   // sf[0] unused: the density flux is S_V of the normal momentum
-    double sp;           // sum w p (added to the normal momentum's flux)
-    double lp, lm;       // max(u_n + c), min(u_n - c)
-};
-
-__device__ __forceinline__ void acc_zero(Acc &a) {
-#pragma unroll
-    for (int f = 0; f < NF_MAX; f++) {
-        a.sv[f] = 0.0;
-        a.sf[f] = 0.0;
-    }
-    a.sp = 0.0;
-    a.lp = -INFINITY;
-    a.lm = INFINITY;
-}
+constexpr int LAYER_D = 4 * PT * 64;                 // layer-step points
+static_assert(ZB_OFF + 4 * 64 <= XCH_D, "combine layout");
+static_assert(LAYER_D <= ZB_OFF, "layer points must not overlap the z speeds");
 
 // ---- the 13 lines: n = 14 + L, (dx,dy,dz) from the base-3 digits of n -------
 
@@ -73,7 +64,7 @@ __device__ __host__ constexpr int ldx(int L) { return (14 + L) % 3 - 1; }
 __device__ __host__ constexpr int ldy(int L) { return ((14 + L) / 3) % 3 - 1; }
 __device__ __host__ constexpr int ldz(int L) { return (14 + L) / 9 - 1; }
 
-// Lines produced by wave w in round r (-1: idle).  Every line's support
+// Lines produced by role w in round r (-1: idle).  Every line's support
 // contains its producer's axis; x: X, (1,1,0), (1,0,1), (1,1,1);
 // y: Y, (-1,1,0), (0,1,1), (-1,1,1); z: Z, (-1,0,1), (0,-1,1), (1,-1,1), (-1,-1,1).
 __device__ __host__ constexpr int line_of(int w, int r) {
@@ -95,88 +86,81 @@ __device__ __forceinline__ double simpson_w(int t1, int t2) {
 
 // ---- PPM in branch-free form ---------------------------------------------
 
-// x with its sign bit flipped where s (a high-word mask) has it set.
-__device__ __forceinline__ double flip(double x, int s) {
-    return __hiloint2double(__double2hiint(x) ^ s, __double2loint(x));
-}
-
-// Monotonised-central slope from the two one-sided differences.
+// Monotonised-central slope from the two one-sided differences.  The sign of
+// the centred difference d is applied by multiplication (the values stay
+// ordinary floats, so min/max need no NaN canonicalisation).
 __device__ __forceinline__ double mc_slope(double dm, double dp) {
     double d = 0.5 * (dm + dp);
-    int s = __double2hiint(d) & (int)0x80000000;
-    double t = fmin(flip(dm, s), flip(dp, s));       // both > 0 iff same sign as d
-    t = fmax(fmin(fabs(d), 2.0 * t), 0.0);
-    return flip(t, s);
+    double sg = copysign(1.0, d);
+    double t = fmin(dm * sg, dp * sg);          // > 0 only if both share d's sign
+    t = fmax(fmin(fabs(d), t + t), 0.0);
+    return t * sg;
 }
 
 // PPM on u_{-2..2}: the Colella-Woodward monotonicity step written in its
 // equivalent clamp form (a = q+ - u0, b = u0 - q-: flatten if a b <= 0, else
 // |b| <= 2|a| and |a| <= 2|b|), which needs no division and no branches.
-__device__ __forceinline__ void ppm_fast(double um2, double um1, double u0, double up1, double up2,
-                                double &qp, double &qm) {
+__device__ __forceinline__ void ppm_fast(double um2, double um1, double u0, double up1,
+                                         double up2, double &qp, double &qm) {
     const double sixth = 1.0 / 6.0;
-    double sm = mc_slope(um1 - um2, u0 - um1);
-    double s0 = mc_slope(u0 - um1, up1 - u0);
-    double sp = mc_slope(up1 - u0, up2 - up1);
+    double d0 = um1 - um2, d1 = u0 - um1, d2 = up1 - u0, d3 = up2 - up1;
+    double sm = mc_slope(d0, d1);
+    double s0 = mc_slope(d1, d2);
+    double sp = mc_slope(d2, d3);
     double ip = fma(s0 - sp, sixth, 0.5 * (u0 + up1));
     double im = fma(sm - s0, sixth, 0.5 * (um1 + u0));
     double a = ip - u0, b = u0 - im;
-    int s = __double2hiint(a) & (int)0x80000000;
+    double sg = copysign(1.0, a);
     double aa = fabs(a);
-    double sb = flip(b, s);                             // |b| if b has a's sign
-    double bn = fmax(fmin(sb, 2.0 * aa), 0.0);
-    double an = fmax(fmin(aa, 2.0 * sb), 0.0);
-    qp = u0 + flip(an, s);
-    qm = u0 - flip(bn, s);
+    double sb = b * sg;                          // |b| if b has a's sign, else < 0
+    double bn = fmax(fmin(sb, aa + aa), 0.0);
+    double an = fmax(fmin(aa, sb + sb), 0.0);
+    qp = fma(an, sg, u0);
+    qm = fma(-bn, sg, u0);
 }
 
-// ---- point state ----------------------------------------------------------
-
-struct PState {
-    double vx, vy, vz, p, cs;
-};
-
-__device__ __forceinline__ PState pstate(double rho, double sx, double sy, double sz, double E,
-                                double tau, double gamma, double gm1, double de, int &bits) {
-    PState st;
-    double r = 1.0 / rho;
-    st.vx = sx * r;
-    st.vy = sy * r;
-    st.vz = sz * r;
-    double ek = 0.5 * fma(sz, st.vz, fma(sy, st.vy, sx * st.vx));
-    double ei = E - ek;
-    if (ei < de * E) ei = pow(tau, gamma);
-    st.p = gm1 * ei;
-    st.cs = sqrt((gamma * st.p) * r);
-    bits |= (rho <= 0.0 ? HYDRO_STATUS_RHO : 0) | (st.p <= 0.0 ? HYDRO_STATUS_P : 0);
-    return st;
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS accesses,
+// not for its global loads and stores (which never carry data between waves).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-__device__ __forceinline__ void acc_hydro(Acc &a, const double *V, double un, double p, double cs,
-                                 double w) {
-    double wun = w * un;
-#pragma unroll
-    for (int f = 0; f < 6; f++) a.sv[f] = fma(w, V[f], a.sv[f]);
-    a.sf[1] = fma(wun, V[1], a.sf[1]);
-    a.sf[2] = fma(wun, V[2], a.sf[2]);
-    a.sf[3] = fma(wun, V[3], a.sf[3]);
-    a.sf[4] = fma(wun, V[4] + p, a.sf[4]);
-    a.sf[5] = fma(wun, V[5], a.sf[5]);
-    a.sp = fma(w, p, a.sp);
-    a.lp = fmax(a.lp, un + cs);
-    a.lm = fmin(a.lm, un - cs);
+// Hide a value from loop-invariant code motion: address arithmetic derived
+// from it is recomputed where it is used instead of being hoisted out of the
+// plane loop and kept live (which would exhaust the register file).
+// Compile-time scheduling fence: keeps the scheduler from hoisting the loads
+// of one stage above the previous one (which would raise register pressure).
+__device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
+
+template <typename T>
+__device__ __forceinline__ T opaque_s(T v) {
+    asm volatile("" : "+s"(v));
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ T opaque_v(T v) {
+    asm volatile("" : "+v"(v));
+    return v;
 }
 
-__device__ __forceinline__ void acc_species(Acc &a, int f, double v, double w, double wun) {
-    a.sv[f] = fma(w, v, a.sv[f]);
-    a.sf[f] = fma(wun, v, a.sf[f]);
-}
+// Per-lane geometry, re-derived from an opaque thread index at the top of each
+// phase so that none of it is hoisted out of the loops and kept live:
+// (ci, cj) is the lane's interior cell of the plane; role-3 lanes own ring
+// cell rc = lane/2 (x-ring for rc < 16, else y-ring; low or high side).
+#define LANE_GEOMETRY()                                                          \
+    const int lane = opaque_v((int)threadIdx.x) & 63;                            \
+    const int ci = 3 + (lane & 7), cj = 3 + (lane >> 3);                         \
+    const int half = lane & 1;                                                   \
+    const int r_axis = (lane >> 1) >> 4, r_side = ((lane >> 1) >> 3) & 1;        \
+    const int r_pos = 3 + ((lane >> 1) & 7);                                     \
+    const int ri = r_axis == 0 ? (r_side ? 11 : 2) : r_pos;                      \
+    const int rj = r_axis == 0 ? r_pos : (r_side ? 11 : 2);                      \
+    (void)ci; (void)cj; (void)half; (void)r_axis; (void)r_side; (void)r_pos;     \
+    (void)ri; (void)rj
 
-// ---- LDS helpers ------------------------------------------------------------
-
-__device__ __forceinline__ const double *win_field(const double *win, int plane, int f) {
-    return win + ((plane % SLOTS) * NF_MAX + f) * NPLANE;
-}
+// ---- LDS window access --------------------------------------------------------
 
 // The five window offsets of the line through (i,j,k) along (dx,dy,dz).
 struct Line5 {
@@ -188,426 +172,634 @@ __device__ __forceinline__ Line5 line5(int i, int j, int k, int dx, int dy, int 
 #pragma unroll
     for (int m = -2; m <= 2; m++) {
         int pl = (k + m * dz) % SLOTS;
-        l.o[m + 2] = pl * NF_MAX * NPLANE + (j + m * dy) * NB + (i + m * dx);
+        l.o[m + 2] = pl * SLOT_D + (j + m * dy) * NB + (i + m * dx);
     }
     return l;
 }
 
-__device__ __forceinline__ void ppm_at(const double *win, const Line5 &l, int f, double &qp, double &qm) {
+__device__ __forceinline__ void ppm_at(const double *win, const Line5 &l, int f, double &qp,
+                                       double &qm) {
     const int fo = f * NPLANE;
     ppm_fast(win[l.o[0] + fo], win[l.o[1] + fo], win[l.o[2] + fo], win[l.o[3] + fo],
              win[l.o[4] + fo], qp, qm);
 }
 
-// Store/load of a 24-double partial at stride `st` (component-major layouts).
-__device__ __forceinline__ void acc_store(double *base, int st, const Acc &a, int nf) {
-#pragma unroll
-    for (int f = 0; f < NF_MAX; f++)
-        if (f < nf) base[f * st] = a.sv[f];
-#pragma unroll
-    for (int f = 1; f < NF_MAX; f++)
-        if (f < nf) base[(10 + f) * st] = a.sf[f];
-    base[21 * st] = a.sp;
-    base[22 * st] = a.lp;
-    base[23 * st] = a.lm;
+// ---- producers ------------------------------------------------------------------
+
+// Hydro fields along one line: reconstructed values and the point states at
+// both ends, written to the exchange slots as they are formed (component
+// stride 64) when `store`; with `both` false only the + point is formed.
+struct PlusState {
+    double q[6];
+    double vx, vy, p, cs;
+};
+
+template <bool store, bool both>
+__device__ __forceinline__ PlusState produce_hydro(const double *win, const Line5 &l,
+                                                   double *pp, double *pm, double gamma,
+                                                   double gm1, double de, int &bits) {
+    PlusState ps;
+    double qp, qm;
+    ppm_at(win, l, 0, qp, qm);
+    ps.q[0] = qp;
+    if (store) pp[0] = qp;
+    if (both) pm[0] = qm;
+    const double rhop = qp, rhom = qm;
+    const double rp = 1.0 / qp, rm = both ? 1.0 / qm : 1.0;
+    ppm_at(win, l, 1, qp, qm);
+    ps.q[1] = qp;
+    if (store) pp[64] = qp;
+    if (both) pm[64] = qm;
+    const double vxp = qp * rp, vxm = qm * rm;
+    double ekp = qp * vxp, ekm = qm * vxm;
+    ppm_at(win, l, 2, qp, qm);
+    ps.q[2] = qp;
+    if (store) pp[2 * 64] = qp;
+    if (both) pm[2 * 64] = qm;
+    const double vyp = qp * rp, vym = qm * rm;
+    ekp = fma(qp, vyp, ekp);
+    ekm = fma(qm, vym, ekm);
+    ppm_at(win, l, 3, qp, qm);
+    ps.q[3] = qp;
+    if (store) pp[3 * 64] = qp;
+    if (both) pm[3 * 64] = qm;
+    const double vzp = qp * rp, vzm = qm * rm;
+    ekp = fma(qp, vzp, ekp);
+    ekm = fma(qm, vzm, ekm);
+    ppm_at(win, l, 4, qp, qm);
+    ps.q[4] = qp;
+    if (store) pp[4 * 64] = qp;
+    if (both) pm[4 * 64] = qm;
+    const double Ep = qp, Em = qm;
+    ppm_at(win, l, 5, qp, qm);
+    ps.q[5] = qp;
+    if (store) pp[5 * 64] = qp;
+    if (both) pm[5 * 64] = qm;
+    double eip = fma(-0.5, ekp, Ep);
+    if (eip < de * Ep) eip = pow(qp, gamma);      // dual energy: tau^gamma
+    const double prp = gm1 * eip;
+    const double csp = sqrt((gamma * prp) * rp);
+    if (store) {
+        pp[P_VX * 64] = vxp;
+        pp[(P_VX + 1) * 64] = vyp;
+        pp[(P_VX + 2) * 64] = vzp;
+        pp[P_P * 64] = prp;
+        pp[P_CS * 64] = csp;
+    }
+    bits |= (rhop <= 0.0 ? HYDRO_STATUS_RHO : 0) | (prp <= 0.0 ? HYDRO_STATUS_P : 0);
+    if (both) {
+        double eim = fma(-0.5, ekm, Em);
+        if (eim < de * Em) eim = pow(qm, gamma);
+        const double prm = gm1 * eim;
+        pm[P_VX * 64] = vxm;
+        pm[(P_VX + 1) * 64] = vym;
+        pm[(P_VX + 2) * 64] = vzm;
+        pm[P_P * 64] = prm;
+        pm[P_CS * 64] = sqrt((gamma * prm) * rm);
+        bits |= (rhom <= 0.0 ? HYDRO_STATUS_RHO : 0) | (prm <= 0.0 ? HYDRO_STATUS_P : 0);
+    }
+    ps.vx = vxp;
+    ps.vy = vyp;
+    ps.p = prp;
+    ps.cs = csp;
+    return ps;
 }
 
-// Face flux from the left partial L and a right partial stored at (R, st)
-// (or the reverse when `left_in_lds`), normal axis `axis`.  Writes Fb[f] for
-// f < nf and returns max(a+, -a-).
-__device__ __forceinline__ double combine(const Acc &mine, const double *other, int st, bool mine_is_left,
-                                 int axis, int nf, double *Fb) {
-    const double lp = fmax(mine.lp, other[22 * st]);
-    const double lm = fmin(mine.lm, other[23 * st]);
-    const double ap = fmax(0.0, lp);
-    const double am = fmin(0.0, lm);
-    const double inv = 1.0 / (ap - am);
-    const double apam = ap * am;
-    // left/right selectors
-    const double cl = mine_is_left ? ap : -am;       // coefficient of my S_F
-    const double co = mine_is_left ? -am : ap;       // coefficient of the other S_F
-    const double sg = mine_is_left ? 1.0 : -1.0;     // (S_V^R - S_V^L) = sg * (other - mine)
-    const double osp = other[21 * st];
-    // (value selects, not an lvalue conditional: the latter would index the
-    // accumulator through a pointer and force it out of registers)
-    const double m1 = mine.sv[1], m2 = mine.sv[2], m3 = mine.sv[3];
-    const double ms_axis = axis == 0 ? m1 : (axis == 1 ? m2 : m3);
-    const double os_axis = other[(1 + axis) * st];
+// ---- accumulation of one surface point into a face-side partial ----------------
+// Hydro waves use all NH slots; species waves use slots 0..4 (sv) and 5..9 (sf).
+
+__device__ __forceinline__ void acc_zero(double (&c)[NH], bool hydro) {
 #pragma unroll
-    for (int f = 0; f < NF_MAX; f++) {
-        if (f < nf) {
-            double sfm, sfo;
-            if (f == 0) {
-                sfm = ms_axis;
-                sfo = os_axis;
+    for (int i = 0; i < NH; i++) c[i] = 0.0;
+    if (hydro) {
+        c[H_LP] = -INFINITY;
+        c[H_LM] = INFINITY;
+    }
+}
+
+__device__ __forceinline__ void acc_h_vals(double (&c)[NH], const double *V, double un,
+                                           double p, double cs, double w) {
+    const double wun = w * un;
+#pragma unroll
+    for (int f = 0; f < 6; f++) c[f] = fma(w, V[f], c[f]);
+    c[6] = fma(wun, V[1], c[6]);
+    c[7] = fma(wun, V[2], c[7]);
+    c[8] = fma(wun, V[3], c[8]);
+    c[9] = fma(wun, V[4] + p, c[9]);
+    c[10] = fma(wun, V[5], c[10]);
+    c[H_SP] = fma(w, p, c[H_SP]);
+    c[H_LP] = fmax(c[H_LP], un + cs);
+    c[H_LM] = fmin(c[H_LM], un - cs);
+}
+
+// point in LDS at pt (component stride 64), normal axis ax
+__device__ __forceinline__ void acc_h_lds(double (&c)[NH], const double *pt, int ax, double w) {
+    double V[6];
+#pragma unroll
+    for (int f = 0; f < 6; f++) V[f] = pt[f * 64];
+    acc_h_vals(c, V, pt[(P_VX + ax) * 64], pt[P_P * 64], pt[P_CS * 64], w);
+}
+
+// (always all 5 species slots: slots past the subgrid's species count hold
+// values that are never stored, so no per-field branch splits the loads)
+__device__ __forceinline__ void acc_s_lds(double (&c)[NH], const double *pt, int ax, double w) {
+    const double wun = w * pt[(P_VX + ax) * 64];
+#pragma unroll
+    for (int i = 0; i < 5; i++) {
+        const double v = pt[(6 + i) * 64];
+        c[i] = fma(w, v, c[i]);
+        c[5 + i] = fma(wun, v, c[5 + i]);
+    }
+}
+
+// ---- partials in LDS (component stride st; hydro comps, then species) ----------
+
+__device__ __forceinline__ void store_h(double *base, int st, const double (&c)[NH]) {
+#pragma unroll
+    for (int i = 0; i < NH; i++) base[i * st] = c[i];
+}
+
+__device__ __forceinline__ void store_s(double *base, int st, const double (&c)[NH], int ns) {
+#pragma unroll
+    for (int i = 0; i < 5; i++)
+        if (i < ns) {
+            base[(NH + i) * st] = c[i];
+            base[(NH + 5 + i) * st] = c[5 + i];
+        }
+}
+
+struct Speeds {
+    double ap, am, inv, apam, amax_face;
+};
+
+__device__ __forceinline__ Speeds face_speeds(double lpL, double lmL, double lpR, double lmR) {
+    Speeds s;
+    s.ap = fmax(0.0, fmax(lpL, lpR));
+    s.am = fmin(0.0, fmin(lmL, lmR));
+    s.inv = 1.0 / (s.ap - s.am);
+    s.apam = s.ap * s.am;
+    s.amax_face = fmax(s.ap, -s.am);
+    return s;
+}
+
+// Hydro fluxes of a face from my partial (registers) and the other side's
+// (LDS at o, stride st).  Writes Fb[0..5].
+__device__ __forceinline__ Speeds combine_h(const double (&m)[NH], const double *o, int st,
+                                            bool mine_left, int axis, double *Fb) {
+    const double mlp = m[H_LP], mlm = m[H_LM], olp = o[H_LP * st], olm = o[H_LM * st];
+    const Speeds s = mine_left ? face_speeds(mlp, mlm, olp, olm) : face_speeds(olp, olm, mlp, mlm);
+    const double cm = mine_left ? s.ap : -s.am;     // coefficient of my S_F
+    const double co = mine_left ? -s.am : s.ap;     // coefficient of the other S_F
+    const double sg = mine_left ? 1.0 : -1.0;       // S_V^R - S_V^L = sg (other - mine)
+    // density flux: S_V of the normal momentum (value selects, no indexing)
+    const double m1 = m[1], m2 = m[2], m3 = m[3];
+    const double ms = axis == 0 ? m1 : (axis == 1 ? m2 : m3);
+    const double os = o[(1 + axis) * st];
+    Fb[0] = fma(cm, ms, co * os) * s.inv + (s.apam * (sg * (o[0] - m[0]))) * s.inv;
+    const double msp = m[H_SP], osp = o[H_SP * st];
+#pragma unroll
+    for (int f = 1; f < 6; f++) {
+        double sfm = m[5 + f], sfo = o[(5 + f) * st];
+        if (f == 1 + axis) {
+            sfm += msp;
+            sfo += osp;
+        }
+        Fb[f] = fma(cm, sfm, co * sfo) * s.inv + (s.apam * (sg * (o[f * st] - m[f]))) * s.inv;
+    }
+    return s;
+}
+
+// Species fluxes of a face, speeds given; the other side's species partial at o.
+__device__ __forceinline__ void combine_s(const double (&m)[NH], const double *o, int st,
+                                          bool mine_left, const Speeds &s, int ns, double *Fb) {
+    const double cm = mine_left ? s.ap : -s.am;
+    const double co = mine_left ? -s.am : s.ap;
+    const double sg = mine_left ? 1.0 : -1.0;
+#pragma unroll
+    for (int i = 0; i < 5; i++)
+        if (i < ns) {
+            const double sfm = m[5 + i], sfo = o[(NH + 5 + i) * st];
+            const double dv = sg * (o[(NH + i) * st] - m[i]);
+            Fb[6 + i] = fma(cm, sfm, co * sfo) * s.inv + (s.apam * dv) * s.inv;
+        }
+}
+
+// Update of one interior cell of plane `kc` from its z flux Fz and the kept
+// x/y difference: U_out = U - lam ((dFx + dFy) + dFz) for fields [f0, f1).
+__device__ __forceinline__ int update_cell(const double *win, const double *keep, int lane,
+                                           int kc, int ci, int cj, int f0, int f1,
+                                           const double *Fz, double lam, double *Os, int fst) {
+    int bits = 0;
+    const int cidx = opaque_v(kc * NPLANE + cj * NB + ci);
+    const int fs = opaque_s(fst);
+#pragma unroll
+    for (int f = 0; f < NF_MAX; f++)
+        if (f >= f0 && f < f1) {
+            const double dfz = Fz[f] - keep[f * 64 + lane];
+            const double sxy = keep[(NF_MAX + f) * 64 + lane];
+            const double u = win[(kc % SLOTS) * SLOT_D + f * NPLANE + cj * NB + ci];
+            const double v = u - lam * (sxy + dfz);
+            if (!isfinite(v) || !isfinite(Fz[f])) bits |= HYDRO_STATUS_NONFINITE;
+            Os[f * fs + cidx] = v;
+        }
+    return bits;
+}
+
+// The work of one subgrid for one field group (HYD: hydro fields and point
+// states; else: species).  Both instantiations execute the same sequence of
+// barriers, so the hydro and species waves of a workgroup stay in step.
+template <bool HYD>
+__device__ __forceinline__ void subgrid_body(double *win, double *xch, double *zl, double *keep,
+                                             double *run, int tid, int role, int nspec,
+                                             const double *Us0, double *Os0, int fst0,
+                                             double lam, double gamma, double gm1, double de,
+                                             double &amax_l, int &bits) {
+    const int nf = 6 + nspec;
+    const int f0 = HYD ? 0 : 6, f1 = HYD ? 6 : nf;     // this wave's fields
+    // this thread's share of a plane: up to 5 of the nf*196 values.  Lanes
+    // without an element load a valid address and store into the slot's
+    // dummy word, so the loads carry no branches and issue back to back.
+    int g_off[5], l_off[5];
+#pragma unroll
+    for (int q = 0; q < 5; q++) {
+        const int e = tid + q * NT;
+        const int f = e / NPLANE, c = e - f * NPLANE;
+        const bool ok = e < nf * NPLANE;
+        g_off[q] = ok ? f * fst0 + c : 0;
+        l_off[q] = ok ? f * NPLANE + c : NF_MAX * NPLANE;
+    }
+
+    lds_barrier();   // the previous subgrid's LDS reads are done
+    // window: planes 0..4, then prefetch plane 5
+    {
+        double v[SLOTS][5];
+#pragma unroll
+        for (int pl = 0; pl < SLOTS; pl++)
+#pragma unroll
+            for (int q = 0; q < 5; q++) v[pl][q] = Us0[g_off[q] + pl * NPLANE];
+#pragma unroll
+        for (int pl = 0; pl < SLOTS; pl++)
+#pragma unroll
+            for (int q = 0; q < 5; q++) win[pl * SLOT_D + l_off[q]] = v[pl][q];
+    }
+    double pf[5];
+#pragma unroll
+    for (int q = 0; q < 5; q++) pf[q] = Us0[g_off[q] + 5 * NPLANE];
+    lds_barrier();
+
+    double acc[2][NH];       // [0]: face + (or the ring / layer face), [1]: face -
+    double Fb[NF_MAX];
+    for (int k = 2; k <= 11; k++) {
+        const double *Us = Us0;
+        double *Os = Os0;
+        const int fst = opaque_s(fst0);
+        (void)fst;
+        acc_zero(acc[0], HYD);
+        acc_zero(acc[1], HYD);
+
+        // ---- rounds of line production and consumption.  Interior planes:
+        // 5 rounds (roles 0-2 produce their lines for the interior cells,
+        // role 3 the ring cells' lines).  Face layers k = 2 and 11: 3 rounds,
+        // every role produces one of the 9 points of the boundary z-face of
+        // the interior cells of the plane; role 2 consumes them.
+        const bool layer = (k == 2 || k == 11);
+        const int nrounds = layer ? 3 : 5;
+        const bool ring = !layer && role == 3;
+#pragma unroll 1
+        for (int r = 0; r < nrounds; r++) {
+            LANE_GEOMETRY();
+            int t = -1, L = -1, dx = 0, dy = 0, dz = 0, pi = ci, pj = cj;
+            bool active;
+            if (layer) {
+                t = role + 4 * r;
+                active = t < 9;
+                dx = t % 3 - 1;
+                dy = t / 3 - 1;
+                dz = k == 2 ? 1 : -1;
+            } else if (role < 3) {
+                L = line_of(role, r);
+                active = L >= 0;
+                dx = ldx(L);
+                dy = ldy(L);
+                dz = ldz(L);
             } else {
-                sfm = mine.sf[f];
-                sfo = other[(10 + f) * st];
-                if (f == 1 + axis) {
-                    sfm += mine.sp;
-                    sfo += osp;
+                t = half ? 5 + r : r;
+                active = t < 9;
+                const int dn = r_side ? -1 : 1;    // normal component
+                dx = r_axis == 0 ? dn : t % 3 - 1;
+                dy = r_axis == 0 ? t % 3 - 1 : dn;
+                dz = t / 3 - 1;
+                pi = ri;
+                pj = rj;
+            }
+            const bool both = !layer && role < 3;
+            double *pp = xch + (layer ? role * PT * 64 : (role * 2 + 0) * PT * 64) + lane;
+            double *pm = xch + (layer ? role * PT * 64 : (role * 2 + 1) * PT * 64) + lane;
+            if (active) {
+                const Line5 l = line5(pi, pj, k, dx, dy, dz);
+                if (HYD) {
+                    PlusState ps;
+                    if (ring)
+                        ps = produce_hydro<false, false>(win, l, pp, pm, gamma, gm1, de, bits);
+                    else if (layer)
+                        ps = produce_hydro<true, false>(win, l, pp, pm, gamma, gm1, de, bits);
+                    else
+                        ps = produce_hydro<true, true>(win, l, pp, pm, gamma, gm1, de, bits);
+                    if (ring) {
+                        const double vx = ps.vx, vy = ps.vy;
+                        const double un = r_axis == 0 ? vx : vy;
+                        acc_h_vals(acc[0], ps.q, un, ps.p, ps.cs,
+                                   simpson_w(t % 3 - 1, t / 3 - 1));
+                        run[lane] = un;
+                    }
+                } else {
+                    // all 5 species slots (see acc_s_lds); none at all without species
+                    if (nspec > 0) {
+#pragma unroll
+                        for (int f = 6; f < NF_MAX; f++) {
+                            double qp, qm;
+                            ppm_at(win, l, f, qp, qm);
+                            if (ring) {
+                                run[(f - 5) * 64 + lane] = qp;
+                            } else {
+                                pp[f * 64] = qp;
+                                if (both) pm[f * 64] = qm;
+                            }
+                        }
+                    }
                 }
             }
-            double dv = sg * (other[f * st] - mine.sv[f]);
-            Fb[f] = fma(cl, sfm, co * sfo) * inv + (apam * dv) * inv;
+            lds_barrier();
+            if (layer) {
+                if (role == 2) {
+#pragma unroll
+                    for (int w = 0; w < 4; w++) {
+                        const int t2 = w + 4 * r;
+                        if (t2 < 9) {
+                            const double wt = simpson_w(t2 % 3 - 1, t2 / 3 - 1);
+                            const double *pt = xch + w * PT * 64 + lane;
+                            if (HYD) acc_h_lds(acc[0], pt, 2, wt);
+                            else acc_s_lds(acc[0], pt, 2, wt);
+                        }
+                    }
+                }
+            } else if (role < 3) {
+                const int ax = role;
+                const int b1 = ax == 0 ? 1 : 0, b2 = ax == 2 ? 1 : 2;
+#pragma unroll
+                for (int p = 0; p < 3; p++) {
+                    const int Lp = line_of(p, r);
+                    if (Lp < 0) continue;
+                    const int dA = comp(Lp, ax);
+                    if (dA == 0) continue;              // wave-uniform: line not on my faces
+                    // both points of the line lie on my faces: the one on the + face
+                    // goes to acc[0], the other to acc[1]; same tangential weight
+                    const double wt = simpson_w(comp(Lp, b1), comp(Lp, b2));
+                    const double *p0 = xch + (p * 2 + 0) * PT * 64 + lane;
+                    const double *p1 = xch + (p * 2 + 1) * PT * 64 + lane;
+                    const double *pa = dA > 0 ? p0 : p1;
+                    const double *pb = dA > 0 ? p1 : p0;
+                    if (HYD) {
+                        acc_h_lds(acc[0], pa, ax, wt);
+                        acc_h_lds(acc[1], pb, ax, wt);
+                    } else {
+                        acc_s_lds(acc[0], pa, ax, wt);
+                        acc_s_lds(acc[1], pb, ax, wt);
+                    }
+                }
+            } else if (!HYD && active) {
+                // ring species: the normal velocity came from the hydro wave
+                const double wt = simpson_w(t % 3 - 1, t / 3 - 1);
+                const double wun = wt * run[lane];
+#pragma unroll
+                for (int i = 0; i < 5; i++) {
+                    const double v = run[(1 + i) * 64 + lane];
+                    acc[0][i] = fma(wt, v, acc[0][i]);
+                    acc[0][5 + i] = fma(wun, v, acc[0][5 + i]);
+                }
+            }
+            lds_barrier();
+        }
+
+        // plane k-2 is no longer read: its slot takes plane k+3 (prefetched one
+        // step ahead); then the loads of plane k+4 start, behind this step's stores
+        if (k + 3 <= 13) {
+            double *dst = win + ((k + 3) % SLOTS) * SLOT_D;
+#pragma unroll
+            for (int q = 0; q < 5; q++) dst[l_off[q]] = pf[q];
+            if (k + 4 <= 13) {
+#pragma unroll
+                for (int q = 0; q < 5; q++) pf[q] = Us[g_off[q] + (k + 4) * NPLANE];
+            }
+        }
+        lds_barrier();
+
+        if (layer) {
+            LANE_GEOMETRY();
+            if (k == 2) {
+                if (role == 2) {
+                    if (HYD) store_h(zl + lane, 64, acc[0]);
+                    else store_s(zl + lane, 64, acc[0], nspec);
+                }
+            } else {
+                // face (10|11): left partial from step 10, right = acc[0]; the species
+                // wave gets the right-side speeds through LDS
+                if (role == 2 && HYD) {
+                    xch[ZB_OFF + 2 * 64 + lane] = acc[0][H_LP];
+                    xch[ZB_OFF + 3 * 64 + lane] = acc[0][H_LM];
+                }
+                lds_barrier();
+                if (role == 2) {
+                    double Fz[NF_MAX];
+                    if (HYD) {
+                        const Speeds sp = combine_h(acc[0], zl + lane, 64, false, 2, Fz);
+                        amax_l = fmax(amax_l, sp.amax_face);
+                    } else {
+                        const Speeds sp = face_speeds(zl[H_LP * 64 + lane], zl[H_LM * 64 + lane],
+                                                      xch[ZB_OFF + 2 * 64 + lane],
+                                                      xch[ZB_OFF + 3 * 64 + lane]);
+                        combine_s(acc[0], zl + lane, 64, false, sp, nspec, Fz);
+                    }
+                    bits |= update_cell(win, keep, lane, 10, ci, cj, f0, f1, Fz, lam, Os, fst);
+                }
+            }
+            continue;
+        }
+
+        // ---- face fluxes of plane k and the update of plane k-1
+        {
+        LANE_GEOMETRY();
+        if (role == 3) {
+            // the two lanes of a ring cell hold partial sums: add them
+#pragma unroll
+            for (int i = 0; i < NH; i++) {
+                const double o = __shfl_xor(acc[0][i], 1);
+                if (HYD && i == H_LP) acc[0][i] = fmax(acc[0][i], o);
+                else if (HYD && i == H_LM) acc[0][i] = fmin(acc[0][i], o);
+                else acc[0][i] += o;
+            }
+        }
+        // phase 1: right-side partials and left-side speeds -> LDS
+        if (role == 0 || role == 1) {
+            double *R = xch + XR_OFF + (role == 0 ? (0 * 8 + (cj - 3)) * 9 + (ci - 3)
+                                                  : (1 * 8 + (ci - 3)) * 9 + (cj - 3));
+            if (HYD) store_h(R, RST, acc[1]);
+            else store_s(R, RST, acc[1], nspec);
+        }
+        if (role == 3 && half == 0 && r_side == 1) {
+            double *R = xch + XR_OFF + (r_axis * 8 + (r_pos - 3)) * 9 + 8;
+            if (HYD) store_h(R, RST, acc[0]);
+            else store_s(R, RST, acc[0], nspec);
+        }
+        if (HYD) {
+            int ll = -1;
+            if (role == 0) ll = (0 * 8 + (cj - 3)) * 9 + (ci - 2);
+            if (role == 1) ll = (1 * 8 + (ci - 3)) * 9 + (cj - 2);
+            if (role == 3 && half == 0 && r_side == 0) ll = (r_axis * 8 + (r_pos - 3)) * 9;
+            if (ll >= 0) {
+                xch[LL_OFF + ll] = acc[0][H_LP];
+                xch[LL_OFF + RST + ll] = acc[0][H_LM];
+            }
+            if (role == 2) {   // z face (k-1|k): left speeds (last step), right speeds
+                xch[ZB_OFF + 0 * 64 + lane] = zl[H_LP * 64 + lane];
+                xch[ZB_OFF + 1 * 64 + lane] = zl[H_LM * 64 + lane];
+                xch[ZB_OFF + 2 * 64 + lane] = acc[1][H_LP];
+                xch[ZB_OFF + 3 * 64 + lane] = acc[1][H_LM];
+            }
+        }
+        lds_barrier();
+        // phase 2: left owners form the x/y face fluxes; z owners the z face
+        if (role < 2 || (role == 3 && half == 0 && r_side == 0)) {
+            const int ax = role < 2 ? role : r_axis;
+            const int row = role == 0 ? cj - 3 : role == 1 ? ci - 3 : r_pos - 3;
+            const int p = role == 0 ? ci - 2 : role == 1 ? cj - 2 : 0;
+            const int fi = (ax * 8 + row) * 9 + p;
+            const double *R = xch + XR_OFF + fi;
+            double *Fo = xch + XF_OFF + fi;
+            if (HYD) {
+                const Speeds sp = combine_h(acc[0], R, RST, true, ax, Fb);
+                amax_l = fmax(amax_l, sp.amax_face);
+            } else {
+                const Speeds sp = face_speeds(xch[LL_OFF + fi], xch[LL_OFF + RST + fi],
+                                              R[H_LP * RST], R[H_LM * RST]);
+                combine_s(acc[0], R, RST, true, sp, nspec, Fb);
+            }
+#pragma unroll
+            for (int f = 0; f < NF_MAX; f++)
+                if (f >= f0 && f < f1) {
+                    Fo[f * RST] = Fb[f];
+                    if (!isfinite(Fb[f])) bits |= HYDRO_STATUS_NONFINITE;
+                }
+        }
+        if (role == 2) {
+            // z-face (k-1|k): left partial from the previous step, right = acc[1]
+            double Fz[NF_MAX];
+            if (HYD) {
+                const Speeds sp = combine_h(acc[1], zl + lane, 64, false, 2, Fz);
+                amax_l = fmax(amax_l, sp.amax_face);
+            } else {
+                const Speeds sp = face_speeds(xch[ZB_OFF + lane], xch[ZB_OFF + 64 + lane],
+                                              xch[ZB_OFF + 128 + lane], xch[ZB_OFF + 192 + lane]);
+                combine_s(acc[1], zl + lane, 64, false, sp, nspec, Fz);
+            }
+            if (k >= 4) bits |= update_cell(win, keep, lane, k - 1, ci, cj, f0, f1, Fz, lam, Os, fst);
+#pragma unroll
+            for (int f = 0; f < NF_MAX; f++)
+                if (f >= f0 && f < f1) {
+                    if (!isfinite(Fz[f])) bits |= HYDRO_STATUS_NONFINITE;
+                    keep[f * 64 + lane] = Fz[f];
+                }
+            if (HYD) store_h(zl + lane, 64, acc[0]);
+            else store_s(zl + lane, 64, acc[0], nspec);
+        }
+        lds_barrier();
+        // phase 3: x/y owners: flux differences of their cells -> LDS ([2][11][64])
+        if (role < 2) {
+            const int row = role == 0 ? cj - 3 : ci - 3;
+            const int p = role == 0 ? ci - 3 : cj - 3;      // left face of the cell
+            const double *Fl = xch + XF_OFF + (role * 8 + row) * 9 + p;
+            double *d = xch + DX_OFF + role * NF_MAX * 64 + lane;
+#pragma unroll
+            for (int f = 0; f < NF_MAX; f++)
+                if (f >= f0 && f < f1) d[f * 64] = Fb[f] - Fl[f * RST];
+        }
+        lds_barrier();
+        if (role == 2) {
+#pragma unroll
+            for (int f = 0; f < NF_MAX; f++)
+                if (f >= f0 && f < f1)
+                    keep[(NF_MAX + f) * 64 + lane] =
+                        xch[DX_OFF + f * 64 + lane] + xch[DX_OFF + (NF_MAX + f) * 64 + lane];
+        }
+        // (the next step's window barrier orders these reads before XCH reuse)
         }
     }
-    return fmax(ap, -am);
+
 }
 
 // ---- the kernel ---------------------------------------------------------------
 
-__global__ __launch_bounds__(NT, 1) void k_fused(StepArgs a, const double *__restrict__ U,
+__global__ __launch_bounds__(NT, 2) void k_fused(StepArgs a, const double *__restrict__ U,
                                                  double *__restrict__ Uo,
                                                  double *__restrict__ amax,
                                                  int32_t *__restrict__ status, int order) {
     __shared__ double lds[LDS_D];
-    __shared__ int red_bits[4];
+    __shared__ int red_bits[8];
     double *win = lds;
     double *xch = lds + WIN_D;
-    double *zl = xch + XCH_D;
-    double *keep = zl + ZL_D;          // [0: F_z of the previous face][1: dFx+dFy][11][64]
-    double *red = keep + KEEP_D;
+    double *zl = xch + XCH_D;          // z-face left partials carried between steps
+    double *keep = zl + ZL_D;          // [0: F_z of the face below][1: dFx+dFy][11][64]
+    double *run = keep + KEEP_D;       // ring lanes' normal velocity
+    double *red = run + RUN_D;
 
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int ci = 3 + (lane & 7), cj = 3 + (lane >> 3);
-    // ring cell of wave 3 (two lanes per cell)
-    const int rc = lane >> 1, half = lane & 1;
-    const int r_axis = rc >> 4;
-    const int r_side = (rc >> 3) & 1;        // 0: low side (left cell), 1: high side
-    const int r_pos = 3 + (rc & 7);
-    const int ri = r_axis == 0 ? (r_side ? 11 : 2) : r_pos;
-    const int rj = r_axis == 0 ? r_pos : (r_side ? 11 : 2);
+    const int tid = threadIdx.x, wave = tid >> 6;
+    const int role = wave & 3;           // wave-uniform
+    const bool hyd = wave < 4;
 
     const double gamma = a.gamma, gm1 = a.gamma - 1.0, de = a.de_switch;
 
     for (int it = blockIdx.x; it < a.n_sub; it += gridDim.x) {
         const int s = order ? (a.n_sub - 1 - it) : it;
-        const int ns = a.n_species[s];
+        const int nspec = a.n_species[s];
         const int64_t off = a.offset[s];
-        if (ns < 0 || ns > 5 || off < 0 || (off & 1)) {
+        if (nspec < 0 || nspec > 5 || off < 0 || (off & 1)) {
             if (tid == 0) {
                 amax[s] = 0.0;
                 if (status) status[s] = HYDRO_STATUS_BADMETA;
             }
             continue;
         }
-        const int nf = 6 + ns;
         const double lam = a.dt / a.h[s];
-        const double *Us = U + off;
-        double *Os = Uo + off;
-        const int64_t fst = a.fstride;
+        const double *Us0 = U + off;
+        double *Os0 = Uo + off;
+        const int fst0 = a.fstride;
         double amax_l = 0.0;
         int bits = 0;
 
-        __syncthreads();   // previous subgrid's LDS reads are done
-        // window: planes 0..4
-        for (int pl = 0; pl < SLOTS; pl++)
-            for (int e = tid; e < nf * NPLANE; e += NT) {
-                int f = e / NPLANE, c = e - f * NPLANE;
-                win[(pl * NF_MAX + f) * NPLANE + c] = Us[f * fst + pl * NPLANE + c];
-            }
-        double pf[9];
-#pragma unroll
-        for (int q = 0; q < 9; q++) {   // prefetch plane 5
-            int e = tid + q * NT;
-            pf[q] = 0.0;
-            if (e < nf * NPLANE) {
-                int f = e / NPLANE, c = e - f * NPLANE;
-                pf[q] = Us[f * fst + 5 * NPLANE + c];
-            }
-        }
-        __syncthreads();
-
-        Acc A, B;
-        for (int k = 2; k <= 11; k++) {
-            if (k >= 3) {
-                // plane k+2 from the prefetch registers, then prefetch k+3
-#pragma unroll
-                for (int q = 0; q < 9; q++) {
-                    int e = tid + q * NT;
-                    if (e < nf * NPLANE) {
-                        int f = e / NPLANE, c = e - f * NPLANE;
-                        win[(((k + 2) % SLOTS) * NF_MAX + f) * NPLANE + c] = pf[q];
-                    }
-                }
-                if (k + 3 <= 13) {
-#pragma unroll
-                    for (int q = 0; q < 9; q++) {
-                        int e = tid + q * NT;
-                        if (e < nf * NPLANE) {
-                            int f = e / NPLANE, c = e - f * NPLANE;
-                            pf[q] = Us[f * fst + (k + 3) * NPLANE + c];
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-            acc_zero(A);
-            acc_zero(B);
-
-            if (k == 2 || k == 11) {
-                // ---- z face layer: 9 points of one side of the boundary z-faces
-                const int dzs = k == 2 ? 1 : -1;
-                for (int r = 0; r < 3; r++) {
-                    const int t = wave + 4 * r;
-                    if (t < 9) {
-                        const int tx = t % 3 - 1, ty = t / 3 - 1;
-                        Line5 l = line5(ci, cj, k, tx, ty, dzs);
-                        double *pt = xch + wave * PT * 64 + lane;
-                        double q[6], qm;
-#pragma unroll
-                        for (int f = 0; f < 6; f++) ppm_at(win, l, f, q[f], qm);
-                        PState st = pstate(q[0], q[1], q[2], q[3], q[4], q[5], gamma, gm1, de, bits);
-#pragma unroll
-                        for (int f = 0; f < 6; f++) pt[f * 64] = q[f];
-#pragma unroll
-                        for (int f = 6; f < NF_MAX; f++)
-                            if (f < nf) {
-                                double v;
-                                ppm_at(win, l, f, v, qm);
-                                pt[f * 64] = v;
-                            }
-                        pt[(P_VX + 2) * 64] = st.vz;
-                        pt[P_P * 64] = st.p;
-                        pt[P_CS * 64] = st.cs;
-                    }
-                    __syncthreads();
-                    if (wave == 2) {
-                        for (int w = 0; w < 4; w++) {
-                            const int t2 = w + 4 * r;
-                            if (t2 >= 9) break;
-                            const double wt = simpson_w(t2 % 3 - 1, t2 / 3 - 1);
-                            const double *pt = xch + w * PT * 64 + lane;
-                            double V[6];
-#pragma unroll
-                            for (int f = 0; f < 6; f++) V[f] = pt[f * 64];
-                            const double un = pt[(P_VX + 2) * 64];
-                            // A holds this side of the boundary face in both layers
-                            acc_hydro(A, V, un, pt[P_P * 64], pt[P_CS * 64], wt);
-                            const double wun = wt * un;
-#pragma unroll
-                            for (int f = 6; f < NF_MAX; f++)
-                                if (f < nf) acc_species(A, f, pt[f * 64], wt, wun);
-                        }
-                    }
-                    __syncthreads();
-                }
-                if (wave == 2) {
-                    if (k == 2) {
-                        acc_store(zl + lane, 64, A, nf);
-                    } else {
-                        // face (10|11): left partial from the previous step, right = A
-                        double Fb[NF_MAX];
-                        double af = combine(A, zl + lane, 64, false, 2, nf, Fb);
-                        amax_l = fmax(amax_l, af);
-                        const int cidx = (k - 1) * NPLANE + cj * NB + ci;
-#pragma unroll
-                        for (int f = 0; f < NF_MAX; f++)
-                            if (f < nf) {
-                                double dfz = Fb[f] - keep[f * 64 + lane];
-                                double sxy = keep[(NF_MAX + f) * 64 + lane];
-                                double u = win_field(win, k - 1, f)[cj * NB + ci];
-                                double v = u - lam * (sxy + dfz);
-                                if (!isfinite(v) || !isfinite(Fb[f])) bits |= HYDRO_STATUS_NONFINITE;
-                                Os[f * fst + cidx] = v;
-                            }
-                    }
-                }
-                continue;
-            }
-
-            // ---- interior plane: 5 rounds of line production and consumption
-#pragma unroll
-            for (int r = 0; r < 5; r++) {
-                if (wave < 3) {
-                    const int L = line_of(wave, r);
-                    if (L >= 0) {
-                        Line5 l = line5(ci, cj, k, ldx(L), ldy(L), ldz(L));
-                        double qp[6], qm[6];
-#pragma unroll
-                        for (int f = 0; f < 6; f++) ppm_at(win, l, f, qp[f], qm[f]);
-                        PState sp = pstate(qp[0], qp[1], qp[2], qp[3], qp[4], qp[5], gamma, gm1, de, bits);
-                        PState sm = pstate(qm[0], qm[1], qm[2], qm[3], qm[4], qm[5], gamma, gm1, de, bits);
-                        double *pp = xch + (wave * 2 + 0) * PT * 64 + lane;
-                        double *pm = xch + (wave * 2 + 1) * PT * 64 + lane;
-#pragma unroll
-                        for (int f = 0; f < 6; f++) {
-                            pp[f * 64] = qp[f];
-                            pm[f * 64] = qm[f];
-                        }
-                        pp[P_VX * 64] = sp.vx; pp[(P_VX + 1) * 64] = sp.vy; pp[(P_VX + 2) * 64] = sp.vz;
-                        pp[P_P * 64] = sp.p; pp[P_CS * 64] = sp.cs;
-                        pm[P_VX * 64] = sm.vx; pm[(P_VX + 1) * 64] = sm.vy; pm[(P_VX + 2) * 64] = sm.vz;
-                        pm[P_P * 64] = sm.p; pm[P_CS * 64] = sm.cs;
-#pragma unroll
-                        for (int f = 6; f < NF_MAX; f++)
-                            if (f < nf) {
-                                double vp, vm;
-                                ppm_at(win, l, f, vp, vm);
-                                pp[f * 64] = vp;
-                                pm[f * 64] = vm;
-                            }
-                    }
-                } else {
-                    const int t = half ? 5 + r : r;
-                    if (t < 9) {
-                        const int t1 = t % 3 - 1, t2 = t / 3 - 1;
-                        const int dn = r_side ? -1 : 1;    // normal component
-                        const int Dx = r_axis == 0 ? dn : t1;
-                        const int Dy = r_axis == 0 ? t1 : dn;
-                        Line5 l = line5(ri, rj, k, Dx, Dy, t2);
-                        double q[6], qm;
-#pragma unroll
-                        for (int f = 0; f < 6; f++) ppm_at(win, l, f, q[f], qm);
-                        PState st = pstate(q[0], q[1], q[2], q[3], q[4], q[5], gamma, gm1, de, bits);
-                        const double wt = simpson_w(t1, t2);
-                        const double vx = st.vx, vy = st.vy;
-                        const double un = r_axis == 0 ? vx : vy;
-                        acc_hydro(A, q, un, st.p, st.cs, wt);
-                        const double wun = wt * un;
-#pragma unroll
-                        for (int f = 6; f < NF_MAX; f++)
-                            if (f < nf) {
-                                double v;
-                                ppm_at(win, l, f, v, qm);
-                                acc_species(A, f, v, wt, wun);
-                            }
-                    }
-                }
-                __syncthreads();
-                if (wave < 3) {
-                    const int ax = wave;
-                    const int b1 = ax == 0 ? 1 : 0, b2 = ax == 2 ? 1 : 2;
-#pragma unroll
-                    for (int p = 0; p < 3; p++) {
-                        const int L = line_of(p, r);
-                        if (L < 0) continue;
-                        const int dA = comp(L, ax);
-                        if (dA == 0) continue;
-#pragma unroll
-                        for (int pm = 0; pm < 2; pm++) {
-                            const int sgn = pm == 0 ? 1 : -1;
-                            const int t1 = sgn * comp(L, b1), t2 = sgn * comp(L, b2);
-                            const double wt = simpson_w(t1, t2);
-                            const double *pt = xch + (p * 2 + pm) * PT * 64 + lane;
-                            double V[6];
-#pragma unroll
-                            for (int f = 0; f < 6; f++) V[f] = pt[f * 64];
-                            const double un = pt[(P_VX + ax) * 64];
-                            const double pr = pt[P_P * 64], cs = pt[P_CS * 64];
-                            const double wun = wt * un;
-                            if (sgn * dA > 0) {
-                                acc_hydro(A, V, un, pr, cs, wt);
-#pragma unroll
-                                for (int f = 6; f < NF_MAX; f++)
-                                    if (f < nf) acc_species(A, f, pt[f * 64], wt, wun);
-                            } else {
-                                acc_hydro(B, V, un, pr, cs, wt);
-#pragma unroll
-                                for (int f = 6; f < NF_MAX; f++)
-                                    if (f < nf) acc_species(B, f, pt[f * 64], wt, wun);
-                            }
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-
-            // ---- face fluxes of plane k and the update of plane k-1
-            if (wave == 3) {
-                // the two lanes of a ring cell hold partial sums: add them
-#pragma unroll
-                for (int f = 0; f < NF_MAX; f++) {
-                    A.sv[f] += __shfl_xor(A.sv[f], 1);
-                    A.sf[f] += __shfl_xor(A.sf[f], 1);
-                }
-                A.sp += __shfl_xor(A.sp, 1);
-                A.lp = fmax(A.lp, __shfl_xor(A.lp, 1));
-                A.lm = fmin(A.lm, __shfl_xor(A.lm, 1));
-            }
-            // right-side partials of the x and y faces -> LDS  ([24][2][8][9])
-            constexpr int RST = 2 * 8 * 9;
-            if (wave == 0) acc_store(xch + XR_OFF + (0 * 8 + (cj - 3)) * 9 + (ci - 3), RST, B, nf);
-            if (wave == 1) acc_store(xch + XR_OFF + (1 * 8 + (ci - 3)) * 9 + (cj - 3), RST, B, nf);
-            if (wave == 3 && half == 0 && r_side == 1)
-                acc_store(xch + XR_OFF + (r_axis * 8 + (r_pos - 3)) * 9 + 8, RST, A, nf);
-            __syncthreads();
-            // left owners form the face fluxes ([11][2][8][9])
-            double Fb[NF_MAX];
-            if (wave < 2 || (wave == 3 && half == 0 && r_side == 0)) {
-                const int ax = wave < 2 ? wave : r_axis;
-                const int row = wave == 0 ? cj - 3 : wave == 1 ? ci - 3 : r_pos - 3;
-                const int p = wave == 0 ? ci - 2 : wave == 1 ? cj - 2 : 0;
-                const double *R = xch + XR_OFF + (ax * 8 + row) * 9 + p;
-                double af = combine(A, R, RST, true, ax, nf, Fb);
-                amax_l = fmax(amax_l, af);
-                double *Fo = xch + XF_OFF + (ax * 8 + row) * 9 + p;
-#pragma unroll
-                for (int f = 0; f < NF_MAX; f++)
-                    if (f < nf) {
-                        Fo[f * RST] = Fb[f];
-                        if (!isfinite(Fb[f])) bits |= HYDRO_STATUS_NONFINITE;
-                    }
-            }
-            if (wave == 2) {
-                // z-face (k-1|k): left partial from the previous step, right = B
-                double Fz[NF_MAX];
-                double af = combine(B, zl + lane, 64, false, 2, nf, Fz);
-                amax_l = fmax(amax_l, af);
-                const int cidx = (k - 1) * NPLANE + cj * NB + ci;
-#pragma unroll
-                for (int f = 0; f < NF_MAX; f++)
-                    if (f < nf) {
-                        if (k >= 4) {
-                            double dfz = Fz[f] - keep[f * 64 + lane];
-                            double sxy = keep[(NF_MAX + f) * 64 + lane];
-                            double u = win_field(win, k - 1, f)[cj * NB + ci];
-                            double v = u - lam * (sxy + dfz);
-                            if (!isfinite(v)) bits |= HYDRO_STATUS_NONFINITE;
-                            Os[f * fst + cidx] = v;
-                        }
-                        if (!isfinite(Fz[f])) bits |= HYDRO_STATUS_NONFINITE;
-                        keep[f * 64 + lane] = Fz[f];
-                    }
-                acc_store(zl + lane, 64, A, nf);
-            }
-            __syncthreads();
-            // x/y owners: flux differences of their cells -> LDS ([2][11][64])
-            if (wave < 2) {
-                const int ax = wave;
-                const int row = wave == 0 ? cj - 3 : ci - 3;
-                const int p = wave == 0 ? ci - 3 : cj - 3;      // left face of the cell
-                const double *Fl = xch + XF_OFF + (ax * 8 + row) * 9 + p;
-                double *d = xch + DX_OFF + ax * NF_MAX * 64 + lane;
-#pragma unroll
-                for (int f = 0; f < NF_MAX; f++)
-                    if (f < nf) d[f * 64] = Fb[f] - Fl[f * RST];
-            }
-            __syncthreads();
-            if (wave == 2) {
-#pragma unroll
-                for (int f = 0; f < NF_MAX; f++)
-                    if (f < nf)
-                        keep[(NF_MAX + f) * 64 + lane] =
-                            xch[DX_OFF + f * 64 + lane] + xch[DX_OFF + (NF_MAX + f) * 64 + lane];
-            }
-            // (the next step's window barrier orders these reads before XCH reuse)
-        }
+        if (hyd)
+            subgrid_body<true>(win, xch, zl, keep, run, tid, role, nspec, Us0, Os0, fst0, lam,
+                               gamma, gm1, de, amax_l, bits);
+        else
+            subgrid_body<false>(win, xch, zl, keep, run, tid, role, nspec, Us0, Os0, fst0, lam,
+                                gamma, gm1, de, amax_l, bits);
 
         // ---- per-subgrid speed and status
         for (int o = 32; o > 0; o >>= 1) {
             amax_l = fmax(amax_l, __shfl_xor(amax_l, o));
             bits |= __shfl_xor(bits, o);
         }
-        if (lane == 0) {
+        if ((tid & 63) == 0) {
             red[wave] = amax_l;
             red_bits[wave] = bits;
         }
-        __syncthreads();
+        lds_barrier();
         if (tid == 0) {
-            double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-            int b = red_bits[0] | red_bits[1] | red_bits[2] | red_bits[3];
+            double m = 0.0;
+            int b = 0;
+            for (int w = 0; w < 8; w++) {
+                m = fmax(m, red[w]);
+                b |= red_bits[w];
+            }
             if (!isfinite(m)) b |= HYDRO_STATUS_NONFINITE;
             amax[s] = m;
             if (status) status[s] = b;
