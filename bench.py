@@ -16,6 +16,7 @@ Prints ONE JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,9 +30,74 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TFLOPS = 78.6     # MI355X vector FP64 (published)
 HBM_PEAK_GBPS = 8000.0      # MI355X HBM3E (published)
 
+# HBM traffic of the fused kernel, from two counter passes over
+# `bench.py --traffic-probe` (one fused step on the 128^3 batch, then a copy of
+# COPY_BYTES).  The counter file also holds the hash of the kernel sources the
+# counts were taken with; traffic is reported only while those are unchanged.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fused_binary_star_4096_traffic.md")
+KERNEL_SOURCES = ("paper_2210_06439_amd/csrc/fused.hip", "paper_2210_06439_amd/csrc/hydro_internal.hpp")
+COPY_BYTES = 512 * 1024 * 1024
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_per_launch():
+    """HBM bytes per fused launch from the committed counter summary, scaled by
+    the copy calibration, or None if the kernel changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            lines = f.read().splitlines()
+    except OSError:
+        return None, "no counter summary"
+    vals = {}
+    for ln in lines:
+        parts = ln.split()
+        if len(parts) == 3 and parts[0] == "counter:":
+            vals[parts[1]] = parts[2]
+    try:
+        if vals["sources_sha256"] != kernel_source_hash():
+            return None, "kernel changed since the counters were taken"
+        copy_kib = float(vals["copy_bytes"]) / 1024.0
+        f_scale = copy_kib / float(vals["copy_FETCH_SIZE_KiB"])
+        w_scale = copy_kib / float(vals["copy_WRITE_SIZE_KiB"])
+        fetch = float(vals["k_fused_FETCH_SIZE_KiB"]) * f_scale * 1024.0
+        write = float(vals["k_fused_WRITE_SIZE_KiB"]) * w_scale * 1024.0
+    except (KeyError, ValueError, ZeroDivisionError):
+        return None, "counter summary incomplete"
+    return {"bytes": fetch + write, "read_bytes": fetch, "write_bytes": write,
+            "fetch_scale": f_scale, "write_scale": w_scale}, None
+
+
+def traffic_probe():
+    """One fused step on the 128^3 batch, then a device copy of COPY_BYTES
+    (the calibration for FETCH_SIZE / WRITE_SIZE); run under rocprofv3 --pmc."""
+    import torch
+
+    from paper_2210_06439_amd import hydro, inputs
+    torch.cuda.set_device(0)
+    b = inputs.config3()
+    db = hydro.DeviceBatch.from_inputs(b)
+    U_out = db.U.clone()
+    amax = torch.zeros(db.n_sub, dtype=torch.float64, device="cuda")
+    hydro.step(hydro.params(dt=b.dt), db.struct, db.U, U_out, amax)
+    torch.cuda.synchronize()
+    src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"traffic_probe": True, "copy_bytes": COPY_BYTES,
+                      "sources_sha256": kernel_source_hash()}), flush=True)
 
 
 def timed_plan(plan, steps, warmup, torch):
@@ -126,11 +192,16 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="one fused step and a calibration copy, for counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the hydro stage is measured on a single "
               "MI355X (multi-GPU sharding is a design note, not built).", file=sys.stderr)
         sys.exit(2)
+    if args.traffic_probe:
+        traffic_probe()
+        return
 
     import torch
 
@@ -162,6 +233,12 @@ def main():
     log(f"config3 fused: {ms_per_step:.3f} ms/step wall, kernel {kern_ms:.3f} ms, "
         f"{value:.3e} cell-updates/s, {achieved_tf:.1f} TFLOP/s, {achieved_gbps:.0f} GB/s")
     plan.close()
+    traffic, why = traffic_per_launch()
+    if traffic is None:
+        log(f"traffic: null ({why})")
+    else:
+        log(f"traffic: {traffic['bytes'] / 1e9:.3f} GB per launch "
+            f"({traffic['bytes'] / nbytes:.3f} x algorithmic)")
 
     result = {
         "metric": "FP64 hydro cell-updates/s, batched vs per-subgrid launch; p50/p99 step latency",
@@ -182,11 +259,14 @@ def main():
                    "variant": hydro.variant_name(best)},
         "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99))},
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved_tf / FP64_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved_tf / FP64_PEAK_TFLOPS,
+                     "traffic": None if traffic is None else traffic["bytes"],
                      "kernel": "k_fused", "flops_per_launch": flops,
                      "kernel_ms": kern_ms},
         "hbm": {"achieved": achieved_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": achieved_gbps / HBM_PEAK_GBPS, "bytes_per_launch": nbytes},
+                "frac": achieved_gbps / HBM_PEAK_GBPS, "bytes_per_launch": nbytes,
+                "traffic_bytes_per_launch": None if traffic is None else traffic["bytes"],
+                "traffic_over_algorithmic": None if traffic is None else traffic["bytes"] / nbytes},
     }
     del U_out, db
     torch.cuda.empty_cache()

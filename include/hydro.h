@@ -157,8 +157,8 @@ int hydro_step_variant(const hydro_params *params, const hydro_batch *batch,
 /*
  * hydro_autotune -- times every variant on this batch (`reps` launches each,
  * after one warm-up, with HIP events on `stream`, synchronising the stream),
- * records the fastest for batches of this kind (keyed by the power-of-two
- * bucket of n_sub and the largest species count) and returns its index, or a
+ * records the fastest for batches of this size (keyed by the power-of-two
+ * bucket of n_sub) and returns its index, or a
  * negative error code.  times_ms (host, may be NULL) receives
  * hydro_variant_count() mean times.  U_out, amax and status are overwritten.
  */
@@ -166,8 +166,9 @@ int hydro_autotune(const hydro_params *params, const hydro_batch *batch,
                    const double *U_in, double *U_out, double *amax,
                    int32_t *status, int reps, float *times_ms, void *stream);
 
-/* The variant hydro_step will use for a batch of n_sub subgrids whose largest
- * species count is max_species (the tuned one, else the default). */
+/* The variant hydro_step will use for a batch of n_sub subgrids (the tuned one
+ * for that power-of-two bucket, else the default).  max_species is reserved:
+ * the choice does not depend on it. */
 int hydro_selected_variant(int n_sub, int max_species);
 
 /* ---------------------------------------------------------------------------
