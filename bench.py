@@ -164,6 +164,30 @@ def plain_vs_batched(torch, hydro, inputs, reps=3):
     return out
 
 
+def serving_run(torch, hydro, serving, b, db, peak_subgrids_per_s, n_requests, budget_gb):
+    """Continuous-batching serving of Poisson request streams drawn from the
+    128^3 batch at offered loads 0.3/0.6/0.9 of the measured batched peak."""
+    n_slots = serving.slots_for_budget(int(budget_gb * 1e9))
+    be = serving.GpuBackend(n_slots, catalogue=db)
+    work = serving.mean_work(4000, b.n_sub)
+    out = {"budget_GB": budget_gb, "slots": n_slots, "requests_per_load": n_requests,
+           "peak_subgrid_steps_per_s": peak_subgrids_per_s, "mean_subgrid_steps_per_request": work,
+           "streams": 2, "loads": {}}
+    for load in (0.3, 0.6, 0.9):
+        rate = load * peak_subgrids_per_s / work
+        reqs = serving.poisson_requests(n_requests, rate, b.n_sub, b.h, b.n_species)
+        recs = serving.HydroServer(be, b.dt).run(reqs, realtime=True)
+        summ = serving.summarize(recs)
+        summ["offered_requests_per_s"] = rate
+        out["loads"][str(load)] = summ
+        log(f"serving load {load}: {summ['cell_updates_per_s']:.3e} cell-updates/s, "
+            f"p50 {summ['latency_ms']['p50']:.2f} ms, p99 {summ['latency_ms']['p99']:.2f} ms, "
+            f"{summ['ticks']} ticks")
+    del be
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(b, seconds):
     """The oracle, single-threaded, on evenly spaced subgrids of the workload."""
     import oracle
@@ -192,6 +216,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--serving-budget-gb", type=float, default=64.0)
     ap.add_argument("--traffic-probe", action="store_true",
                     help="one fused step and a calibration copy, for counter runs")
     args = ap.parse_args()
@@ -205,7 +232,7 @@ def main():
 
     import torch
 
-    from paper_2210_06439_amd import costmodel, hydro, inputs
+    from paper_2210_06439_amd import costmodel, hydro, inputs, serving
 
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
@@ -268,7 +295,12 @@ def main():
                 "traffic_bytes_per_launch": None if traffic is None else traffic["bytes"],
                 "traffic_over_algorithmic": None if traffic is None else traffic["bytes"] / nbytes},
     }
-    del U_out, db
+    del U_out
+    torch.cuda.empty_cache()
+    if not args.no_serving:
+        result["serving"] = serving_run(torch, hydro, serving, b, db, b.n_sub / (kern_ms * 1e-3),
+                                        args.serving_requests, args.serving_budget_gb)
+    del db
     torch.cuda.empty_cache()
     if not args.no_plain:
         result["plain_vs_batched"] = plain_vs_batched(torch, hydro, inputs)
