@@ -320,27 +320,23 @@ def config4(seed: int = 1004, launch: int = 0, max_sub: int = 8192,
 
 # ---------------------------------------------------------------- config 5 --
 
-@dataclasses.dataclass
-class Request:
-    rid: int
-    arrival: float           # seconds after the stream starts
-    subgrids: np.ndarray     # indices into config 3's 4096 subgrids
-    steps: int               # session length S (steps with frozen ghosts)
-
-
-def config5_requests(n_requests: int, rate: float, seed: int = 1005,
-                     pool: int = 4096, max_sub: int = 4096):
-    """Poisson(rate) arrivals; sizes clip(round(lognormal(ln 128, 1.5)), 1, 4096)
-    subgrids drawn without replacement from a pool; S in {1, 2, 4} steps."""
+def config5_requests(n_requests: int, rate: float, seed: int = 1005, pool: int = 4096,
+                     max_sub: int = 4096, median_n: float = 128.0, sigma: float = 1.5,
+                     steps=(1, 2, 4)):
+    """Request stream: Poisson(rate) arrivals; sizes
+    clip(round(lognormal(ln median_n, sigma)), 1, min(max_sub, pool)) subgrids
+    drawn without replacement from a pool of subgrids; session length S
+    uniform over `steps`.  Returns (arrival seconds, subgrid indices, S) per
+    request."""
     rng = np.random.default_rng(seed)
-    t = 0.0
-    reqs = []
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n_requests))
+    out = []
     for i in range(n_requests):
-        t += float(rng.exponential(1.0 / rate))
-        n = int(np.clip(round(float(np.exp(rng.normal(np.log(128), 1.5)))), 1, min(max_sub, pool)))
+        n = int(np.clip(np.round(np.exp(rng.normal(np.log(median_n), sigma))), 1,
+                        min(max_sub, pool)))
         idx = np.sort(rng.choice(pool, size=n, replace=False))
-        reqs.append(Request(i, t, idx, int(rng.choice([1, 2, 4]))))
-    return reqs
+        out.append((float(t[i]), idx, int(rng.choice(steps))))
+    return out
 
 
 # ------------------------------------------------------------ ghost fills --

@@ -40,6 +40,7 @@ from typing import Callable, Optional
 
 import numpy as np
 
+from . import inputs
 from .inputs import FSTRIDE
 
 NF_MAX = 11
@@ -231,20 +232,15 @@ def summarize(records, cells_per_subgrid: int = 512) -> dict:
 
 
 def poisson_requests(n_requests: int, rate: float, catalogue_n: int, h, n_species,
-                     seed: int = 1005, max_n: int = 4096, median_n: int = 128,
+                     seed: int = 1005, max_n: int = 4096, median_n: float = 128.0,
                      sigma: float = 1.5, steps=(1, 2, 4)) -> list:
-    """Poisson arrivals at `rate` requests/s; sizes clip(round(lognormal)) in
-    [1, max_n] drawn without replacement from a catalogue of catalogue_n
-    subgrids; S uniform over `steps`."""
-    rng = np.random.default_rng(seed)
-    t = np.cumsum(rng.exponential(1.0 / rate, size=n_requests))
+    """Requests over a catalogue of catalogue_n subgrids (the seeded stream of
+    inputs.config5_requests) with their per-subgrid metadata."""
     out = []
-    for i in range(n_requests):
-        n = int(np.clip(np.round(np.exp(rng.normal(np.log(median_n), sigma))), 1,
-                        min(max_n, catalogue_n)))
-        idx = np.sort(rng.choice(catalogue_n, size=n, replace=False))
-        out.append(Request(i, idx, np.asarray(h)[idx], np.asarray(n_species)[idx],
-                           int(rng.choice(steps)), float(t[i])))
+    for i, (t, idx, S) in enumerate(inputs.config5_requests(
+            n_requests, rate, seed=seed, pool=catalogue_n, max_sub=max_n,
+            median_n=median_n, sigma=sigma, steps=steps)):
+        out.append(Request(i, idx, np.asarray(h)[idx], np.asarray(n_species)[idx], S, t))
     return out
 
 
