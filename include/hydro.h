@@ -186,6 +186,99 @@ int hydro_plan_set_dt(hydro_plan *plan, double dt);
 int hydro_plan_launch(hydro_plan *plan, void *stream);
 int hydro_plan_destroy(hydro_plan *plan);
 
+/* ---------------------------------------------------------------------------
+ * Device-resident time integration.  Sec. V: a time step of the paper's
+ * runs holds three hydro iterations (Test 2), and every step determines its
+ * step size and exchanges ghost cells (Test 1); ghost handling is a large
+ * part of the hydro time on a CPU (Test 3).  The calls below keep all of
+ * that on the device: ghost fill from neighbour interiors, a batch-wide CFL
+ * reduction that never returns to the host, and the SSP-RK3 combination.
+ */
+
+/*
+ * Ghost map of a batch: for subgrid s and neighbour direction slot
+ * n = 9(dz+1) + 3(dy+1) + (dx+1) (0..26; 13, the subgrid itself, is unused),
+ *   src[s*27 + n]  = batch index of the subgrid that holds the source cells of
+ *                    the ghosts of s in direction (dx,dy,dz);
+ *   mode[s*27 + n] = bit a (1 = x, 2 = y, 4 = z) set where axis a is a
+ *                    zero-gradient (outflow) boundary in that direction: the
+ *                    source index along a is the nearest interior cell (3 or
+ *                    10) of src; clear: the source is the interior cell 8
+ *                    cells back along a in src (i - 8*da), i.e. a neighbour or,
+ *                    with src = s, a periodic wrap onto itself.
+ * Both are device int32 arrays of n_sub*27 entries.
+ */
+typedef struct {
+    const int32_t *src;
+    const int32_t *mode;
+} hydro_ghost_map;
+
+/*
+ * hydro_fill_ghosts -- copies every ghost cell of every subgrid from the
+ * interior cell the map names (all fields of the subgrid).  Only interior
+ * cells are read and only ghost cells written, so U is updated in place.
+ * A map entry naming no valid subgrid, or a source with fewer fields, leaves
+ * those ghosts unchanged and sets HYDRO_STATUS_BADMETA in status[s] (status
+ * may be NULL; bits are ORed in).
+ */
+int hydro_fill_ghosts(const hydro_batch *batch, const hydro_ghost_map *map, double *U,
+                      int32_t *status, void *stream);
+
+/*
+ * hydro_rate -- the fused stage in rate form: writes R = L(U_in) =
+ * -(1/h)((dF_x + dF_y) + dF_z) on the interior of R (same layout as U_in;
+ * ghosts of R are not written), amax[s] as hydro_step, and ORs the status
+ * bits into status[s] (may be NULL).  params->dt is not used.  R must not
+ * alias U_in.
+ */
+int hydro_rate(const hydro_params *params, const hydro_batch *batch, const double *U_in,
+               double *R, double *amax, int32_t *status, void *stream);
+
+/*
+ * hydro_cfl_dt -- batch-wide step size on the device:
+ *     dt = cfl * min over s with amax[s] > 0 of h[s] / amax[s],
+ * cut to t_end - t so that the clock lands exactly on t_end (then t = t_end);
+ * dt = 0 once t >= t_end, or when no subgrid has a positive speed and t_end
+ * is infinite.  clock: device double[3] = {t, dt, n}, read and updated; n
+ * counts the calls that produced dt > 0.
+ */
+int hydro_cfl_dt(const hydro_batch *batch, const double *amax, double cfl, double t_end,
+                 double *clock, void *stream);
+
+/*
+ * hydro_rk_update -- one SSP-RK3 stage combination on the interior:
+ *     U_out = a U0 + b (Uk + dt R),  dt = clock[1],
+ * or U_out = U0 when dt == 0 (an empty step leaves the state unchanged).
+ * U_out may alias U0 or Uk (element-wise update); ghosts are not written.
+ */
+int hydro_rk_update(const hydro_batch *batch, double a, const double *U0, double b,
+                    const double *Uk, const double *R, const double *clock, double *U_out,
+                    void *stream);
+
+/*
+ * SSP-RK3 time steps captured in one hipGraph.  One replay is one step:
+ *   fill(U); R = L(U); clock <- CFL(amax); U1 = U + dt R;
+ *   fill(U1); R = L(U1); U2 = 3/4 U + 1/4 (U1 + dt R);
+ *   fill(U2); R = L(U2); U  = 1/3 U + 2/3 (U2 + dt R).
+ * U holds the state (its ghosts are refilled at the start of every step, so
+ * after the last step they hold the previous step's values); U1, U2 and R
+ * are work buffers with U's layout; amax [n_sub]; status [n_sub] collects
+ * the OR of every stage's bits (clear it before the first step); clock
+ * [3] = {t, dt, n} as for hydro_cfl_dt (set t and n before the first step).  Steps past t_end have
+ * dt = 0 and leave U unchanged.  The plan keeps every pointer (including
+ * batch and map arrays) until destroyed; their contents may change between
+ * replays.
+ */
+typedef struct hydro_rk3 hydro_rk3;
+
+int hydro_rk3_create(const hydro_params *params, const hydro_batch *batch,
+                     const hydro_ghost_map *map, double *U, double *U1, double *U2, double *R,
+                     double *amax, int32_t *status, double *clock, double cfl, double t_end,
+                     void *stream, hydro_rk3 **plan_out);
+/* Replays n_steps steps on `stream`. */
+int hydro_rk3_launch(hydro_rk3 *plan, int n_steps, void *stream);
+int hydro_rk3_destroy(hydro_rk3 *plan);
+
 #ifdef __cplusplus
 }
 #endif

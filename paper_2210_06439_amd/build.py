@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libhydro.so")
-SOURCES = ["api.hip", "plain.hip", "fused.hip"]
+SOURCES = ["api.hip", "plain.hip", "fused.hip", "evolve.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

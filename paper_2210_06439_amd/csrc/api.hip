@@ -41,10 +41,15 @@ int check_device() {
     return r;
 }
 
-int check_common(const hydro_params *p, const hydro_batch *b) {
-    if (!p || !b) return HYDRO_EINVAL;
+int check_batch(const hydro_batch *b) {
+    if (!b) return HYDRO_EINVAL;
     if (b->n_sub < 0 || b->fstride < NCELL || (b->fstride & 1)) return HYDRO_EINVAL;
     if (b->n_sub > 0 && (!b->offset || !b->h || !b->n_species)) return HYDRO_EINVAL;
+    return HYDRO_OK;
+}
+
+int check_common(const hydro_params *p, const hydro_batch *b) {
+    if (!p || check_batch(b)) return HYDRO_EINVAL;
     if (p->flags != 0) return HYDRO_EINVAL;
     return HYDRO_OK;
 }
@@ -105,6 +110,11 @@ struct hydro_plan {
     hipGraphNode_t node;
     hipGraphExec_t exec;
     hipKernelNodeParams np;
+};
+
+struct hydro_rk3 {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
 };
 
 extern "C" {
@@ -257,7 +267,7 @@ int hydro_plan_create(const hydro_params *params, const hydro_batch *batch, cons
     p->amax = amax;
     p->status = status;
     int variant = hydro_selected_variant(batch->n_sub, 5);
-    p->order = 0;
+    p->order = fused_variant_order(variant);
     p->kargs[0] = &p->args;
     p->kargs[1] = &p->U_in;
     p->kargs[2] = &p->U_out;
@@ -290,6 +300,155 @@ int hydro_plan_launch(hydro_plan *plan, void *stream) {
 }
 
 int hydro_plan_destroy(hydro_plan *plan) {
+    if (!plan) return HYDRO_EINVAL;
+    hipGraphExecDestroy(plan->exec);
+    hipGraphDestroy(plan->graph);
+    delete plan;
+    return HYDRO_OK;
+}
+
+// ---- device-resident time integration ---------------------------------------
+
+int hydro_fill_ghosts(const hydro_batch *batch, const hydro_ghost_map *map, double *U,
+                      int32_t *status, void *stream) {
+    int rc = check_batch(batch);
+    if (rc) return rc;
+    if (batch->n_sub == 0) return HYDRO_OK;
+    if (!map || !map->src || !map->mode || !U || !aligned8(U)) return HYDRO_EINVAL;
+    if ((rc = check_device())) return rc;
+    hipError_t e = launch_fill_ghosts(batch->n_sub, batch->fstride, batch->offset,
+                                      batch->n_species, map->src, map->mode, U, status,
+                                      static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HYDRO_OK : fail_hip(e);
+}
+
+int hydro_rate(const hydro_params *params, const hydro_batch *batch, const double *U_in,
+               double *R, double *amax, int32_t *status, void *stream) {
+    int rc = check_common(params, batch);
+    if (rc) return rc;
+    if (batch->n_sub == 0) return HYDRO_OK;
+    if (!U_in || !R || !amax || U_in == R || !aligned8(U_in) || !aligned8(R)) return HYDRO_EINVAL;
+    if ((rc = check_device())) return rc;
+    StepArgs a = make_args(params, batch);
+    a.rate = 1;
+    hipError_t e = launch_fused_step(a, U_in, R, amax, status,
+                                     hydro_selected_variant(batch->n_sub, 5),
+                                     static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HYDRO_OK : fail_hip(e);
+}
+
+int hydro_cfl_dt(const hydro_batch *batch, const double *amax, double cfl, double t_end,
+                 double *clock, void *stream) {
+    int rc = check_batch(batch);
+    if (rc) return rc;
+    if ((batch->n_sub > 0 && !amax) || !clock || !(cfl > 0.0)) return HYDRO_EINVAL;
+    if ((rc = check_device())) return rc;
+    hipError_t e = launch_cfl_dt(batch->n_sub, batch->h, amax, cfl, t_end, clock,
+                                 static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HYDRO_OK : fail_hip(e);
+}
+
+int hydro_rk_update(const hydro_batch *batch, double a, const double *U0, double b,
+                    const double *Uk, const double *R, const double *clock, double *U_out,
+                    void *stream) {
+    int rc = check_batch(batch);
+    if (rc) return rc;
+    if (batch->n_sub == 0) return HYDRO_OK;
+    if (!U0 || !Uk || !R || !clock || !U_out) return HYDRO_EINVAL;
+    if ((rc = check_device())) return rc;
+    hipError_t e = launch_rk_update(batch->n_sub, batch->fstride, batch->offset,
+                                    batch->n_species, a, U0, b, Uk, R, clock, U_out,
+                                    static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HYDRO_OK : fail_hip(e);
+}
+
+namespace {
+
+// One SSP-RK3 step, enqueued on `st` (recorded when st is capturing).
+hipError_t enqueue_rk3_step(const StepArgs &ra, int variant, const hydro_ghost_map *map,
+                            double *U, double *U1, double *U2, double *R, double *amax,
+                            int32_t *status, double *clock, double cfl, double t_end,
+                            hipStream_t st) {
+    const int n = ra.n_sub, fs = ra.fstride;
+    hipError_t e;
+    auto fill = [&](double *X) {
+        return launch_fill_ghosts(n, fs, ra.offset, ra.n_species, map->src, map->mode, X,
+                                  status, st);
+    };
+    if ((e = fill(U))) return e;
+    if ((e = launch_fused_step(ra, U, R, amax, status, variant, st))) return e;
+    if ((e = launch_cfl_dt(n, ra.h, amax, cfl, t_end, clock, st))) return e;
+    if ((e = launch_rk_update(n, fs, ra.offset, ra.n_species, 0.0, U, 1.0, U, R, clock, U1, st)))
+        return e;
+    if ((e = fill(U1))) return e;
+    if ((e = launch_fused_step(ra, U1, R, amax, status, variant, st))) return e;
+    if ((e = launch_rk_update(n, fs, ra.offset, ra.n_species, 0.75, U, 0.25, U1, R, clock, U2,
+                              st)))
+        return e;
+    if ((e = fill(U2))) return e;
+    if ((e = launch_fused_step(ra, U2, R, amax, status, variant, st))) return e;
+    return launch_rk_update(n, fs, ra.offset, ra.n_species, 1.0 / 3.0, U, 2.0 / 3.0, U2, R, clock,
+                            U, st);
+}
+
+}  // namespace
+
+int hydro_rk3_create(const hydro_params *params, const hydro_batch *batch,
+                     const hydro_ghost_map *map, double *U, double *U1, double *U2, double *R,
+                     double *amax, int32_t *status, double *clock, double cfl, double t_end,
+                     void *stream, hydro_rk3 **plan_out) {
+    (void)stream;
+    int rc = check_common(params, batch);
+    if (rc) return rc;
+    if (!plan_out || batch->n_sub == 0 || !map || !map->src || !map->mode || !U || !U1 || !U2 ||
+        !R || !amax || !clock || !(cfl > 0.0))
+        return HYDRO_EINVAL;
+    const double *bufs[4] = {U, U1, U2, R};
+    for (int i = 0; i < 4; i++) {
+        if (!aligned8(bufs[i])) return HYDRO_EINVAL;
+        for (int j = 0; j < i; j++)
+            if (bufs[i] == bufs[j]) return HYDRO_EINVAL;
+    }
+    if ((rc = check_device())) return rc;
+    StepArgs ra = make_args(params, batch);
+    ra.rate = 1;
+    const int variant = hydro_selected_variant(batch->n_sub, 5);
+    hipStream_t cs;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail_hip(e);
+    hydro_rk3 *p = new (std::nothrow) hydro_rk3();
+    if (!p) {
+        hipStreamDestroy(cs);
+        return HYDRO_EINVAL;
+    }
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t e1 = enqueue_rk3_step(ra, variant, map, U, U1, U2, R, amax, status, clock, cfl,
+                                         t_end, cs);
+        e = hipStreamEndCapture(cs, &p->graph);
+        if (e1 != hipSuccess) e = e1;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        if (p->graph) hipGraphDestroy(p->graph);
+        delete p;
+        return fail_hip(e);
+    }
+    *plan_out = p;
+    return HYDRO_OK;
+}
+
+int hydro_rk3_launch(hydro_rk3 *plan, int n_steps, void *stream) {
+    if (!plan || n_steps < 0) return HYDRO_EINVAL;
+    for (int i = 0; i < n_steps; i++) {
+        hipError_t e = hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) return fail_hip(e);
+    }
+    return HYDRO_OK;
+}
+
+int hydro_rk3_destroy(hydro_rk3 *plan) {
     if (!plan) return HYDRO_EINVAL;
     hipGraphExecDestroy(plan->exec);
     hipGraphDestroy(plan->graph);

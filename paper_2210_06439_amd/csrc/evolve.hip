@@ -1,0 +1,146 @@
+// evolve.hip -- device-resident time integration around the fused stage:
+// ghost fill from neighbour interiors, the batch-wide CFL step size, and the
+// SSP-RK3 stage combination.  Sec. V (Test 2): one time step holds three
+// hydro iterations; Test 1 names time-step size determination and ghost
+// exchange as part of every step; Test 3 finds ghost handling to be where
+// much of the hydro time goes on a CPU.
+#include "hydro_internal.hpp"
+
+namespace hydro {
+namespace {
+
+constexpr int NG = 3;   // ghost layers
+constexpr int NI = 8;   // interior cells per dimension
+
+// Source index along one axis of a ghost cell at index i (direction d):
+// inside the interior (d == 0) the index itself; toward a neighbour its
+// interior cell 8 cells back; at a clamped boundary the nearest interior cell.
+__device__ __forceinline__ int ghost_src(int i, int d, bool clamp) {
+    if (d == 0) return i;
+    if (clamp) return i < NG ? NG : NG + NI - 1;
+    return i - NI * d;
+}
+
+__device__ __forceinline__ int dir_of(int i) { return i < NG ? -1 : (i >= NG + NI ? 1 : 0); }
+
+// One block per (subgrid, field): every ghost cell of the field is copied
+// from the interior cell that the map names.  Only interior cells are read
+// and only ghost cells are written, so the fill is safe in place.
+__global__ __launch_bounds__(256) void k_fill_ghosts(int n_sub, int fstride,
+                                                     const int64_t *__restrict__ offset,
+                                                     const int32_t *__restrict__ n_species,
+                                                     const int32_t *__restrict__ src,
+                                                     const int32_t *__restrict__ mode,
+                                                     double *U, int32_t *status) {
+    const int s = blockIdx.x, f = blockIdx.y;
+    const int ns = n_species[s];
+    const int64_t off = offset[s];
+    if (ns < 0 || ns > 5 || off < 0 || f >= 6 + ns) return;
+    int bad = 0;
+    for (int c = threadIdx.x; c < NCELL; c += blockDim.x) {
+        const int i = c % NB, j = (c / NB) % NB, k = c / NPLANE;
+        const int dx = dir_of(i), dy = dir_of(j), dz = dir_of(k);
+        if ((dx | dy | dz) == 0) continue;
+        const int n = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1);
+        const int sb = src[s * 27 + n];
+        const int m = mode[s * 27 + n];
+        if (sb < 0 || sb >= n_sub) {
+            bad = 1;
+            continue;
+        }
+        const int ns2 = n_species[sb];
+        const int64_t off2 = offset[sb];
+        if (ns2 < 0 || ns2 > 5 || off2 < 0 || f >= 6 + ns2) {
+            bad = 1;
+            continue;
+        }
+        const int si = ghost_src(i, dx, m & 1), sj = ghost_src(j, dy, m & 2),
+                  sk = ghost_src(k, dz, m & 4);
+        U[off + (int64_t)f * fstride + c] =
+            U[off2 + (int64_t)f * fstride + (sk * NB + sj) * NB + si];
+    }
+    if (bad && status) atomicOr(&status[s], (int)HYDRO_STATUS_BADMETA);
+}
+
+// dt = cfl * min_s h_s / amax_s, cut so that the clock lands exactly on
+// t_end; clock = {t, dt, steps taken with dt > 0}.  One block.
+__global__ __launch_bounds__(1024) void k_cfl_dt(int n_sub, const double *__restrict__ h,
+                                                 const double *__restrict__ amax, double cfl,
+                                                 double t_end, double *clock) {
+    __shared__ double red[16];
+    double m = INFINITY;
+    for (int s = threadIdx.x; s < n_sub; s += blockDim.x) {
+        const double a = amax[s];
+        if (a > 0.0) m = fmin(m, h[s] / a);
+    }
+    for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); w++) m = fmin(m, red[w]);
+        double t = clock[0];
+        const double rem = t_end - t;
+        double dt = cfl * m;
+        if (!(rem > 0.0)) {
+            dt = 0.0;
+        } else if (!(dt < rem)) {
+            dt = rem;
+            t = t_end;
+        } else {
+            t = t + dt;
+        }
+        if (!isfinite(dt)) dt = 0.0;
+        clock[0] = t;
+        clock[1] = dt;
+        if (dt > 0.0) clock[2] += 1.0;
+    }
+}
+
+// U_out = a U0 + b (Uk + dt R) on the interior, dt = clock[1]; with dt == 0
+// the stage is the identity (U_out = U0), which makes a whole step a no-op.
+__global__ __launch_bounds__(512) void k_rk_update(int fstride, const int64_t *__restrict__ offset,
+                                                   const int32_t *__restrict__ n_species,
+                                                   double a, const double *U0, double b,
+                                                   const double *Uk, const double *R,
+                                                   const double *__restrict__ clock,
+                                                   double *Uo) {
+    const int s = blockIdx.x, f = blockIdx.y;
+    const int ns = n_species[s];
+    const int64_t off = offset[s];
+    if (ns < 0 || ns > 5 || off < 0 || f >= 6 + ns) return;
+    const int t = threadIdx.x;
+    const int i = NG + (t & 7), j = NG + ((t >> 3) & 7), k = NG + (t >> 6);
+    const int64_t idx = off + (int64_t)f * fstride + (k * NB + j) * NB + i;
+    const double dt = clock[1];
+    const double u0 = U0[idx];
+    Uo[idx] = dt == 0.0 ? u0 : a * u0 + b * (Uk[idx] + dt * R[idx]);
+}
+
+}  // namespace
+
+hipError_t launch_fill_ghosts(int n_sub, int fstride, const int64_t *offset,
+                              const int32_t *n_species, const int32_t *src, const int32_t *mode,
+                              double *U, int32_t *status, hipStream_t st) {
+    if (n_sub == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_ghosts, dim3(n_sub, NF_MAX), dim3(256), 0, st, n_sub, fstride,
+                       offset, n_species, src, mode, U, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_cfl_dt(int n_sub, const double *h, const double *amax, double cfl,
+                         double t_end, double *clock, hipStream_t st) {
+    hipLaunchKernelGGL(k_cfl_dt, dim3(1), dim3(1024), 0, st, n_sub, h, amax, cfl, t_end, clock);
+    return hipGetLastError();
+}
+
+hipError_t launch_rk_update(int n_sub, int fstride, const int64_t *offset,
+                            const int32_t *n_species, double a, const double *U0, double b,
+                            const double *Uk, const double *R, const double *clock, double *Uo,
+                            hipStream_t st) {
+    if (n_sub == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rk_update, dim3(n_sub, NF_MAX), dim3(512), 0, st, fstride, offset,
+                       n_species, a, U0, b, Uk, R, clock, Uo);
+    return hipGetLastError();
+}
+
+}  // namespace hydro

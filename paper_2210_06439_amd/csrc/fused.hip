@@ -385,10 +385,12 @@ __device__ __forceinline__ void combine_s(const double (&m)[NH], const double *o
 }
 
 // Update of one interior cell of plane `kc` from its z flux Fz and the kept
-// x/y difference: U_out = U - lam ((dFx + dFy) + dFz) for fields [f0, f1).
+// x/y difference: U_out = U - lam ((dFx + dFy) + dFz) for fields [f0, f1),
+// or, for the rate form, U_out = -lam ((dFx + dFy) + dFz) with lam = 1/h.
 __device__ __forceinline__ int update_cell(const double *win, const double *keep, int lane,
                                            int kc, int ci, int cj, int f0, int f1,
-                                           const double *Fz, double lam, double *Os, int fst) {
+                                           const double *Fz, double lam, bool rate, double *Os,
+                                           int fst) {
     int bits = 0;
     const int cidx = opaque_v(kc * NPLANE + cj * NB + ci);
     const int fs = opaque_s(fst);
@@ -398,7 +400,7 @@ __device__ __forceinline__ int update_cell(const double *win, const double *keep
             const double dfz = Fz[f] - keep[f * 64 + lane];
             const double sxy = keep[(NF_MAX + f) * 64 + lane];
             const double u = win[(kc % SLOTS) * SLOT_D + f * NPLANE + cj * NB + ci];
-            const double v = u - lam * (sxy + dfz);
+            const double v = (rate ? 0.0 : u) - lam * (sxy + dfz);
             if (!isfinite(v) || !isfinite(Fz[f])) bits |= HYDRO_STATUS_NONFINITE;
             Os[f * fs + cidx] = v;
         }
@@ -412,8 +414,8 @@ template <bool HYD>
 __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *zl, double *keep,
                                              double *run, int tid, int role, int nspec,
                                              const double *Us0, double *Os0, int fst0,
-                                             double lam, double gamma, double gm1, double de,
-                                             double &amax_l, int &bits) {
+                                             double lam, bool rate, double gamma, double gm1,
+                                             double de, double &amax_l, int &bits) {
     const int nf = 6 + nspec;
     const int f0 = HYD ? 0 : 6, f1 = HYD ? 6 : nf;     // this wave's fields
     // this thread's share of a plane: up to 5 of the nf*196 values.  Lanes
@@ -620,7 +622,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                                                       xch[ZB_OFF + 3 * 64 + lane]);
                         combine_s(acc[0], zl + lane, 64, false, sp, nspec, Fz);
                     }
-                    bits |= update_cell(win, keep, lane, 10, ci, cj, f0, f1, Fz, lam, Os, fst);
+                    bits |= update_cell(win, keep, lane, 10, ci, cj, f0, f1, Fz, lam, rate, Os, fst);
                 }
             }
             continue;
@@ -702,7 +704,8 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                                               xch[ZB_OFF + 128 + lane], xch[ZB_OFF + 192 + lane]);
                 combine_s(acc[1], zl + lane, 64, false, sp, nspec, Fz);
             }
-            if (k >= 4) bits |= update_cell(win, keep, lane, k - 1, ci, cj, f0, f1, Fz, lam, Os, fst);
+            if (k >= 4) bits |= update_cell(win, keep, lane, k - 1, ci, cj, f0, f1, Fz, lam, rate,
+                                            Os, fst);
 #pragma unroll
             for (int f = 0; f < NF_MAX; f++)
                 if (f >= f0 && f < f1) {
@@ -757,6 +760,7 @@ __global__ __launch_bounds__(NT, 2) void k_fused(StepArgs a, const double *__res
     const bool hyd = wave < 4;
 
     const double gamma = a.gamma, gm1 = a.gamma - 1.0, de = a.de_switch;
+    const bool rate = a.rate != 0;
 
     for (int it = blockIdx.x; it < a.n_sub; it += gridDim.x) {
         const int s = order ? (a.n_sub - 1 - it) : it;
@@ -765,11 +769,11 @@ __global__ __launch_bounds__(NT, 2) void k_fused(StepArgs a, const double *__res
         if (nspec < 0 || nspec > 5 || off < 0 || (off & 1)) {
             if (tid == 0) {
                 amax[s] = 0.0;
-                if (status) status[s] = HYDRO_STATUS_BADMETA;
+                if (status) status[s] = (rate ? status[s] : 0) | HYDRO_STATUS_BADMETA;
             }
             continue;
         }
-        const double lam = a.dt / a.h[s];
+        const double lam = rate ? 1.0 / a.h[s] : a.dt / a.h[s];
         const double *Us0 = U + off;
         double *Os0 = Uo + off;
         const int fst0 = a.fstride;
@@ -777,10 +781,10 @@ __global__ __launch_bounds__(NT, 2) void k_fused(StepArgs a, const double *__res
         int bits = 0;
 
         if (hyd)
-            subgrid_body<true>(win, xch, zl, keep, run, tid, role, nspec, Us0, Os0, fst0, lam,
+            subgrid_body<true>(win, xch, zl, keep, run, tid, role, nspec, Us0, Os0, fst0, lam, rate,
                                gamma, gm1, de, amax_l, bits);
         else
-            subgrid_body<false>(win, xch, zl, keep, run, tid, role, nspec, Us0, Os0, fst0, lam,
+            subgrid_body<false>(win, xch, zl, keep, run, tid, role, nspec, Us0, Os0, fst0, lam, rate,
                                 gamma, gm1, de, amax_l, bits);
 
         // ---- per-subgrid speed and status
@@ -802,7 +806,7 @@ __global__ __launch_bounds__(NT, 2) void k_fused(StepArgs a, const double *__res
             }
             if (!isfinite(m)) b |= HYDRO_STATUS_NONFINITE;
             amax[s] = m;
-            if (status) status[s] = b;
+            if (status) status[s] = rate ? (status[s] | b) : b;
         }
     }
 }
@@ -843,6 +847,9 @@ dim3 grid_of(const StepArgs &a, int v) {
 int fused_variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
 const char *fused_variant_name(int v) {
     return (v >= 0 && v < fused_variant_count()) ? kVariants[v].name : "?";
+}
+int fused_variant_order(int v) {
+    return (v >= 0 && v < fused_variant_count()) ? kVariants[v].order : 0;
 }
 
 hipError_t launch_fused_step(const StepArgs &a, const double *U_in, double *U_out,

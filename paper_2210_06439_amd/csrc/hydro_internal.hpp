@@ -29,6 +29,7 @@ struct StepArgs {
     const int64_t *offset;
     const double *h;
     const int32_t *n_species;
+    int32_t rate;   // 0: U_out = U + dt L(U); 1: U_out = L(U) on the interior
 };
 
 inline StepArgs make_args(const hydro_params *p, const hydro_batch *b) {
@@ -41,6 +42,7 @@ inline StepArgs make_args(const hydro_params *p, const hydro_batch *b) {
     a.offset = b->offset;
     a.h = b->h;
     a.n_species = b->n_species;
+    a.rate = 0;
     return a;
 }
 
@@ -58,6 +60,18 @@ int fused_variant_count();
 const char *fused_variant_name(int v);
 hipError_t launch_fused_step(const StepArgs &a, const double *U_in, double *U_out,
                              double *amax, int32_t *status, int variant, hipStream_t st);
+// Device-resident time integration (evolve.hip).
+hipError_t launch_fill_ghosts(int n_sub, int fstride, const int64_t *offset,
+                              const int32_t *n_species, const int32_t *src, const int32_t *mode,
+                              double *U, int32_t *status, hipStream_t st);
+hipError_t launch_cfl_dt(int n_sub, const double *h, const double *amax, double cfl,
+                         double t_end, double *clock, hipStream_t st);
+hipError_t launch_rk_update(int n_sub, int fstride, const int64_t *offset,
+                            const int32_t *n_species, double a, const double *U0, double b,
+                            const double *Uk, const double *R, const double *clock, double *Uo,
+                            hipStream_t st);
+int fused_variant_order(int v);
+
 // The kernel node's argument block, for in-place dt updates of a captured graph.
 hipError_t fused_kernel_node_params(const StepArgs &a, const double *U_in, double *U_out,
                                     double *amax, int32_t *status, int variant,

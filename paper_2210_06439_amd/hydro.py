@@ -20,6 +20,8 @@ EXPORTS = [
     "hydro_variant_count", "hydro_variant_name", "hydro_step_variant",
     "hydro_autotune", "hydro_selected_variant",
     "hydro_plan_create", "hydro_plan_set_dt", "hydro_plan_launch", "hydro_plan_destroy",
+    "hydro_fill_ghosts", "hydro_rate", "hydro_cfl_dt", "hydro_rk_update",
+    "hydro_rk3_create", "hydro_rk3_launch", "hydro_rk3_destroy",
 ]
 
 STATUS_RHO, STATUS_P, STATUS_NONFINITE, STATUS_BADMETA = 1, 2, 4, 8
@@ -38,6 +40,10 @@ class Batch(ctypes.Structure):
     _fields_ = [("n_sub", ctypes.c_int32), ("fstride", ctypes.c_int32),
                 ("offset", ctypes.c_void_p), ("h", ctypes.c_void_p),
                 ("n_species", ctypes.c_void_p)]
+
+
+class GhostMap(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_void_p), ("mode", ctypes.c_void_p)]
 
 
 _lib = None
@@ -72,6 +78,15 @@ def lib():
         L.hydro_plan_set_dt.argtypes = [vp, ctypes.c_double]
         L.hydro_plan_launch.argtypes = [vp, vp]
         L.hydro_plan_destroy.argtypes = [vp]
+        G, dbl = ctypes.POINTER(GhostMap), ctypes.c_double
+        L.hydro_fill_ghosts.argtypes = [B, G, vp, vp, vp]
+        L.hydro_rate.argtypes = [P, B, vp, vp, vp, vp, vp]
+        L.hydro_cfl_dt.argtypes = [B, vp, dbl, dbl, vp, vp]
+        L.hydro_rk_update.argtypes = [B, dbl, vp, dbl, vp, vp, vp, vp, vp]
+        L.hydro_rk3_create.argtypes = [P, B, G, vp, vp, vp, vp, vp, vp, vp, dbl, dbl, vp,
+                                       ctypes.POINTER(vp)]
+        L.hydro_rk3_launch.argtypes = [vp, ctypes.c_int, vp]
+        L.hydro_rk3_destroy.argtypes = [vp]
         _lib = L
         del i32
     return _lib
@@ -215,6 +230,114 @@ class Plan:
     def close(self):
         if self._h:
             lib().hydro_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- device-resident time integration ----------------------------------------
+
+def box_ghost_map(nx: int, ny: int, nz: int, periodic=(True, True, True)):
+    """Ghost map (src, mode), int32 [n*27] each, of an nx x ny x nz box of
+    subgrids numbered s = (kz*ny + ky)*nx + kx.  Along an axis that is not
+    periodic, directions that leave the box are zero-gradient (outflow)."""
+    n = nx * ny * nz
+    src = np.zeros((n, 27), dtype=np.int32)
+    mode = np.zeros((n, 27), dtype=np.int32)
+    dims = (nx, ny, nz)
+    for s in range(n):
+        kx, ky, kz = s % nx, (s // nx) % ny, s // (nx * ny)
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    slot = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1)
+                    pos, m = [], 0
+                    for a, (k, d) in enumerate(((kx, dx), (ky, dy), (kz, dz))):
+                        t = k + d
+                        if 0 <= t < dims[a]:
+                            pos.append(t)
+                        elif periodic[a]:
+                            pos.append(t % dims[a])
+                        else:
+                            pos.append(k)
+                            m |= 1 << a
+                    src[s, slot] = (pos[2] * ny + pos[1]) * nx + pos[0]
+                    mode[s, slot] = m
+    return src.reshape(-1), mode.reshape(-1)
+
+
+class DeviceGhostMap:
+    def __init__(self, src, mode):
+        import torch
+        self.src = torch.as_tensor(np.asarray(src, dtype=np.int32)).cuda()
+        self.mode = torch.as_tensor(np.asarray(mode, dtype=np.int32)).cuda()
+        self.struct = GhostMap(self.src.data_ptr(), self.mode.data_ptr())
+
+
+def fill_ghosts(batch: Batch, gmap: DeviceGhostMap, U, status=None, stream=None):
+    check(lib().hydro_fill_ghosts(ctypes.byref(batch), ctypes.byref(gmap.struct), _ptr(U),
+                                  _ptr(status), _stream(stream)))
+
+
+def rate(prm: Params, batch: Batch, U_in, R, amax, status=None, stream=None):
+    check(lib().hydro_rate(ctypes.byref(prm), ctypes.byref(batch), _ptr(U_in), _ptr(R),
+                           _ptr(amax), _ptr(status), _stream(stream)))
+
+
+def cfl_dt(batch: Batch, amax, cfl, t_end, clock, stream=None):
+    check(lib().hydro_cfl_dt(ctypes.byref(batch), _ptr(amax), float(cfl), float(t_end),
+                             _ptr(clock), _stream(stream)))
+
+
+def rk_update(batch: Batch, a, U0, b, Uk, R, clock, U_out, stream=None):
+    check(lib().hydro_rk_update(ctypes.byref(batch), float(a), _ptr(U0), float(b), _ptr(Uk),
+                                _ptr(R), _ptr(clock), _ptr(U_out), _stream(stream)))
+
+
+class RK3:
+    """SSP-RK3 steps with device ghost fill and device CFL, one hipGraph per
+    step.  Owns the work buffers, amax, status and the clock {t, dt}."""
+
+    def __init__(self, prm: Params, db: "DeviceBatch", gmap: DeviceGhostMap, U, cfl=0.4,
+                 t_end=float("inf"), stream=None):
+        import torch
+        self.db, self.gmap, self.U = db, gmap, U
+        self.U1 = torch.zeros_like(U)
+        self.U2 = torch.zeros_like(U)
+        self.R = torch.zeros_like(U)
+        self.amax = torch.zeros(db.n_sub, dtype=torch.float64, device=U.device)
+        self.status = torch.zeros(db.n_sub, dtype=torch.int32, device=U.device)
+        self.clock = torch.zeros(3, dtype=torch.float64, device=U.device)
+        self._h = ctypes.c_void_p()
+        check(lib().hydro_rk3_create(ctypes.byref(prm), ctypes.byref(db.struct),
+                                     ctypes.byref(gmap.struct), _ptr(U), _ptr(self.U1),
+                                     _ptr(self.U2), _ptr(self.R), _ptr(self.amax),
+                                     _ptr(self.status), _ptr(self.clock), float(cfl),
+                                     float(t_end), _stream(stream), ctypes.byref(self._h)))
+
+    def launch(self, n_steps=1, stream=None):
+        check(lib().hydro_rk3_launch(self._h, int(n_steps), _stream(stream)))
+
+    def run_to_end(self, chunk=16, max_launches=1_000_000, stream=None):
+        """Replay until a step finds the clock at t_end (checked every `chunk`
+        replays); returns the number of steps that advanced time."""
+        import torch
+        launched = 0
+        while launched < max_launches:
+            self.launch(chunk, stream)
+            launched += chunk
+            torch.cuda.synchronize()
+            if self.clock[1].item() == 0.0:
+                break
+        return int(self.clock[2].item())
+
+    def close(self):
+        if self._h:
+            lib().hydro_rk3_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -13,14 +13,19 @@ from paper_2210_06439_amd import inputs
 
 
 def rk3_evolve(batch, step, t_end, refill, C=0.4, max_steps=100000):
+    """SSP-RK3 to t_end; the last step is cut to land exactly on t_end."""
     U = batch.U.copy()
     refill(U)
     t = 0.0
     nsteps = 0
-    while t < t_end - 1e-15 and nsteps < max_steps:
+    while t < t_end and nsteps < max_steps:
         _, amax = step(U, 0.0)
         dt = C * float(np.min(batch.h / amax))
-        dt = min(dt, t_end - t)
+        if dt < t_end - t:
+            t_next = t + dt
+        else:
+            dt = t_end - t
+            t_next = t_end
         U1, _ = step(U, dt)
         refill(U1)
         S1, _ = step(U1, dt)
@@ -29,7 +34,7 @@ def rk3_evolve(batch, step, t_end, refill, C=0.4, max_steps=100000):
         S2, _ = step(U2, dt)
         U = (1.0 / 3.0) * U + (2.0 / 3.0) * S2
         refill(U)
-        t += dt
+        t = t_next
         nsteps += 1
     return U, nsteps
 
