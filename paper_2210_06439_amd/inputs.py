@@ -339,6 +339,39 @@ def config5_requests(n_requests: int, rate: float, seed: int = 1005, pool: int =
     return out
 
 
+# ------------------------------------------------------------- Sedov blast --
+
+def sedov(N: int = 64, E0: float = 1.0, r0_cells: float = 3.5, p_amb: float = 1e-5,
+          n_species: int = 0) -> SubgridBatch:
+    """Point blast in the periodic unit box (N = 64: 512 subgrids, the
+    paper's hydro-only blast-wave grid): rho = 1, v = 0, pressure p_amb, plus
+    the energy E0 spread evenly as internal energy over the cells whose
+    centres lie within r0_cells cells of the box centre (a cell corner).
+    Species, if any, are fixed fractions (0.3, 0.25, 0.2, 0.15, 0.1) of rho.
+    The batch's dt is left 0: the step size comes from the CFL condition."""
+    h = 1.0 / N
+    c = (np.arange(N) + 0.5) * h - 0.5
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    hot = (X * X + Y * Y + Z * Z) <= (r0_cells * h) ** 2
+    n_hot = int(np.count_nonzero(hot))
+    eint = np.where(hot, E0 / (n_hot * h ** 3), 0.0) + p_amb / (GAMMA - 1.0)
+    rho = np.ones_like(X)
+    p = (GAMMA - 1.0) * eint
+    zero = np.zeros_like(rho)
+    frac = (0.3, 0.25, 0.2, 0.15, 0.1)
+    species = [frac[k] * rho for k in range(n_species)]
+    G = periodic_extend(conserved_from_primitive(rho, zero, zero, zero, p, species))
+    return _subgrids_from_global(G, N // NI, h, 0.0, f"sedov{N}")
+
+
+def sedov_energy(batch: SubgridBatch, U: np.ndarray | None = None) -> float:
+    """Total energy sum(E) h^3 over the interiors."""
+    tot = 0.0
+    for s in range(batch.n_sub):
+        tot += float(np.sum(batch.interior(s, U)[4])) * float(batch.h[s]) ** 3
+    return tot
+
+
 # ------------------------------------------------------------ ghost fills --
 
 def fill_ghosts_periodic_chain(batch: SubgridBatch, U: np.ndarray, axis: int,
