@@ -188,6 +188,31 @@ def serving_run(torch, hydro, serving, b, db, peak_subgrids_per_s, n_requests, b
     return out
 
 
+def rk3_timing(torch, hydro, db, n_per_dim, periodic, steps):
+    """Device-resident SSP-RK3 time steps: three fused stages in rate form,
+    three ghost fills from the neighbour map, the on-device CFL step size and
+    three stage combinations, replayed as one hipGraph per time step."""
+    gm = hydro.DeviceGhostMap(*hydro.box_ghost_map(*n_per_dim, periodic=periodic))
+    rk = hydro.RK3(hydro.params(), db, gm, db.U, cfl=0.4)
+    rk.launch(2)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    rk.launch(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    st = int(rk.status.any().item())
+    t_sim = float(rk.clock[0].item())
+    rk.close()
+    cells = db.n_sub * 512
+    return {"ms_per_time_step": ms, "stages_per_step": 3,
+            "stage_cell_updates_per_s": 3 * cells / (ms * 1e-3),
+            "time_steps_per_s": 1e3 / ms, "simulated_time": t_sim,
+            "nonzero_status": st}
+
+
 def cpu_baseline(b, seconds):
     """The oracle, single-threaded, on evenly spaced subgrids of the workload."""
     import oracle
@@ -217,6 +242,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-rk3", action="store_true")
+    ap.add_argument("--rk3-steps", type=int, default=10)
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-budget-gb", type=float, default=64.0)
     ap.add_argument("--traffic-probe", action="store_true",
@@ -300,6 +327,19 @@ def main():
     if not args.no_serving:
         result["serving"] = serving_run(torch, hydro, serving, b, db, b.n_sub / (kern_ms * 1e-3),
                                         args.serving_requests, args.serving_budget_gb)
+    if not args.no_rk3:
+        # config 3's mesh with outflow boundaries (evolves db.U in place)
+        result["rk3_binary_star"] = rk3_timing(torch, hydro, db, (16, 16, 16),
+                                               (False, False, False), args.rk3_steps)
+        log(f"rk3 128^3 binary star: {result['rk3_binary_star']['ms_per_time_step']:.3f} ms "
+            f"per time step")
+        sb = inputs.sedov(64)
+        sdb = hydro.DeviceBatch.from_inputs(sb)
+        result["rk3_sedov"] = rk3_timing(torch, hydro, sdb, (8, 8, 8), (True, True, True),
+                                         args.rk3_steps)
+        result["rk3_sedov"]["workload"] = "64^3 Sedov blast, 512 subgrids, 6 fields, periodic"
+        log(f"rk3 64^3 sedov: {result['rk3_sedov']['ms_per_time_step']:.3f} ms per time step")
+        del sdb
     del db
     torch.cuda.empty_cache()
     if not args.no_plain:
