@@ -64,17 +64,29 @@ __device__ __host__ constexpr int ldx(int L) { return (14 + L) % 3 - 1; }
 __device__ __host__ constexpr int ldy(int L) { return ((14 + L) / 3) % 3 - 1; }
 __device__ __host__ constexpr int ldz(int L) { return (14 + L) / 9 - 1; }
 
-// Lines produced by role w in round r (-1: idle).  Every line's support
-// contains its producer's axis; x: X, (1,1,0), (1,0,1), (1,1,1);
-// y: Y, (-1,1,0), (0,1,1), (-1,1,1); z: Z, (-1,0,1), (0,-1,1), (1,-1,1), (-1,-1,1).
+// Lines produced by role w in round r (-1: idle).  Each round's lines cross
+// every axis at most twice, so no face owner consumes more than two lines per
+// round: rounds 0-1 hold the four body diagonals, rounds 2-3 one face
+// diagonal of each plane, round 4 the three axes.
 __device__ __host__ constexpr int line_of(int w, int r) {
-    return w == 0 ? (r == 0 ? 0 : r == 1 ? 3 : r == 2 ? 9 : r == 3 ? 12 : -1)
-         : w == 1 ? (r == 0 ? 2 : r == 1 ? 1 : r == 2 ? 11 : r == 3 ? 10 : -1)
-                  : (r == 0 ? 8 : r == 1 ? 7 : r == 2 ? 5 : r == 3 ? 6 : 4);
+    return w == 0 ? (r == 0 ? 12 : r == 1 ? -1 : r == 2 ? 1 : r == 3 ? 3 : 0)
+         : w == 1 ? (r == 0 ? 10 : r == 1 ? 6 : r == 2 ? 7 : r == 3 ? 9 : 2)
+                  : (r == 0 ? -1 : r == 1 ? 4 : r == 2 ? 5 : r == 3 ? 11 : 8);
 }
 
 __device__ __forceinline__ int comp(int L, int axis) {
     return axis == 0 ? ldx(L) : axis == 1 ? ldy(L) : ldz(L);
+}
+
+// Producer of the j-th line that crosses the faces of axis ax in round r
+// (round 4 has one such line; j = 1 repeats it).
+__device__ __host__ constexpr int cons_producer(int ax, int r, int j) {
+    return r == 4 ? ax
+         : r == 1 ? 1 + j
+         : r == 0 ? j
+         : ax == 0 ? j
+         : ax == 1 ? 2 * j
+                   : 1 + j;
 }
 
 // Simpson weight of a surface point from its two tangential offsets.
@@ -151,7 +163,7 @@ __device__ __forceinline__ T opaque_v(T v) {
 // cell rc = lane/2 (x-ring for rc < 16, else y-ring; low or high side).
 #define LANE_GEOMETRY()                                                          \
     const int lane = opaque_v((int)threadIdx.x) & 63;                            \
-    const int ci = 3 + (lane & 7), cj = 3 + (lane >> 3);                         \
+    const int ci = 3 + (lane & 7), cj = 3 + ((((lane >> 3) & 1) << 2) | (lane >> 4)); \
     const int half = lane & 1;                                                   \
     const int r_axis = (lane >> 1) >> 4, r_side = ((lane >> 1) >> 3) & 1;        \
     const int r_pos = 3 + ((lane >> 1) & 7);                                     \
@@ -459,80 +471,35 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
         acc_zero(acc[0], HYD);
         acc_zero(acc[1], HYD);
 
-        // ---- rounds of line production and consumption.  Interior planes:
-        // 5 rounds (roles 0-2 produce their lines for the interior cells,
-        // role 3 the ring cells' lines).  Face layers k = 2 and 11: 3 rounds,
-        // every role produces one of the 9 points of the boundary z-face of
-        // the interior cells of the plane; role 2 consumes them.
+        // ---- rounds of line production and consumption.  Face layers k = 2
+        // and 11: 3 rounds, every role produces one of the 9 points of the
+        // boundary z-face of the interior cells of the plane and role 2
+        // consumes them.  Interior planes: 5 rounds; roles 0-2 produce their
+        // lines for the interior cells and consume the two lines of the round
+        // that cross their faces, role 3 works on the ring cells.  Each kind
+        // of wave runs its own loop (same barrier count), so the
+        // accumulators never pass through a control-flow merge.
         const bool layer = (k == 2 || k == 11);
-        const int nrounds = layer ? 3 : 5;
-        const bool ring = !layer && role == 3;
+        if (layer) {
 #pragma unroll 1
-        for (int r = 0; r < nrounds; r++) {
-            LANE_GEOMETRY();
-            int t = -1, L = -1, dx = 0, dy = 0, dz = 0, pi = ci, pj = cj;
-            bool active;
-            if (layer) {
-                t = role + 4 * r;
-                active = t < 9;
-                dx = t % 3 - 1;
-                dy = t / 3 - 1;
-                dz = k == 2 ? 1 : -1;
-            } else if (role < 3) {
-                L = line_of(role, r);
-                active = L >= 0;
-                dx = ldx(L);
-                dy = ldy(L);
-                dz = ldz(L);
-            } else {
-                t = half ? 5 + r : r;
-                active = t < 9;
-                const int dn = r_side ? -1 : 1;    // normal component
-                dx = r_axis == 0 ? dn : t % 3 - 1;
-                dy = r_axis == 0 ? t % 3 - 1 : dn;
-                dz = t / 3 - 1;
-                pi = ri;
-                pj = rj;
-            }
-            const bool both = !layer && role < 3;
-            double *pp = xch + (layer ? role * PT * 64 : (role * 2 + 0) * PT * 64) + lane;
-            double *pm = xch + (layer ? role * PT * 64 : (role * 2 + 1) * PT * 64) + lane;
-            if (active) {
-                const Line5 l = line5(pi, pj, k, dx, dy, dz);
-                if (HYD) {
-                    PlusState ps;
-                    if (ring)
-                        ps = produce_hydro<false, false>(win, l, pp, pm, gamma, gm1, de, bits);
-                    else if (layer)
-                        ps = produce_hydro<true, false>(win, l, pp, pm, gamma, gm1, de, bits);
-                    else
-                        ps = produce_hydro<true, true>(win, l, pp, pm, gamma, gm1, de, bits);
-                    if (ring) {
-                        const double vx = ps.vx, vy = ps.vy;
-                        const double un = r_axis == 0 ? vx : vy;
-                        acc_h_vals(acc[0], ps.q, un, ps.p, ps.cs,
-                                   simpson_w(t % 3 - 1, t / 3 - 1));
-                        run[lane] = un;
-                    }
-                } else {
-                    // all 5 species slots (see acc_s_lds); none at all without species
-                    if (nspec > 0) {
+            for (int r = 0; r < 3; r++) {
+                LANE_GEOMETRY();
+                const int t = role + 4 * r;
+                double *pp = xch + role * PT * 64 + lane;
+                if (t < 9) {
+                    const Line5 l = line5(ci, cj, k, t % 3 - 1, t / 3 - 1, k == 2 ? 1 : -1);
+                    if (HYD) {
+                        produce_hydro<true, false>(win, l, pp, pp, gamma, gm1, de, bits);
+                    } else if (nspec > 0) {
 #pragma unroll
                         for (int f = 6; f < NF_MAX; f++) {
                             double qp, qm;
                             ppm_at(win, l, f, qp, qm);
-                            if (ring) {
-                                run[(f - 5) * 64 + lane] = qp;
-                            } else {
-                                pp[f * 64] = qp;
-                                if (both) pm[f * 64] = qm;
-                            }
+                            pp[f * 64] = qp;
                         }
                     }
                 }
-            }
-            lds_barrier();
-            if (layer) {
+                lds_barrier();
                 if (role == 2) {
 #pragma unroll
                     for (int w = 0; w < 4; w++) {
@@ -545,22 +512,44 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                         }
                     }
                 }
-            } else if (role < 3) {
-                const int ax = role;
-                const int b1 = ax == 0 ? 1 : 0, b2 = ax == 2 ? 1 : 2;
+                lds_barrier();
+            }
+        } else if (role < 3) {
+            const int ax = role;
+            const int b1 = ax == 0 ? 1 : 0, b2 = ax == 2 ? 1 : 2;
+#pragma unroll 1
+            for (int r = 0; r < 5; r++) {
+                LANE_GEOMETRY();
+                const int L = line_of(role, r);
+                double *pp = xch + (role * 2 + 0) * PT * 64 + lane;
+                double *pm = xch + (role * 2 + 1) * PT * 64 + lane;
+                if (L >= 0) {
+                    const Line5 l = line5(ci, cj, k, ldx(L), ldy(L), ldz(L));
+                    if (HYD) {
+                        produce_hydro<true, true>(win, l, pp, pm, gamma, gm1, de, bits);
+                    } else if (nspec > 0) {
 #pragma unroll
-                for (int p = 0; p < 3; p++) {
+                        for (int f = 6; f < NF_MAX; f++) {
+                            double qp, qm;
+                            ppm_at(win, l, f, qp, qm);
+                            pp[f * 64] = qp;
+                            pm[f * 64] = qm;
+                        }
+                    }
+                }
+                lds_barrier();
+                // the two lines of the round that cross my faces (one in the
+                // last round: the second repeats the first with weight 0,
+                // which leaves the sums and the speed extrema unchanged)
+#pragma unroll
+                for (int j = 0; j < 2; j++) {
+                    const int p = cons_producer(ax, r, j);
                     const int Lp = line_of(p, r);
-                    if (Lp < 0) continue;
                     const int dA = comp(Lp, ax);
-                    if (dA == 0) continue;              // wave-uniform: line not on my faces
-                    // both points of the line lie on my faces: the one on the + face
-                    // goes to acc[0], the other to acc[1]; same tangential weight
-                    const double wt = simpson_w(comp(Lp, b1), comp(Lp, b2));
-                    const double *p0 = xch + (p * 2 + 0) * PT * 64 + lane;
-                    const double *p1 = xch + (p * 2 + 1) * PT * 64 + lane;
-                    const double *pa = dA > 0 ? p0 : p1;
-                    const double *pb = dA > 0 ? p1 : p0;
+                    const double wt = (r == 4 && j == 1) ? 0.0
+                                                         : simpson_w(comp(Lp, b1), comp(Lp, b2));
+                    const double *pa = xch + (p * 2 + (dA > 0 ? 0 : 1)) * PT * 64 + lane;
+                    const double *pb = xch + (p * 2 + (dA > 0 ? 1 : 0)) * PT * 64 + lane;
                     if (HYD) {
                         acc_h_lds(acc[0], pa, ax, wt);
                         acc_h_lds(acc[1], pb, ax, wt);
@@ -569,18 +558,49 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                         acc_s_lds(acc[1], pb, ax, wt);
                     }
                 }
-            } else if (!HYD && active) {
-                // ring species: the normal velocity came from the hydro wave
-                const double wt = simpson_w(t % 3 - 1, t / 3 - 1);
-                const double wun = wt * run[lane];
-#pragma unroll
-                for (int i = 0; i < 5; i++) {
-                    const double v = run[(1 + i) * 64 + lane];
-                    acc[0][i] = fma(wt, v, acc[0][i]);
-                    acc[0][5 + i] = fma(wun, v, acc[0][5 + i]);
-                }
+                lds_barrier();
             }
-            lds_barrier();
+        } else {
+#pragma unroll 1
+            for (int r = 0; r < 5; r++) {
+                LANE_GEOMETRY();
+                // ring cell: 9 points of its face to the interior over two lanes
+                // (t = 0..4 and 5..8; the second lane's last round repeats t = 8
+                // with weight 0)
+                const int t0 = half ? 5 + r : r;
+                const int t = t0 < 9 ? t0 : 8;
+                const double wt = t0 < 9 ? simpson_w(t % 3 - 1, t / 3 - 1) : 0.0;
+                const int dn = r_side ? -1 : 1;    // normal component
+                const int dx = r_axis == 0 ? dn : t % 3 - 1;
+                const int dy = r_axis == 0 ? t % 3 - 1 : dn;
+                const Line5 l = line5(ri, rj, k, dx, dy, t / 3 - 1);
+                if (HYD) {
+                    const PlusState ps =
+                        produce_hydro<false, false>(win, l, nullptr, nullptr, gamma, gm1, de, bits);
+                    const double un = r_axis == 0 ? ps.vx : ps.vy;
+                    acc_h_vals(acc[0], ps.q, un, ps.p, ps.cs, wt);
+                    run[lane] = un;
+                } else if (nspec > 0) {
+#pragma unroll
+                    for (int f = 6; f < NF_MAX; f++) {
+                        double qp, qm;
+                        ppm_at(win, l, f, qp, qm);
+                        run[(f - 5) * 64 + lane] = qp;
+                    }
+                }
+                lds_barrier();
+                if (!HYD) {
+                    // ring species: the normal velocity came from the hydro wave
+                    const double wun = wt * run[lane];
+#pragma unroll
+                    for (int i = 0; i < 5; i++) {
+                        const double v = run[(1 + i) * 64 + lane];
+                        acc[0][i] = fma(wt, v, acc[0][i]);
+                        acc[0][5 + i] = fma(wun, v, acc[0][5 + i]);
+                    }
+                }
+                lds_barrier();
+            }
         }
 
         // plane k-2 is no longer read: its slot takes plane k+3 (prefetched one

@@ -38,7 +38,10 @@ def test_uniform_state_stays_uniform():
     for s in range(2):
         got = b.interior(s, Ug)
         want = np.broadcast_to(V[:got.shape[0], None, None, None], got.shape)
-        assert np.max(np.abs(got - want) / np.abs(want)) <= 2e-16
+        # the oracle keeps a uniform state bitwise; the fused kernel adds the 9
+        # point terms of a ring or face-layer face side in another association
+        # than those of interior face sides, so it keeps it to a few ulp
+        assert np.max(np.abs(got - want) / np.abs(want)) <= 16 * 2.0 ** -53
     assert np.all(sg == 0)
 
 
