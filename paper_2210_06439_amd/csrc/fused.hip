@@ -10,12 +10,13 @@
 //     (density, momenta, energy, tau and the point states) and the "species"
 //     wave (the passive scalars).  Roles 0, 1, 2 own the x-, y- and z-faces
 //     of the 8x8 interior cells of plane k (lane = cell); the 13 PPM lines of
-//     a cell are split between them (4, 4 and 5 lines, each computed once),
-//     and every line's two surface points go through LDS to each role whose
-//     faces contain them.  Role 3 handles the 32 "ring" cells just outside
-//     the interior in x and y (2 lanes each), which only need the 9 points of
-//     the face they share with the interior.  The hydro and species waves of
-//     a role sit on the same SIMD, which keeps two waves per SIMD.
+//     a cell are produced once each over 5 rounds, and every line's two
+//     surface points go through LDS to each role whose faces contain them.
+//     The rounds are scheduled so that no owner consumes more than two lines
+//     per round.  Role 3 handles the 32 "ring" cells just outside the
+//     interior in x and y (2 lanes each), which only need the 9 points of the
+//     face they share with the interior.  The hydro and species waves of a
+//     role sit on the same SIMD, which keeps two waves per SIMD.
 //   * The flux of a face is linear in the Simpson-weighted point terms once
 //     its speeds a+, a- are known, so each side accumulates
 //         S_V = sum w V,  S_F = sum w F(V),  lambda+- = max/min u_n +- c
@@ -131,6 +132,45 @@ __device__ __forceinline__ void ppm_fast(double um2, double um1, double u0, doub
     qm = fma(-bn, sg, u0);
 }
 
+// 1/x from the hardware estimate and two Newton steps (each doubles the
+// number of correct bits; the result is within an ulp of the rounded quotient).
+__device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// tau^gamma for the dual-energy branch.  For the paper's gas, gamma = 5/3,
+// tau^(5/3) = tau * (tau * tau^(-1/3)) with y = tau^(-1/3) from Newton's
+// iteration for the inverse cube root, y <- y (4 - x y^3) / 3 (quadratic
+// convergence): the exponent is split off exactly (x = m 2^(3q)), a
+// single-precision estimate of m^(-1/3) (about 22 correct bits) is refined
+// twice in double precision.  The result is within 4 ulp of x^(5/3); it
+// differs from pow(x, 5/3 rounded to double) by the rounding of the
+// exponent, a relative 4e-17 |ln x|.  Other gamma, and tau that is not a
+// positive finite number, take the library pow.
+__device__ __forceinline__ double tau_pow(double x, double gamma) {
+    if (gamma == 5.0 / 3.0 && x > 0.0 && x < INFINITY) {
+        int e = __builtin_amdgcn_frexp_exp(x);        // x = m 2^e, m in [0.5, 1)
+        double m = __builtin_amdgcn_frexp_mant(x);
+        int q = (e >= 0 ? e : e - 2) / 3;              // floor(e / 3)
+        m = __builtin_amdgcn_ldexp(m, e - 3 * q);      // m in [0.5, 4)
+        const float mf = (float)m;
+        double y = (double)__builtin_amdgcn_exp2f(-0.333333333f * __builtin_amdgcn_logf(mf));
+        const double third = 1.0 / 3.0;
+#pragma unroll
+        for (int it = 0; it < 2; it++) {
+            const double y3 = (y * y) * y;
+            y = (y * third) * fma(-m, y3, 4.0);
+        }
+        y = __builtin_amdgcn_ldexp(y, -q);             // x^(-1/3)
+        return x * (x * y);
+    }
+    return pow(x, gamma);
+}
+
 // Workgroup barrier for LDS traffic only: waits for this wave's LDS accesses,
 // not for its global loads and stores (which never carry data between waves).
 __device__ __forceinline__ void lds_barrier() {
@@ -217,7 +257,7 @@ __device__ __forceinline__ PlusState produce_hydro(const double *win, const Line
     if (store) pp[0] = qp;
     if (both) pm[0] = qm;
     const double rhop = qp, rhom = qm;
-    const double rp = 1.0 / qp, rm = both ? 1.0 / qm : 1.0;
+    const double rp = recip(qp), rm = both ? recip(qm) : 1.0;
     ppm_at(win, l, 1, qp, qm);
     ps.q[1] = qp;
     if (store) pp[64] = qp;
@@ -248,7 +288,7 @@ __device__ __forceinline__ PlusState produce_hydro(const double *win, const Line
     if (store) pp[5 * 64] = qp;
     if (both) pm[5 * 64] = qm;
     double eip = fma(-0.5, ekp, Ep);
-    if (eip < de * Ep) eip = pow(qp, gamma);      // dual energy: tau^gamma
+    if (eip < de * Ep) eip = tau_pow(qp, gamma);      // dual energy: tau^gamma
     const double prp = gm1 * eip;
     const double csp = sqrt((gamma * prp) * rp);
     if (store) {
@@ -258,17 +298,18 @@ __device__ __forceinline__ PlusState produce_hydro(const double *win, const Line
         pp[P_P * 64] = prp;
         pp[P_CS * 64] = csp;
     }
-    bits |= (rhop <= 0.0 ? HYDRO_STATUS_RHO : 0) | (prp <= 0.0 ? HYDRO_STATUS_P : 0);
+    bits |= (__ballot(rhop <= 0.0) ? HYDRO_STATUS_RHO : 0) | (__ballot(prp <= 0.0) ? HYDRO_STATUS_P : 0);
     if (both) {
         double eim = fma(-0.5, ekm, Em);
-        if (eim < de * Em) eim = pow(qm, gamma);
+        if (eim < de * Em) eim = tau_pow(qm, gamma);
         const double prm = gm1 * eim;
         pm[P_VX * 64] = vxm;
         pm[(P_VX + 1) * 64] = vym;
         pm[(P_VX + 2) * 64] = vzm;
         pm[P_P * 64] = prm;
         pm[P_CS * 64] = sqrt((gamma * prm) * rm);
-        bits |= (rhom <= 0.0 ? HYDRO_STATUS_RHO : 0) | (prm <= 0.0 ? HYDRO_STATUS_P : 0);
+        bits |= (__ballot(rhom <= 0.0) ? HYDRO_STATUS_RHO : 0) |
+                (__ballot(prm <= 0.0) ? HYDRO_STATUS_P : 0);
     }
     ps.vx = vxp;
     ps.vy = vyp;
@@ -399,11 +440,11 @@ __device__ __forceinline__ void combine_s(const double (&m)[NH], const double *o
 // Update of one interior cell of plane `kc` from its z flux Fz and the kept
 // x/y difference: U_out = U - lam ((dFx + dFy) + dFz) for fields [f0, f1),
 // or, for the rate form, U_out = -lam ((dFx + dFy) + dFz) with lam = 1/h.
-__device__ __forceinline__ int update_cell(const double *win, const double *keep, int lane,
-                                           int kc, int ci, int cj, int f0, int f1,
-                                           const double *Fz, double lam, bool rate, double *Os,
-                                           int fst) {
-    int bits = 0;
+// chk collects 0 * v over the outputs: it stays 0 unless some v is not finite.
+__device__ __forceinline__ void update_cell(const double *win, const double *keep, int lane,
+                                            int kc, int ci, int cj, int f0, int f1,
+                                            const double *Fz, double lam, bool rate, double *Os,
+                                            int fst, double &chk) {
     const int cidx = opaque_v(kc * NPLANE + cj * NB + ci);
     const int fs = opaque_s(fst);
 #pragma unroll
@@ -413,10 +454,9 @@ __device__ __forceinline__ int update_cell(const double *win, const double *keep
             const double sxy = keep[(NF_MAX + f) * 64 + lane];
             const double u = win[(kc % SLOTS) * SLOT_D + f * NPLANE + cj * NB + ci];
             const double v = (rate ? 0.0 : u) - lam * (sxy + dfz);
-            if (!isfinite(v) || !isfinite(Fz[f])) bits |= HYDRO_STATUS_NONFINITE;
+            chk = fma(v, 0.0, chk);
             Os[f * fs + cidx] = v;
         }
-    return bits;
 }
 
 // The work of one subgrid for one field group (HYD: hydro fields and point
@@ -429,6 +469,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                                              double lam, bool rate, double gamma, double gm1,
                                              double de, double &amax_l, int &bits) {
     const int nf = 6 + nspec;
+    double chk = 0.0;
     const int f0 = HYD ? 0 : 6, f1 = HYD ? 6 : nf;     // this wave's fields
     // this thread's share of a plane: up to 5 of the nf*196 values.  Lanes
     // without an element load a valid address and store into the slot's
@@ -642,7 +683,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                                                       xch[ZB_OFF + 3 * 64 + lane]);
                         combine_s(acc[0], zl + lane, 64, false, sp, nspec, Fz);
                     }
-                    bits |= update_cell(win, keep, lane, 10, ci, cj, f0, f1, Fz, lam, rate, Os, fst);
+                    update_cell(win, keep, lane, 10, ci, cj, f0, f1, Fz, lam, rate, Os, fst, chk);
                 }
             }
             continue;
@@ -708,10 +749,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
             }
 #pragma unroll
             for (int f = 0; f < NF_MAX; f++)
-                if (f >= f0 && f < f1) {
-                    Fo[f * RST] = Fb[f];
-                    if (!isfinite(Fb[f])) bits |= HYDRO_STATUS_NONFINITE;
-                }
+                if (f >= f0 && f < f1) Fo[f * RST] = Fb[f];
         }
         if (role == 2) {
             // z-face (k-1|k): left partial from the previous step, right = acc[1]
@@ -724,14 +762,11 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                                               xch[ZB_OFF + 128 + lane], xch[ZB_OFF + 192 + lane]);
                 combine_s(acc[1], zl + lane, 64, false, sp, nspec, Fz);
             }
-            if (k >= 4) bits |= update_cell(win, keep, lane, k - 1, ci, cj, f0, f1, Fz, lam, rate,
-                                            Os, fst);
+            if (k >= 4) update_cell(win, keep, lane, k - 1, ci, cj, f0, f1, Fz, lam, rate, Os, fst,
+                                    chk);
 #pragma unroll
             for (int f = 0; f < NF_MAX; f++)
-                if (f >= f0 && f < f1) {
-                    if (!isfinite(Fz[f])) bits |= HYDRO_STATUS_NONFINITE;
-                    keep[f * 64 + lane] = Fz[f];
-                }
+                if (f >= f0 && f < f1) keep[f * 64 + lane] = Fz[f];
             if (HYD) store_h(zl + lane, 64, acc[0]);
             else store_s(zl + lane, 64, acc[0], nspec);
         }
@@ -757,6 +792,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
         // (the next step's window barrier orders these reads before XCH reuse)
         }
     }
+    if (chk != chk) bits |= HYDRO_STATUS_NONFINITE;
 
 }
 
