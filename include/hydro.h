@@ -54,12 +54,20 @@ enum {
 enum { HYDRO_STATUS_RHO = 1, HYDRO_STATUS_P = 2, HYDRO_STATUS_NONFINITE = 4,
        HYDRO_STATUS_BADMETA = 8 };
 
+/* hydro_params.flags bits.  HYDRO_FLAG_KT_SYMMETRIC: the Kurganov-Tadmor
+ * (2000) form of the central flux, one speed for both directions,
+ * a = max over the face's points and sides of |u_n| + c (a+ = a, a- = -a):
+ * the local Lax-Friedrichs flux.  Without it, the one-sided central-upwind
+ * speeds (Kurganov, Noelle, Petrova 2001).  The face speed max(a+, -a-) and
+ * hence amax are the same either way. */
+enum { HYDRO_FLAG_KT_SYMMETRIC = 1 };
+
 typedef struct {
     double gamma;      /* ratio of specific heats (5/3 for the paper's gas)       */
     double de_switch;  /* dual-energy switch eps: p from tau^gamma where the
                           internal energy E - |s|^2/(2 rho) is below eps * E      */
     double dt;         /* step size of the forward-Euler stage; 0 = speeds only   */
-    uint32_t flags;    /* reserved, must be 0                                      */
+    uint32_t flags;    /* HYDRO_FLAG_* bits; any other bit is HYDRO_EINVAL         */
 } hydro_params;
 
 typedef struct {
@@ -244,6 +252,17 @@ int hydro_rate(const hydro_params *params, const hydro_batch *batch, const doubl
  */
 int hydro_cfl_dt(const hydro_batch *batch, const double *amax, double cfl, double t_end,
                  double *clock, void *stream);
+
+/*
+ * hydro_tau_resync -- entropy-tracer re-synchronisation after a stage: in
+ * every interior cell where the internal energy from the total energy,
+ * e_i = E - |s|^2/(2 rho), is reliable (not below params->de_switch * E, the
+ * same switch as in the point state), tau is reset to e_i^(1/gamma); other
+ * cells and fields are left as they are.  U is updated in place; ghosts are
+ * not touched.  params->dt and params->flags are not used.
+ */
+int hydro_tau_resync(const hydro_params *params, const hydro_batch *batch, double *U,
+                     void *stream);
 
 /*
  * hydro_rk_update -- one SSP-RK3 stage combination on the interior:

@@ -66,13 +66,14 @@ def lib():
         L.hydro_ref_flux.argtypes = [P, B, dp, lp, dp, lp, dp, ip]
         L.hydro_ref_divergence.argtypes = [P, B, dp, lp, dp, dp]
         L.hydro_ref_step.argtypes = [P, B, dp, dp, dp, ip]
+        L.hydro_ref_tau_resync.argtypes = [P, B, dp]
         L.hydro_ref_q_elems.argtypes = [ctypes.c_int]
         L.hydro_ref_q_elems.restype = ctypes.c_int64
         L.hydro_ref_f_elems.argtypes = [ctypes.c_int]
         L.hydro_ref_f_elems.restype = ctypes.c_int64
         for name in ("hydro_ref_ppm1d", "hydro_ref_state_flux", "hydro_ref_face",
                      "hydro_ref_reconstruct", "hydro_ref_flux", "hydro_ref_divergence",
-                     "hydro_ref_step"):
+                     "hydro_ref_step", "hydro_ref_tau_resync"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -86,8 +87,11 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def params(gamma=5.0 / 3.0, de_switch=1e-3, dt=0.0):
-    return Params(float(gamma), float(de_switch), float(dt), 0)
+KT_SYMMETRIC = 1   # flags bit: one speed max(|u_n| + c) for both directions
+
+
+def params(gamma=5.0 / 3.0, de_switch=1e-3, dt=0.0, flags=0):
+    return Params(float(gamma), float(de_switch), float(dt), int(flags))
 
 
 class _BatchArgs:
@@ -129,7 +133,7 @@ def state_flux(V, axis, gamma=5.0 / 3.0, de_switch=1e-3):
     return F, un.value, cs.value, p.value, st.value
 
 
-def face(VL, VR, axis, gamma=5.0 / 3.0, de_switch=1e-3):
+def face(VL, VR, axis, gamma=5.0 / 3.0, de_switch=1e-3, flags=0):
     """Central-upwind Simpson-averaged flux of one face from [9][nf] states."""
     VL, VR = _f64(VL), _f64(VR)
     assert VL.shape == VR.shape and VL.shape[0] == 9
@@ -137,7 +141,7 @@ def face(VL, VR, axis, gamma=5.0 / 3.0, de_switch=1e-3):
     Fbar = np.zeros(nf)
     a = ctypes.c_double()
     st = ctypes.c_int32()
-    prm = params(gamma, de_switch)
+    prm = params(gamma, de_switch, flags=flags)
     rc = lib().hydro_ref_face(ctypes.byref(prm), nf, axis, _dp(VL), _dp(VR), _dp(Fbar),
                               ctypes.byref(a), ctypes.byref(st))
     assert rc == 0
@@ -173,7 +177,7 @@ def reconstruct(U, offset, h, n_species, fstride, gamma=5.0 / 3.0, de_switch=1e-
     return Q, q_off
 
 
-def flux(Q, q_offset, offset, h, n_species, fstride, gamma=5.0 / 3.0, de_switch=1e-3):
+def flux(Q, q_offset, offset, h, n_species, fstride, gamma=5.0 / 3.0, de_switch=1e-3, flags=0):
     """Face fluxes; returns (F, f_offset, amax, status)."""
     Q = _f64(Q)
     q_offset = np.ascontiguousarray(q_offset, dtype=np.int64)
@@ -183,7 +187,7 @@ def flux(Q, q_offset, offset, h, n_species, fstride, gamma=5.0 / 3.0, de_switch=
     F = np.zeros(total)
     amax = np.zeros(len(ba.offset))
     status = np.zeros(len(ba.offset), dtype=np.int32)
-    prm = params(gamma, de_switch)
+    prm = params(gamma, de_switch, flags=flags)
     rc = lib().hydro_ref_flux(ctypes.byref(prm), ctypes.byref(ba.struct), _dp(Q),
                               q_offset.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(F),
                               f_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(amax),
@@ -207,7 +211,7 @@ def divergence(F, f_offset, U_in, offset, h, n_species, fstride, dt,
     return U_out
 
 
-def step(U_in, offset, h, n_species, fstride, dt, gamma=5.0 / 3.0, de_switch=1e-3):
+def step(U_in, offset, h, n_species, fstride, dt, gamma=5.0 / 3.0, de_switch=1e-3, flags=0):
     """One forward-Euler hydro stage; returns (U_out, amax, status).
 
     Ghost cells of U_out are copies of U_in (the step never writes them)."""
@@ -217,12 +221,23 @@ def step(U_in, offset, h, n_species, fstride, dt, gamma=5.0 / 3.0, de_switch=1e-
     n = len(ba.offset)
     amax = np.zeros(n)
     status = np.zeros(n, dtype=np.int32)
-    prm = params(gamma, de_switch, dt)
+    prm = params(gamma, de_switch, dt, flags)
     rc = lib().hydro_ref_step(ctypes.byref(prm), ctypes.byref(ba.struct), _dp(U_in),
                               _dp(U_out), _dp(amax),
                               status.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
     assert rc == 0, rc
     return U_out, amax, status
+
+
+def tau_resync(U, offset, h, n_species, fstride, gamma=5.0 / 3.0, de_switch=1e-3):
+    """Copy of U with the entropy tracer of every interior cell reset to
+    e_i^(1/gamma) where e_i >= de_switch * E."""
+    U = _f64(U).copy()
+    ba = _BatchArgs(offset, h, n_species, fstride)
+    prm = params(gamma, de_switch)
+    rc = lib().hydro_ref_tau_resync(ctypes.byref(prm), ctypes.byref(ba.struct), _dp(U))
+    assert rc == 0, rc
+    return U
 
 
 def raw_call(name, *args):

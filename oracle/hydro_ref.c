@@ -26,6 +26,9 @@
  *       over the face's 9 surface points, integrated with the tensor
  *       Simpson (3-point closed Newton-Cotes) rule.
  *   O5  divergence and forward-Euler update of the 8^3 interior.
+ *   Options: the symmetric-speed (Kurganov-Tadmor 2000) flux, and the
+ *   re-synchronisation of the entropy tracer from the total energy after a
+ *   stage (both outside the paper's description; variants of the method).
  *
  * Floating point: IEEE binary64, compiled with -ffp-contract=off; every
  * operation is written in the order that is evaluated.
@@ -45,7 +48,7 @@ typedef struct {
     double gamma;      /* ratio of specific heats                             */
     double de_switch;  /* dual-energy switch: use tau^gamma if e_i < eps * E  */
     double dt;         /* time step of the forward-Euler stage                */
-    uint32_t flags;    /* reserved, must be 0                                 */
+    uint32_t flags;    /* bit 0: symmetric speeds (REF_FLAG_KT_SYMMETRIC)     */
 } hydro_ref_params;
 
 typedef struct {
@@ -57,6 +60,16 @@ typedef struct {
 } hydro_ref_batch;
 
 enum { REF_OK = 0, REF_EINVAL = -1 };
+
+/* Kurganov-Tadmor (2000) form of the central flux: one speed for both
+ * directions, a = max over the face's points and sides of |u_n| + c, i.e.
+ * a+ = a and a- = -a (the face flux becomes the local Lax-Friedrichs one). */
+enum { REF_FLAG_KT_SYMMETRIC = 1 };
+
+static int check_params(const hydro_ref_params *prm)
+{
+    return (prm && (prm->flags & ~(uint32_t)REF_FLAG_KT_SYMMETRIC) == 0) ? REF_OK : REF_EINVAL;
+}
 
 #define NB 14            /* cells per dimension incl. 3 ghost layers each side */
 #define NC (NB * NB * NB)
@@ -214,6 +227,11 @@ static int face_flux(const hydro_ref_params *prm, int nf, int axis,
     }
     double ap = fmax(0.0, lam_p);
     double am = fmin(0.0, lam_m);
+    if (prm->flags & REF_FLAG_KT_SYMMETRIC) {
+        double a = fmax(ap, -am);
+        ap = a;
+        am = -a;
+    }
     double inv = 1.0 / (ap - am);
     double apam = ap * am;
 
@@ -240,7 +258,8 @@ int hydro_ref_face(const hydro_ref_params *prm, int nf, int axis,
                    const double *VL, const double *VR, double *Fbar,
                    double *amax_face, int32_t *status)
 {
-    if (!prm || !VL || !VR || !Fbar || nf < 6 || nf > 11 || axis < 0 || axis > 2)
+    if (check_params(prm) != REF_OK || !VL || !VR || !Fbar || nf < 6 || nf > 11 || axis < 0 ||
+        axis > 2)
         return REF_EINVAL;
     double a = 0.0;
     int bits = face_flux(prm, nf, axis, VL, VR, Fbar, &a);
@@ -382,7 +401,7 @@ int64_t hydro_ref_f_elems(int n_species) { return (int64_t)3 * (6 + n_species) *
 int hydro_ref_reconstruct(const hydro_ref_params *prm, const hydro_ref_batch *b,
                           const double *U, double *Q, const int64_t *q_offset)
 {
-    if (!prm || check_batch(b) != REF_OK) return REF_EINVAL;
+    if (check_params(prm) != REF_OK || check_batch(b) != REF_OK) return REF_EINVAL;
     if (b->n_sub > 0 && (!U || !Q || !q_offset)) return REF_EINVAL;
     for (int s = 0; s < b->n_sub; s++)
         reconstruct_subgrid(U + b->offset[s], b->fstride, 6 + b->n_species[s],
@@ -394,7 +413,7 @@ int hydro_ref_flux(const hydro_ref_params *prm, const hydro_ref_batch *b,
                    const double *Q, const int64_t *q_offset, double *F,
                    const int64_t *f_offset, double *amax, int32_t *status)
 {
-    if (!prm || check_batch(b) != REF_OK) return REF_EINVAL;
+    if (check_params(prm) != REF_OK || check_batch(b) != REF_OK) return REF_EINVAL;
     if (b->n_sub > 0 && (!Q || !q_offset || !F || !f_offset || !amax)) return REF_EINVAL;
     for (int s = 0; s < b->n_sub; s++) {
         double a;
@@ -410,7 +429,7 @@ int hydro_ref_divergence(const hydro_ref_params *prm, const hydro_ref_batch *b,
                          const double *F, const int64_t *f_offset,
                          const double *U_in, double *U_out)
 {
-    if (!prm || check_batch(b) != REF_OK) return REF_EINVAL;
+    if (check_params(prm) != REF_OK || check_batch(b) != REF_OK) return REF_EINVAL;
     if (b->n_sub > 0 && (!F || !f_offset || !U_in || !U_out)) return REF_EINVAL;
     for (int s = 0; s < b->n_sub; s++)
         divergence_subgrid(F + f_offset[s], U_in + b->offset[s], U_out + b->offset[s],
@@ -421,7 +440,7 @@ int hydro_ref_divergence(const hydro_ref_params *prm, const hydro_ref_batch *b,
 int hydro_ref_step(const hydro_ref_params *prm, const hydro_ref_batch *b,
                    const double *U_in, double *U_out, double *amax, int32_t *status)
 {
-    if (!prm || check_batch(b) != REF_OK) return REF_EINVAL;
+    if (check_params(prm) != REF_OK || check_batch(b) != REF_OK) return REF_EINVAL;
     if (b->n_sub > 0 && (!U_in || !U_out || !amax)) return REF_EINVAL;
     double *Q = (double *)malloc(sizeof(double) * hydro_ref_q_elems(5));
     double *F = (double *)malloc(sizeof(double) * hydro_ref_f_elems(5));
@@ -439,5 +458,40 @@ int hydro_ref_step(const hydro_ref_params *prm, const hydro_ref_batch *b,
     }
     free(Q);
     free(F);
+    return REF_OK;
+}
+
+/* ---- entropy-tracer re-synchronisation (after a stage) ------------------------
+ *
+ * In a dual-energy scheme the entropy tracer tau stands in for the internal
+ * energy only where e_i = E - |s|^2/(2 rho) is unreliable (e_i < eps E, the
+ * same switch as in the point state); everywhere else tau is reset from the
+ * total energy so that the two stay consistent: tau = e_i^(1/gamma).  Interior
+ * cells only; U is updated in place.  Returns REF_OK or REF_EINVAL.
+ */
+int hydro_ref_tau_resync(const hydro_ref_params *prm, const hydro_ref_batch *b, double *U)
+{
+    if (check_params(prm) != REF_OK || check_batch(b) != REF_OK) return REF_EINVAL;
+    if (b->n_sub > 0 && !U) return REF_EINVAL;
+    for (int s = 0; s < b->n_sub; s++) {
+        double *Us = U + b->offset[s];
+        const int64_t fs = b->fstride;
+        for (int k = 3; k < 11; k++)
+            for (int j = 3; j < 11; j++)
+                for (int i = 3; i < 11; i++) {
+                    const int c = cell_index(i, j, k);
+                    const double rho = Us[F_RHO * fs + c];
+                    const double sx = Us[(F_SX + 0) * fs + c];
+                    const double sy = Us[(F_SX + 1) * fs + c];
+                    const double sz = Us[(F_SX + 2) * fs + c];
+                    const double E = Us[F_EGAS * fs + c];
+                    const double r = 1.0 / rho;
+                    const double vx = sx * r, vy = sy * r, vz = sz * r;
+                    const double ek = 0.5 * ((sx * vx + sy * vy) + sz * vz);
+                    const double ei = E - ek;
+                    if (!(ei < prm->de_switch * E))
+                        Us[F_TAU * fs + c] = pow(ei, 1.0 / prm->gamma);
+                }
+    }
     return REF_OK;
 }

@@ -50,7 +50,7 @@ int check_batch(const hydro_batch *b) {
 
 int check_common(const hydro_params *p, const hydro_batch *b) {
     if (!p || check_batch(b)) return HYDRO_EINVAL;
-    if (p->flags != 0) return HYDRO_EINVAL;
+    if (p->flags & ~(uint32_t)HYDRO_FLAG_KT_SYMMETRIC) return HYDRO_EINVAL;
     return HYDRO_OK;
 }
 
@@ -345,6 +345,17 @@ int hydro_cfl_dt(const hydro_batch *batch, const double *amax, double cfl, doubl
     if ((rc = check_device())) return rc;
     hipError_t e = launch_cfl_dt(batch->n_sub, batch->h, amax, cfl, t_end, clock,
                                  static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HYDRO_OK : fail_hip(e);
+}
+
+int hydro_tau_resync(const hydro_params *params, const hydro_batch *batch, double *U,
+                     void *stream) {
+    int rc = check_common(params, batch);
+    if (rc) return rc;
+    if (batch->n_sub == 0) return HYDRO_OK;
+    if (!U || !aligned8(U)) return HYDRO_EINVAL;
+    if ((rc = check_device())) return rc;
+    hipError_t e = launch_tau_resync(make_args(params, batch), U, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? HYDRO_OK : fail_hip(e);
 }
 

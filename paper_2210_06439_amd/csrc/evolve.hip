@@ -116,7 +116,35 @@ __global__ __launch_bounds__(512) void k_rk_update(int fstride, const int64_t *_
     Uo[idx] = dt == 0.0 ? u0 : a * u0 + b * (Uk[idx] + dt * R[idx]);
 }
 
+// Entropy-tracer re-synchronisation: tau = e_i^(1/gamma) where the internal
+// energy from E is reliable (e_i not below de_switch * E).  One block per
+// subgrid, a thread per interior cell; evaluated in the written order (no
+// contraction), so the switch decides exactly as in the point state.
+__global__ __launch_bounds__(512) void k_tau_resync(StepArgs a, double *U) {
+#pragma clang fp contract(off)
+    const int s = blockIdx.x;
+    const int ns = a.n_species[s];
+    const int64_t off = a.offset[s];
+    if (ns < 0 || ns > 5 || off < 0) return;
+    const int t = threadIdx.x;
+    const int i = NG + (t & 7), j = NG + ((t >> 3) & 7), k = NG + (t >> 6);
+    double *u = U + off + (k * NB + j) * NB + i;
+    const int64_t fs = a.fstride;
+    const double rho = u[0], sx = u[fs], sy = u[2 * fs], sz = u[3 * fs], E = u[4 * fs];
+    const double r = 1.0 / rho;
+    const double vx = sx * r, vy = sy * r, vz = sz * r;
+    const double ek = 0.5 * ((sx * vx + sy * vy) + sz * vz);
+    const double ei = E - ek;
+    if (!(ei < a.de_switch * E)) u[5 * fs] = pow(ei, 1.0 / a.gamma);
+}
+
 }  // namespace
+
+hipError_t launch_tau_resync(const StepArgs &a, double *U, hipStream_t st) {
+    if (a.n_sub == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tau_resync, dim3(a.n_sub), dim3(512), 0, st, a, U);
+    return hipGetLastError();
+}
 
 hipError_t launch_fill_ghosts(int n_sub, int fstride, const int64_t *offset,
                               const int32_t *n_species, const int32_t *src, const int32_t *mode,

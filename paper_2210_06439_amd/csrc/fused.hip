@@ -120,9 +120,8 @@ __device__ __forceinline__ void ppm_fast(double um2, double um1, double u0, doub
     double sm = mc_slope(d0, d1);
     double s0 = mc_slope(d1, d2);
     double sp = mc_slope(d2, d3);
-    double ip = fma(s0 - sp, sixth, 0.5 * (u0 + up1));
-    double im = fma(sm - s0, sixth, 0.5 * (um1 + u0));
-    double a = ip - u0, b = u0 - im;
+    double a = fma(s0 - sp, sixth, 0.5 * d2);    // q+ - u0
+    double b = fma(s0 - sm, sixth, 0.5 * d1);    // u0 - q-
     double sg = copysign(1.0, a);
     double aa = fabs(a);
     double sb = b * sg;                          // |b| if b has a's sign, else < 0
@@ -385,10 +384,16 @@ struct Speeds {
     double ap, am, inv, apam, amax_face;
 };
 
-__device__ __forceinline__ Speeds face_speeds(double lpL, double lmL, double lpR, double lmR) {
+__device__ __forceinline__ Speeds face_speeds(double lpL, double lmL, double lpR, double lmR,
+                                              bool sym) {
     Speeds s;
     s.ap = fmax(0.0, fmax(lpL, lpR));
     s.am = fmin(0.0, fmin(lmL, lmR));
+    if (sym) {   // one speed for both directions
+        const double a = fmax(s.ap, -s.am);
+        s.ap = a;
+        s.am = -a;
+    }
     s.inv = 1.0 / (s.ap - s.am);
     s.apam = s.ap * s.am;
     s.amax_face = fmax(s.ap, -s.am);
@@ -398,9 +403,10 @@ __device__ __forceinline__ Speeds face_speeds(double lpL, double lmL, double lpR
 // Hydro fluxes of a face from my partial (registers) and the other side's
 // (LDS at o, stride st).  Writes Fb[0..5].
 __device__ __forceinline__ Speeds combine_h(const double (&m)[NH], const double *o, int st,
-                                            bool mine_left, int axis, double *Fb) {
+                                            bool mine_left, int axis, bool sym, double *Fb) {
     const double mlp = m[H_LP], mlm = m[H_LM], olp = o[H_LP * st], olm = o[H_LM * st];
-    const Speeds s = mine_left ? face_speeds(mlp, mlm, olp, olm) : face_speeds(olp, olm, mlp, mlm);
+    const Speeds s = mine_left ? face_speeds(mlp, mlm, olp, olm, sym)
+                               : face_speeds(olp, olm, mlp, mlm, sym);
     const double cm = mine_left ? s.ap : -s.am;     // coefficient of my S_F
     const double co = mine_left ? -s.am : s.ap;     // coefficient of the other S_F
     const double sg = mine_left ? 1.0 : -1.0;       // S_V^R - S_V^L = sg (other - mine)
@@ -466,7 +472,8 @@ template <bool HYD>
 __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *zl, double *keep,
                                              double *run, int tid, int role, int nspec,
                                              const double *Us0, double *Os0, int fst0,
-                                             double lam, bool rate, double gamma, double gm1,
+                                             double lam, bool rate, bool sym, double gamma,
+                                             double gm1,
                                              double de, double &amax_l, int &bits) {
     const int nf = 6 + nspec;
     double chk = 0.0;
@@ -675,12 +682,12 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                 if (role == 2) {
                     double Fz[NF_MAX];
                     if (HYD) {
-                        const Speeds sp = combine_h(acc[0], zl + lane, 64, false, 2, Fz);
+                        const Speeds sp = combine_h(acc[0], zl + lane, 64, false, 2, sym, Fz);
                         amax_l = fmax(amax_l, sp.amax_face);
                     } else {
                         const Speeds sp = face_speeds(zl[H_LP * 64 + lane], zl[H_LM * 64 + lane],
                                                       xch[ZB_OFF + 2 * 64 + lane],
-                                                      xch[ZB_OFF + 3 * 64 + lane]);
+                                                      xch[ZB_OFF + 3 * 64 + lane], sym);
                         combine_s(acc[0], zl + lane, 64, false, sp, nspec, Fz);
                     }
                     update_cell(win, keep, lane, 10, ci, cj, f0, f1, Fz, lam, rate, Os, fst, chk);
@@ -740,11 +747,11 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
             const double *R = xch + XR_OFF + fi;
             double *Fo = xch + XF_OFF + fi;
             if (HYD) {
-                const Speeds sp = combine_h(acc[0], R, RST, true, ax, Fb);
+                const Speeds sp = combine_h(acc[0], R, RST, true, ax, sym, Fb);
                 amax_l = fmax(amax_l, sp.amax_face);
             } else {
                 const Speeds sp = face_speeds(xch[LL_OFF + fi], xch[LL_OFF + RST + fi],
-                                              R[H_LP * RST], R[H_LM * RST]);
+                                              R[H_LP * RST], R[H_LM * RST], sym);
                 combine_s(acc[0], R, RST, true, sp, nspec, Fb);
             }
 #pragma unroll
@@ -755,11 +762,12 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
             // z-face (k-1|k): left partial from the previous step, right = acc[1]
             double Fz[NF_MAX];
             if (HYD) {
-                const Speeds sp = combine_h(acc[1], zl + lane, 64, false, 2, Fz);
+                const Speeds sp = combine_h(acc[1], zl + lane, 64, false, 2, sym, Fz);
                 amax_l = fmax(amax_l, sp.amax_face);
             } else {
                 const Speeds sp = face_speeds(xch[ZB_OFF + lane], xch[ZB_OFF + 64 + lane],
-                                              xch[ZB_OFF + 128 + lane], xch[ZB_OFF + 192 + lane]);
+                                              xch[ZB_OFF + 128 + lane], xch[ZB_OFF + 192 + lane],
+                                              sym);
                 combine_s(acc[1], zl + lane, 64, false, sp, nspec, Fz);
             }
             if (k >= 4) update_cell(win, keep, lane, k - 1, ci, cj, f0, f1, Fz, lam, rate, Os, fst,
@@ -817,6 +825,7 @@ __global__ __launch_bounds__(NT, 2) void k_fused(StepArgs a, const double *__res
 
     const double gamma = a.gamma, gm1 = a.gamma - 1.0, de = a.de_switch;
     const bool rate = a.rate != 0;
+    const bool sym = a.sym != 0;
 
     for (int it = blockIdx.x; it < a.n_sub; it += gridDim.x) {
         const int s = order ? (a.n_sub - 1 - it) : it;
@@ -837,10 +846,10 @@ __global__ __launch_bounds__(NT, 2) void k_fused(StepArgs a, const double *__res
         int bits = 0;
 
         if (hyd)
-            subgrid_body<true>(win, xch, zl, keep, run, tid, role, nspec, Us0, Os0, fst0, lam, rate,
+            subgrid_body<true>(win, xch, zl, keep, run, tid, role, nspec, Us0, Os0, fst0, lam, rate, sym,
                                gamma, gm1, de, amax_l, bits);
         else
-            subgrid_body<false>(win, xch, zl, keep, run, tid, role, nspec, Us0, Os0, fst0, lam, rate,
+            subgrid_body<false>(win, xch, zl, keep, run, tid, role, nspec, Us0, Os0, fst0, lam, rate, sym,
                                 gamma, gm1, de, amax_l, bits);
 
         // ---- per-subgrid speed and status

@@ -30,6 +30,7 @@ struct StepArgs {
     const double *h;
     const int32_t *n_species;
     int32_t rate;   // 0: U_out = U + dt L(U); 1: U_out = L(U) on the interior
+    int32_t sym;    // symmetric (Kurganov-Tadmor 2000) face speeds
 };
 
 inline StepArgs make_args(const hydro_params *p, const hydro_batch *b) {
@@ -43,6 +44,7 @@ inline StepArgs make_args(const hydro_params *p, const hydro_batch *b) {
     a.h = b->h;
     a.n_species = b->n_species;
     a.rate = 0;
+    a.sym = (p->flags & HYDRO_FLAG_KT_SYMMETRIC) ? 1 : 0;
     return a;
 }
 
@@ -71,6 +73,7 @@ hipError_t launch_rk_update(int n_sub, int fstride, const int64_t *offset,
                             const double *Uk, const double *R, const double *clock, double *Uo,
                             hipStream_t st);
 int fused_variant_order(int v);
+hipError_t launch_tau_resync(const StepArgs &a, double *U, hipStream_t st);
 
 // The kernel node's argument block, for in-place dt updates of a captured graph.
 hipError_t fused_kernel_node_params(const StepArgs &a, const double *U_in, double *U_out,

@@ -242,8 +242,13 @@ __global__ __launch_bounds__(256) void k_flux(StepArgs a, const double *__restri
             lam_p = fmax(lam_p, fmax(L.un + L.cs, R.un + R.cs));
             lam_m = fmin(lam_m, fmin(L.un - L.cs, R.un - R.cs));
         }
-        const double ap = fmax(0.0, lam_p);
-        const double am = fmin(0.0, lam_m);
+        double ap = fmax(0.0, lam_p);
+        double am = fmin(0.0, lam_m);
+        if (a.sym) {   // one speed for both directions
+            const double sa = fmax(ap, -am);
+            ap = sa;
+            am = -sa;
+        }
         const double inv = 1.0 / (ap - am);
         const double apam = ap * am;
         const double sixth = 1.0 / 6.0;

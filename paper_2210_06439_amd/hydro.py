@@ -21,10 +21,11 @@ EXPORTS = [
     "hydro_autotune", "hydro_selected_variant",
     "hydro_plan_create", "hydro_plan_set_dt", "hydro_plan_launch", "hydro_plan_destroy",
     "hydro_fill_ghosts", "hydro_rate", "hydro_cfl_dt", "hydro_rk_update",
-    "hydro_rk3_create", "hydro_rk3_launch", "hydro_rk3_destroy",
+    "hydro_rk3_create", "hydro_rk3_launch", "hydro_rk3_destroy", "hydro_tau_resync",
 ]
 
 STATUS_RHO, STATUS_P, STATUS_NONFINITE, STATUS_BADMETA = 1, 2, 4, 8
+KT_SYMMETRIC = 1   # params flag: one face speed max(|u_n| + c) for both directions
 
 
 class HydroError(RuntimeError):
@@ -87,6 +88,7 @@ def lib():
                                        ctypes.POINTER(vp)]
         L.hydro_rk3_launch.argtypes = [vp, ctypes.c_int, vp]
         L.hydro_rk3_destroy.argtypes = [vp]
+        L.hydro_tau_resync.argtypes = [P, B, vp, vp]
         _lib = L
         del i32
     return _lib
@@ -109,8 +111,8 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def params(gamma=5.0 / 3.0, de_switch=1e-3, dt=0.0) -> Params:
-    return Params(float(gamma), float(de_switch), float(dt), 0)
+def params(gamma=5.0 / 3.0, de_switch=1e-3, dt=0.0, flags=0) -> Params:
+    return Params(float(gamma), float(de_switch), float(dt), int(flags))
 
 
 def q_elems(n_species: int) -> int:
@@ -345,3 +347,9 @@ class RK3:
             self.close()
         except Exception:
             pass
+
+
+def tau_resync(prm: Params, batch: Batch, U, stream=None):
+    """Entropy tracer reset to e_i^(1/gamma) where e_i >= de_switch * E (in place)."""
+    check(lib().hydro_tau_resync(ctypes.byref(prm), ctypes.byref(batch), _ptr(U),
+                                 _stream(stream)))

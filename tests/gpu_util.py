@@ -15,7 +15,7 @@ def device_batch(b):
     return hydro.DeviceBatch.from_inputs(b)
 
 
-def gpu_step(b, dt=None, variant=None, db=None):
+def gpu_step(b, dt=None, variant=None, db=None, flags=0):
     """Fused step; returns (U_out host array, amax, status)."""
     T = torch()
     db = db or device_batch(b)
@@ -23,17 +23,18 @@ def gpu_step(b, dt=None, variant=None, db=None):
     U_out = db.U.clone()
     amax = T.zeros(db.n_sub, dtype=T.float64, device="cuda")
     status = T.zeros(db.n_sub, dtype=T.int32, device="cuda")
-    hydro.step(hydro.params(dt=dt), db.struct, db.U, U_out, amax, status, variant=variant)
+    hydro.step(hydro.params(dt=dt, flags=flags), db.struct, db.U, U_out, amax, status,
+               variant=variant)
     T.cuda.synchronize()
     return U_out.cpu().numpy(), amax.cpu().numpy(), status.cpu().numpy()
 
 
-def gpu_plain(b, dt=None, db=None):
+def gpu_plain(b, dt=None, db=None, flags=0):
     """Unfused reconstruct -> flux -> divergence; returns (Q, F, U_out, amax, status)."""
     T = torch()
     db = db or device_batch(b)
     dt = b.dt if dt is None else dt
-    prm = hydro.params(dt=dt)
+    prm = hydro.params(dt=dt, flags=flags)
     qo, qn = db.q_layout()
     fo, fn = db.f_layout()
     Q = T.zeros(qn, dtype=T.float64, device="cuda")

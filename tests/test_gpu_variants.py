@@ -1,0 +1,76 @@
+"""Method variants on the GPU against the oracle: the symmetric-speed
+(Kurganov-Tadmor 2000) flux in the fused and the plain paths, and the
+entropy-tracer re-synchronisation."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import device_batch, gpu_plain, gpu_step, rel, torch
+from metrics import max_err_step
+from paper_2210_06439_amd import hydro, inputs
+
+pytestmark = pytest.mark.gpu
+
+SYM = hydro.KT_SYMMETRIC
+
+
+def _flow_batch():
+    """Subgrids with flow (rotating binary star, 32^3), and random states."""
+    c3 = inputs.config3(N=32).subset([0, 9, 21, 42, 63])
+    rb = inputs.random_batch(4, seed=91, species=(0, 5))
+    blocks = [np.array(c3.block(s)) for s in range(c3.n_sub)] + \
+             [np.array(rb.block(s)) for s in range(rb.n_sub)]
+    return inputs.pack_blocks(blocks, list(c3.h) + list(rb.h), dt=min(c3.dt, rb.dt))
+
+
+def test_symmetric_fused_matches_oracle():
+    b = _flow_batch()
+    Ug, ag, sg = gpu_step(b, flags=SYM)
+    Ur, ar, sr = oracle.step(b.U, b.offset, b.h, b.n_species, b.fstride, b.dt, flags=SYM)
+    assert max_err_step(b, Ug, Ur) <= 1e-12
+    assert rel(ag, ar) <= 1e-13 and np.array_equal(sg, sr)
+    # the flag changes the result where there is flow
+    U0, _, _ = gpu_step(b)
+    assert max_err_step(b, U0, Ur) > 1e-9
+
+
+def test_symmetric_plain_bitwise():
+    """Bitwise where no cell takes the dual-energy branch (its pow comes from
+    each side's libm), within 1e-12 on the rotating-star subgrids."""
+    rb = inputs.random_batch(4, seed=91, species=(0, 5))
+    Qg, Fg, Ug, ag, sg = gpu_plain(rb, flags=SYM)
+    Q, qo = oracle.reconstruct(rb.U, rb.offset, rb.h, rb.n_species, rb.fstride)
+    F, fo, a, st = oracle.flux(Q, qo, rb.offset, rb.h, rb.n_species, rb.fstride, flags=SYM)
+    assert np.array_equal(Fg, F)
+    assert np.array_equal(ag, a) and np.array_equal(sg, st)
+    Ur, _, _ = oracle.step(rb.U, rb.offset, rb.h, rb.n_species, rb.fstride, rb.dt, flags=SYM)
+    for s in range(rb.n_sub):
+        assert np.array_equal(rb.interior(s, Ug), rb.interior(s, Ur))
+    b = _flow_batch()
+    _, _, Ug, ag, _ = gpu_plain(b, flags=SYM)
+    Ur, ar, _ = oracle.step(b.U, b.offset, b.h, b.n_species, b.fstride, b.dt, flags=SYM)
+    assert max_err_step(b, Ug, Ur) <= 1e-12 and rel(ag, ar) <= 1e-13
+
+
+def test_unknown_flag_is_rejected():
+    b = inputs.config1()
+    with pytest.raises(hydro.HydroError):
+        gpu_step(b, flags=2)
+
+
+def test_tau_resync_matches_oracle():
+    T = torch()
+    b = inputs.config3(N=32).subset(list(range(0, 64, 3)))
+    db = device_batch(b)
+    hydro.tau_resync(hydro.params(), db.struct, db.U)
+    T.cuda.synchronize()
+    Ug = db.U.cpu().numpy()
+    Ur = oracle.tau_resync(b.U, b.offset, b.h, b.n_species, b.fstride)
+    changed = 0
+    for s in range(b.n_sub):
+        g, r, i0 = b.block(s, Ug), b.block(s, Ur), b.block(s)
+        assert np.array_equal(np.delete(g, 5, axis=0), np.delete(r, 5, axis=0))
+        # tau: one pow on each side (device and host libm), a few ulp apart
+        assert np.all(np.abs(g[5] - r[5]) <= 4 * 2.0 ** -52 * np.abs(r[5]))
+        changed += int(np.count_nonzero(r[5] != i0[5]))
+    assert changed > 100

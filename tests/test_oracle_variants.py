@@ -1,0 +1,143 @@
+"""Method variants of the oracle: the symmetric-speed (Kurganov-Tadmor 2000)
+central flux and the entropy-tracer re-synchronisation after a stage."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2210_06439_amd import inputs
+
+GAMMA = 5.0 / 3.0
+W = np.outer([1.0, 4.0, 1.0], [1.0, 4.0, 1.0]).ravel() / 36.0   # Simpson, t = (tb2+1)*3 + (tb+1)
+
+
+def _face_states(rng, n=9, nf=11, vel=0.1):
+    rho = rng.uniform(0.5, 2.0, n)
+    v = rng.normal(0.0, vel, (n, 3))
+    p = rng.uniform(0.5, 2.0, n)
+    sp = [rho * w for w in rng.uniform(0.0, 0.2, (nf - 6, n))]
+    U = inputs.conserved_from_primitive(rho, v[:, 0], v[:, 1], v[:, 2], p, sp)
+    return U.T.copy()                                          # [9][nf]
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_symmetric_flux_is_local_lax_friedrichs(axis):
+    """With the flag the face flux is the Simpson average of
+    0.5 (F_L + F_R) - 0.5 a (V_R - V_L), a = max |u_n| + c over the face."""
+    rng = np.random.default_rng(80 + axis)
+    VL, VR = _face_states(rng), _face_states(rng)
+    got, a_got, st = oracle.face(VL, VR, axis, flags=oracle.KT_SYMMETRIC)
+    assert st == 0
+    FL, FR, speeds = [], [], []
+    for t in range(9):
+        fl, unl, csl, _, _ = oracle.state_flux(VL[t], axis)
+        fr, unr, csr, _, _ = oracle.state_flux(VR[t], axis)
+        FL.append(fl)
+        FR.append(fr)
+        speeds += [abs(unl) + csl, abs(unr) + csr]
+    a = max(speeds)
+    H = 0.5 * (np.array(FL) + np.array(FR)) - 0.5 * a * (VR - VL)
+    want = W @ H
+    scale = np.max(np.abs(np.array(FL)), axis=0) + a * np.max(np.abs(VL), axis=0)
+    assert np.max(np.abs(got - want) / scale) <= 1e-14
+    assert a_got == a
+
+
+def test_symmetric_flag_matters_only_for_asymmetric_speeds():
+    rng = np.random.default_rng(90)
+    # at rest: u_n = 0 everywhere, so a+ = -a- already
+    V = _face_states(rng, vel=0.0)
+    f0, a0, _ = oracle.face(V, V[::-1].copy(), 0)
+    f1, a1, _ = oracle.face(V, V[::-1].copy(), 0, flags=oracle.KT_SYMMETRIC)
+    assert np.array_equal(f0, f1) and a0 == a1
+    # supersonic to the right: the one-sided flux is upwind, the symmetric one is not
+    Vs = _face_states(rng)
+    Vs[:, 1] = Vs[:, 0] * 5.0                                   # u_x = 5 >> c
+    Vs[:, 4] += 0.5 * 25.0 * Vs[:, 0]
+    Vr = Vs.copy()
+    Vr[:, 0] *= 1.1
+    fu, au, _ = oracle.face(Vs, Vr, 0)
+    fs, as_, _ = oracle.face(Vs, Vr, 0, flags=oracle.KT_SYMMETRIC)
+    FL = np.array([oracle.state_flux(Vs[t], 0)[0] for t in range(9)])
+    assert np.max(np.abs(fu - W @ FL) / np.max(np.abs(FL))) <= 1e-14
+    assert np.max(np.abs(fs - fu) / np.max(np.abs(FL))) > 1e-3
+    assert au == as_
+
+
+def test_symmetric_step_keeps_uniform_state_and_conserves():
+    V = np.array([1.3, 0.2, -0.1, 0.05, 2.7, 1.1, 0.2, 0.3, 0.4, 0.2, 0.2])
+    blk = np.broadcast_to(V[:, None, None, None], (11, 14, 14, 14)).copy()
+    b = inputs.pack_blocks([blk], [0.125], dt=0.01)
+    Uo, _, _ = oracle.step(b.U, b.offset, b.h, b.n_species, b.fstride, 0.01,
+                           flags=oracle.KT_SYMMETRIC)
+    assert np.array_equal(b.interior(0, Uo), b.interior(0))
+    c2 = inputs.config2(N=16)
+    U0, a0, _ = oracle.step(c2.U, c2.offset, c2.h, c2.n_species, c2.fstride, c2.dt)
+    U1, a1, _ = oracle.step(c2.U, c2.offset, c2.h, c2.n_species, c2.fstride, c2.dt,
+                            flags=oracle.KT_SYMMETRIC)
+    assert np.array_equal(a0, a1)                # the face speed is max(a+, -a-) either way
+    for f in range(11):
+        tot0 = sum(float(np.sum(c2.interior(s)[f])) for s in range(c2.n_sub))
+        tot1 = sum(float(np.sum(c2.interior(s, U1)[f])) for s in range(c2.n_sub))
+        scale = sum(float(np.sum(np.abs(c2.interior(s)[f]))) for s in range(c2.n_sub))
+        if f in (1, 2, 3):
+            scale = sum(float(np.sum(np.sqrt(c2.interior(s)[0] * c2.interior(s)[4])))
+                        for s in range(c2.n_sub))
+        assert abs(tot1 - tot0) <= 1e-13 * scale, f
+    # with zero velocity a+ = -a- already, so the two forms agree
+    assert np.array_equal(U0, U1)
+    # with flow they differ (the symmetric form adds more diffusion)
+    c3 = inputs.config3(N=16).subset([0, 5, 7])
+    Ua, _, _ = oracle.step(c3.U, c3.offset, c3.h, c3.n_species, c3.fstride, c3.dt)
+    Ub, _, _ = oracle.step(c3.U, c3.offset, c3.h, c3.n_species, c3.fstride, c3.dt,
+                           flags=oracle.KT_SYMMETRIC)
+    assert not np.array_equal(Ua, Ub)
+
+
+def test_unknown_flag_rejected():
+    b = inputs.config1()
+    prm = oracle.params(flags=2)
+    ba = oracle._BatchArgs(b.offset, b.h, b.n_species, b.fstride)
+    out = np.zeros_like(b.U)
+    amax = np.zeros(1)
+    rc = oracle.raw_call("hydro_ref_step", ctypes.byref(prm), ctypes.byref(ba.struct),
+                         oracle._dp(b.U), oracle._dp(out), oracle._dp(amax), None)
+    assert rc == -1
+
+
+def _resync_case():
+    b = inputs.config3(N=16)                     # floor cells fire the switch, stars do not
+    return b
+
+
+def test_tau_resync_warm_cells_satisfy_the_closed_form():
+    b = _resync_case()
+    U1 = oracle.tau_resync(b.U, b.offset, b.h, b.n_species, b.fstride)
+    warm = cold = 0
+    for s in range(b.n_sub):
+        I0, I1 = b.interior(s), b.interior(s, U1)
+        rho, sx, sy, sz, E = I0[0], I0[1], I0[2], I0[3], I0[4]
+        r = 1.0 / rho
+        ei = E - 0.5 * ((sx * (sx * r) + sy * (sy * r)) + sz * (sz * r))
+        hot = ei >= 1e-3 * E
+        warm += int(np.count_nonzero(hot))
+        cold += int(np.count_nonzero(~hot & (np.abs(ei - 1e-3 * E) > 1e-9 * E)))
+        # tau^gamma = e_i where reset (a few ulp: one pow each way)
+        t = I1[5][hot]
+        assert np.all(np.abs(t ** GAMMA - ei[hot]) <= 1e-14 * ei[hot])
+        # cold cells (clear of the switch threshold) keep their tracer bitwise
+        keep = ~hot & (np.abs(ei - 1e-3 * E) > 1e-9 * E)
+        assert np.array_equal(I1[5][keep], I0[5][keep])
+        # every other field is untouched, and so are the ghosts
+        assert np.array_equal(np.delete(I1, 5, axis=0), np.delete(I0, 5, axis=0))
+        blk0, blk1 = b.block(s), b.block(s, U1)
+        assert np.array_equal(blk1[:, :3], blk0[:, :3]) and np.array_equal(blk1[:, 11:], blk0[:, 11:])
+    assert warm > 1000 and cold > 1000
+
+
+def test_tau_resync_is_idempotent():
+    b = _resync_case()
+    U1 = oracle.tau_resync(b.U, b.offset, b.h, b.n_species, b.fstride)
+    U2 = oracle.tau_resync(U1, b.offset, b.h, b.n_species, b.fstride)
+    assert np.array_equal(U1, U2)
