@@ -54,10 +54,13 @@ constexpr int XR_OFF = 0;                            // [24][2][8][9] right part
 constexpr int XF_OFF = NACC * RST;                   // [11][2][8][9] face fluxes
 constexpr int LL_OFF = XF_OFF + NF_MAX * RST;        // [2][2][8][9] left speeds
 constexpr int ZB_OFF = LL_OFF + 2 * RST;             // [4][64] z-face speeds
-constexpr int DX_OFF = 0;                            // [2][11][64] (aliases XR)
+constexpr int DY_OFF = LL_OFF;                       // [11][64] (after LL and ZB are read)
 constexpr int LAYER_D = 4 * PT * 64;                 // layer-step points
 static_assert(ZB_OFF + 4 * 64 <= XCH_D, "combine layout");
 static_assert(LAYER_D <= ZB_OFF, "layer points must not overlap the z speeds");
+static_assert(DY_OFF >= XF_OFF + NF_MAX * RST && DY_OFF >= 4 * PT * 64 &&
+                  DY_OFF + NF_MAX * 64 <= XCH_D,
+              "dFy must not overlap the x/y fluxes or round 0's exchange slots");
 
 // ---- the 13 lines: n = 14 + L, (dx,dy,dz) from the base-3 digits of n -------
 
@@ -74,6 +77,8 @@ __device__ __host__ constexpr int line_of(int w, int r) {
          : w == 1 ? (r == 0 ? 10 : r == 1 ? 6 : r == 2 ? 7 : r == 3 ? 9 : 2)
                   : (r == 0 ? -1 : r == 1 ? 4 : r == 2 ? 5 : r == 3 ? 11 : 8);
 }
+
+static_assert(line_of(2, 0) < 0, "the z-line producer must be idle in round 0 (see DY_OFF)");
 
 __device__ __forceinline__ int comp(int L, int axis) {
     return axis == 0 ? ldx(L) : axis == 1 ? ldy(L) : ldz(L);
@@ -575,9 +580,15 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                     const Line5 l = line5(ci, cj, k, ldx(L), ldy(L), ldz(L));
                     if (HYD) {
                         produce_hydro<true, true>(win, l, pp, pm, gamma, gm1, de, bits);
+                        if (nspec > 0) {   // the last species field, to balance the pair
+                            double qp, qm;
+                            ppm_at(win, l, NF_MAX - 1, qp, qm);
+                            pp[(NF_MAX - 1) * 64] = qp;
+                            pm[(NF_MAX - 1) * 64] = qm;
+                        }
                     } else if (nspec > 0) {
 #pragma unroll
-                        for (int f = 6; f < NF_MAX; f++) {
+                        for (int f = 6; f < NF_MAX - 1; f++) {
                             double qp, qm;
                             ppm_at(win, l, f, qp, qm);
                             pp[f * 64] = qp;
@@ -628,9 +639,14 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                     const double un = r_axis == 0 ? ps.vx : ps.vy;
                     acc_h_vals(acc[0], ps.q, un, ps.p, ps.cs, wt);
                     run[lane] = un;
+                    if (nspec > 0) {
+                        double qp, qm;
+                        ppm_at(win, l, NF_MAX - 1, qp, qm);
+                        run[(NF_MAX - 1 - 5) * 64 + lane] = qp;
+                    }
                 } else if (nspec > 0) {
 #pragma unroll
-                    for (int f = 6; f < NF_MAX; f++) {
+                    for (int f = 6; f < NF_MAX - 1; f++) {
                         double qp, qm;
                         ppm_at(win, l, f, qp, qm);
                         run[(f - 5) * 64 + lane] = qp;
@@ -651,8 +667,11 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
             }
         }
 
-        // plane k-2 is no longer read: its slot takes plane k+3 (prefetched one
-        // step ahead); then the loads of plane k+4 start, behind this step's stores
+        // plane k-2 is no longer read (the rounds' last barrier has passed):
+        // its slot takes plane k+3 (prefetched one step ahead); then the loads
+        // of plane k+4 start, behind this step's stores.  On interior planes
+        // the barriers of the flux phases below order these stores before the
+        // next step's reads; after the first face layer a barrier does.
         if (k + 3 <= 13) {
             double *dst = win + ((k + 3) % SLOTS) * SLOT_D;
 #pragma unroll
@@ -662,7 +681,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                 for (int q = 0; q < 5; q++) pf[q] = Us[g_off[q] + (k + 4) * NPLANE];
             }
         }
-        lds_barrier();
+        if (layer) lds_barrier();
 
         if (layer) {
             LANE_GEOMETRY();
@@ -779,12 +798,16 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
             else store_s(zl + lane, 64, acc[0], nspec);
         }
         lds_barrier();
-        // phase 3: x/y owners: flux differences of their cells -> LDS ([2][11][64])
+        // phase 3: x/y owners: flux differences of their cells.  The x owner
+        // writes dFx into the cell's kept x/y difference, the y owner puts dFy
+        // in LDS; after the barrier the z owner adds it.  DY lies where the
+        // next step's first round writes nothing (the z-line producer is idle
+        // in round 0), so no XCH value is read after the next rounds begin.
         if (role < 2) {
             const int row = role == 0 ? cj - 3 : ci - 3;
             const int p = role == 0 ? ci - 3 : cj - 3;      // left face of the cell
             const double *Fl = xch + XF_OFF + (role * 8 + row) * 9 + p;
-            double *d = xch + DX_OFF + role * NF_MAX * 64 + lane;
+            double *d = role == 0 ? keep + NF_MAX * 64 + lane : xch + DY_OFF + lane;
 #pragma unroll
             for (int f = 0; f < NF_MAX; f++)
                 if (f >= f0 && f < f1) d[f * 64] = Fb[f] - Fl[f * RST];
@@ -794,10 +817,8 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
 #pragma unroll
             for (int f = 0; f < NF_MAX; f++)
                 if (f >= f0 && f < f1)
-                    keep[(NF_MAX + f) * 64 + lane] =
-                        xch[DX_OFF + f * 64 + lane] + xch[DX_OFF + (NF_MAX + f) * 64 + lane];
+                    keep[(NF_MAX + f) * 64 + lane] += xch[DY_OFF + f * 64 + lane];
         }
-        // (the next step's window barrier orders these reads before XCH reuse)
         }
     }
     if (chk != chk) bits |= HYDRO_STATUS_NONFINITE;
