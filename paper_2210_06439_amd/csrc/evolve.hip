@@ -23,41 +23,70 @@ __device__ __forceinline__ int ghost_src(int i, int d, bool clamp) {
 
 __device__ __forceinline__ int dir_of(int i) { return i < NG ? -1 : (i >= NG + NI ? 1 : 0); }
 
-// One block per (subgrid, field): every ghost cell of the field is copied
-// from the interior cell that the map names.  Only interior cells are read
-// and only ghost cells are written, so the fill is safe in place.
-__global__ __launch_bounds__(256) void k_fill_ghosts(int n_sub, int fstride,
+// The 2232 ghost cells of a 14^3 block, each packed as cell index (12 bits)
+// and neighbour direction slot (5 bits), built once per block in LDS.
+constexpr int NGHOST = NCELL - NI * NI * NI;
+
+// One block per (subgrid, field group): every ghost cell is copied from the
+// interior cell that the map names.  Only interior cells are read and only
+// ghost cells written, so the fill is safe in place.  Threads walk the ghost
+// list, so consecutive threads copy consecutive cells of a row.
+__global__ __launch_bounds__(512) void k_fill_ghosts(int n_sub, int fstride,
                                                      const int64_t *__restrict__ offset,
                                                      const int32_t *__restrict__ n_species,
                                                      const int32_t *__restrict__ src,
                                                      const int32_t *__restrict__ mode,
                                                      double *U, int32_t *status) {
-    const int s = blockIdx.x, f = blockIdx.y;
+    __shared__ int ghost[NGHOST];
+    __shared__ int64_t src_off[27];
+    __shared__ int src_mode[27];
+    __shared__ int src_nf[27];
+    const int s = blockIdx.x;
     const int ns = n_species[s];
     const int64_t off = offset[s];
-    if (ns < 0 || ns > 5 || off < 0 || f >= 6 + ns) return;
-    int bad = 0;
+    if (ns < 0 || ns > 5 || off < 0) return;
+    const int nf = 6 + ns;
+    // ghost list: cell c is a ghost iff some index is outside [3, 11)
     for (int c = threadIdx.x; c < NCELL; c += blockDim.x) {
         const int i = c % NB, j = (c / NB) % NB, k = c / NPLANE;
         const int dx = dir_of(i), dy = dir_of(j), dz = dir_of(k);
         if ((dx | dy | dz) == 0) continue;
+        // rank of c among ghosts: cells before c minus interior cells before c
+        const int kk = k < NG ? 0 : (k >= NG + NI ? NI : k - NG);
+        const int jj = j < NG ? 0 : (j >= NG + NI ? NI : j - NG);
+        const int ii = i < NG ? 0 : (i >= NG + NI ? NI : i - NG);
+        int inner = kk * NI * NI;                       // interior cells in planes below
+        if (k >= NG && k < NG + NI) inner += jj * NI + ((j >= NG && j < NG + NI) ? ii : 0);
         const int n = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1);
-        const int sb = src[s * 27 + n];
-        const int m = mode[s * 27 + n];
-        if (sb < 0 || sb >= n_sub) {
+        ghost[c - inner] = c | (n << 12);
+    }
+    if (threadIdx.x < 27) {
+        const int sb = src[s * 27 + threadIdx.x];
+        const bool ok = threadIdx.x != 13 && sb >= 0 && sb < n_sub;
+        const int ns2 = ok ? n_species[sb] : -1;
+        const int64_t off2 = ok ? offset[sb] : -1;
+        const bool good = ok && ns2 >= 0 && ns2 <= 5 && off2 >= 0;
+        src_off[threadIdx.x] = good ? off2 : -1;
+        src_nf[threadIdx.x] = good ? 6 + ns2 : 0;
+        src_mode[threadIdx.x] = mode[s * 27 + threadIdx.x];
+    }
+    __syncthreads();
+    int bad = 0;
+    for (int e = threadIdx.x; e < nf * NGHOST; e += blockDim.x) {
+        const int f = e / NGHOST;
+        const int g = ghost[e - f * NGHOST];
+        const int c = g & 0xfff, n = g >> 12;
+        const int64_t o2 = src_off[n];
+        if (o2 < 0 || f >= src_nf[n]) {
             bad = 1;
             continue;
         }
-        const int ns2 = n_species[sb];
-        const int64_t off2 = offset[sb];
-        if (ns2 < 0 || ns2 > 5 || off2 < 0 || f >= 6 + ns2) {
-            bad = 1;
-            continue;
-        }
+        const int m = src_mode[n];
+        const int i = c % NB, j = (c / NB) % NB, k = c / NPLANE;
+        const int dx = n % 3 - 1, dy = (n / 3) % 3 - 1, dz = n / 9 - 1;
         const int si = ghost_src(i, dx, m & 1), sj = ghost_src(j, dy, m & 2),
                   sk = ghost_src(k, dz, m & 4);
-        U[off + (int64_t)f * fstride + c] =
-            U[off2 + (int64_t)f * fstride + (sk * NB + sj) * NB + si];
+        U[off + (int64_t)f * fstride + c] = U[o2 + (int64_t)f * fstride + (sk * NB + sj) * NB + si];
     }
     if (bad && status) atomicOr(&status[s], (int)HYDRO_STATUS_BADMETA);
 }
@@ -150,8 +179,8 @@ hipError_t launch_fill_ghosts(int n_sub, int fstride, const int64_t *offset,
                               const int32_t *n_species, const int32_t *src, const int32_t *mode,
                               double *U, int32_t *status, hipStream_t st) {
     if (n_sub == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_ghosts, dim3(n_sub, NF_MAX), dim3(256), 0, st, n_sub, fstride,
-                       offset, n_species, src, mode, U, status);
+    hipLaunchKernelGGL(k_fill_ghosts, dim3(n_sub), dim3(512), 0, st, n_sub, fstride, offset,
+                       n_species, src, mode, U, status);
     return hipGetLastError();
 }
 
