@@ -275,10 +275,20 @@ int hydro_rk_update(const hydro_batch *batch, double a, const double *U0, double
                     void *stream);
 
 /*
+ * hydro_rk_stage -- a fused Runge-Kutta stage with the step size on the
+ * device: U_out = a U0 + b (U_in + dt L(U_in)) on the interior, dt =
+ * clock[1], or U_out = U0 where dt == 0.  amax[s] as hydro_step; status bits
+ * are ORed into status[s] (may be NULL).  U_out may alias U0 but not U_in.
+ */
+int hydro_rk_stage(const hydro_params *params, const hydro_batch *batch, const double *U_in,
+                   double *U_out, const double *U0, double a, double b, const double *clock,
+                   double *amax, int32_t *status, void *stream);
+
+/*
  * SSP-RK3 time steps captured in one hipGraph.  One replay is one step:
  *   fill(U); R = L(U); clock <- CFL(amax); U1 = U + dt R;
- *   fill(U1); R = L(U1); U2 = 3/4 U + 1/4 (U1 + dt R);
- *   fill(U2); R = L(U2); U  = 1/3 U + 2/3 (U2 + dt R).
+ *   fill(U1); U2 = 3/4 U + 1/4 (U1 + dt L(U1))      (one fused stage);
+ *   fill(U2); U  = 1/3 U + 2/3 (U2 + dt L(U2))      (one fused stage).
  * U holds the state (its ghosts are refilled at the start of every step, so
  * after the last step they hold the previous step's values); U1, U2 and R
  * are work buffers with U's layout; amax [n_sub]; status [n_sub] collects

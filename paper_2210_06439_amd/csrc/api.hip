@@ -348,6 +348,27 @@ int hydro_cfl_dt(const hydro_batch *batch, const double *amax, double cfl, doubl
     return e == hipSuccess ? HYDRO_OK : fail_hip(e);
 }
 
+int hydro_rk_stage(const hydro_params *params, const hydro_batch *batch, const double *U_in,
+                   double *U_out, const double *U0, double a, double b, const double *clock,
+                   double *amax, int32_t *status, void *stream) {
+    int rc = check_common(params, batch);
+    if (rc) return rc;
+    if (batch->n_sub == 0) return HYDRO_OK;
+    if (!U_in || !U_out || !U0 || !clock || !amax || U_in == U_out || !aligned8(U_in) ||
+        !aligned8(U_out) || !aligned8(U0))
+        return HYDRO_EINVAL;
+    if ((rc = check_device())) return rc;
+    StepArgs sa = make_args(params, batch);
+    sa.clock = clock;
+    sa.U0 = U0;
+    sa.c0 = a;
+    sa.c1 = b;
+    hipError_t e = launch_fused_step(sa, U_in, U_out, amax, status,
+                                     hydro_selected_variant(batch->n_sub, 5),
+                                     static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HYDRO_OK : fail_hip(e);
+}
+
 int hydro_tau_resync(const hydro_params *params, const hydro_batch *batch, double *U,
                      void *stream) {
     int rc = check_common(params, batch);
@@ -392,14 +413,17 @@ hipError_t enqueue_rk3_step(const StepArgs &ra, int variant, const hydro_ghost_m
     if ((e = launch_rk_update(n, fs, ra.offset, ra.n_species, 0.0, U, 1.0, U, R, clock, U1, st)))
         return e;
     if ((e = fill(U1))) return e;
-    if ((e = launch_fused_step(ra, U1, R, amax, status, variant, st))) return e;
-    if ((e = launch_rk_update(n, fs, ra.offset, ra.n_species, 0.75, U, 0.25, U1, R, clock, U2,
-                              st)))
-        return e;
+    StepArgs sa = ra;               // fused stages with dt from the device clock
+    sa.rate = 0;
+    sa.clock = clock;
+    sa.U0 = U;
+    sa.c0 = 0.75;
+    sa.c1 = 0.25;
+    if ((e = launch_fused_step(sa, U1, U2, amax, status, variant, st))) return e;
     if ((e = fill(U2))) return e;
-    if ((e = launch_fused_step(ra, U2, R, amax, status, variant, st))) return e;
-    return launch_rk_update(n, fs, ra.offset, ra.n_species, 1.0 / 3.0, U, 2.0 / 3.0, U2, R, clock,
-                            U, st);
+    sa.c0 = 1.0 / 3.0;
+    sa.c1 = 2.0 / 3.0;
+    return launch_fused_step(sa, U2, U, amax, status, variant, st);
 }
 
 }  // namespace

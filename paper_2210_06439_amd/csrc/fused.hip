@@ -451,11 +451,18 @@ __device__ __forceinline__ void combine_s(const double (&m)[NH], const double *o
 // Update of one interior cell of plane `kc` from its z flux Fz and the kept
 // x/y difference: U_out = U - lam ((dFx + dFy) + dFz) for fields [f0, f1),
 // or, for the rate form, U_out = -lam ((dFx + dFy) + dFz) with lam = 1/h.
+// Runge-Kutta stage combination of the update (U0 of this subgrid, or null).
+struct Stage {
+    const double *U0;
+    double c0, c1;
+    bool identity;   // dt == 0: the stage returns U0
+};
+
 // chk collects 0 * v over the outputs: it stays 0 unless some v is not finite.
 __device__ __forceinline__ void update_cell(const double *win, const double *keep, int lane,
                                             int kc, int ci, int cj, int f0, int f1,
-                                            const double *Fz, double lam, bool rate, double *Os,
-                                            int fst, double &chk) {
+                                            const double *Fz, double lam, bool rate,
+                                            const Stage &stg, double *Os, int fst, double &chk) {
     const int cidx = opaque_v(kc * NPLANE + cj * NB + ci);
     const int fs = opaque_s(fst);
 #pragma unroll
@@ -464,7 +471,11 @@ __device__ __forceinline__ void update_cell(const double *win, const double *kee
             const double dfz = Fz[f] - keep[f * 64 + lane];
             const double sxy = keep[(NF_MAX + f) * 64 + lane];
             const double u = win[(kc % SLOTS) * SLOT_D + f * NPLANE + cj * NB + ci];
-            const double v = (rate ? 0.0 : u) - lam * (sxy + dfz);
+            double v = (rate ? 0.0 : u) - lam * (sxy + dfz);
+            if (stg.U0) {
+                const double u0 = stg.U0[f * fs + cidx];
+                v = stg.identity ? u0 : fma(stg.c0, u0, stg.c1 * v);
+            }
             chk = fma(v, 0.0, chk);
             Os[f * fs + cidx] = v;
         }
@@ -477,7 +488,8 @@ template <bool HYD>
 __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *zl, double *keep,
                                              double *run, int tid, int role, int nspec,
                                              const double *Us0, double *Os0, int fst0,
-                                             double lam, bool rate, bool sym, double gamma,
+                                             double lam, bool rate, const Stage &stg, bool sym,
+                                             double gamma,
                                              double gm1,
                                              double de, double &amax_l, int &bits) {
     const int nf = 6 + nspec;
@@ -709,7 +721,8 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                                                       xch[ZB_OFF + 3 * 64 + lane], sym);
                         combine_s(acc[0], zl + lane, 64, false, sp, nspec, Fz);
                     }
-                    update_cell(win, keep, lane, 10, ci, cj, f0, f1, Fz, lam, rate, Os, fst, chk);
+                    update_cell(win, keep, lane, 10, ci, cj, f0, f1, Fz, lam, rate, stg, Os, fst,
+                                chk);
                 }
             }
             continue;
@@ -789,7 +802,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                                               sym);
                 combine_s(acc[1], zl + lane, 64, false, sp, nspec, Fz);
             }
-            if (k >= 4) update_cell(win, keep, lane, k - 1, ci, cj, f0, f1, Fz, lam, rate, Os, fst,
+            if (k >= 4) update_cell(win, keep, lane, k - 1, ci, cj, f0, f1, Fz, lam, rate, stg, Os, fst,
                                     chk);
 #pragma unroll
             for (int f = 0; f < NF_MAX; f++)
@@ -828,7 +841,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
 // ---- the kernel ---------------------------------------------------------------
 
 __global__ __launch_bounds__(NT, 2) void k_fused(StepArgs a, const double *__restrict__ U,
-                                                 double *__restrict__ Uo,
+                                                 double *Uo,
                                                  double *__restrict__ amax,
                                                  int32_t *__restrict__ status, int order) {
     __shared__ double lds[LDS_D];
@@ -855,11 +868,17 @@ __global__ __launch_bounds__(NT, 2) void k_fused(StepArgs a, const double *__res
         if (nspec < 0 || nspec > 5 || off < 0 || (off & 1)) {
             if (tid == 0) {
                 amax[s] = 0.0;
-                if (status) status[s] = (rate ? status[s] : 0) | HYDRO_STATUS_BADMETA;
+                if (status) status[s] = (rate || a.U0 ? status[s] : 0) | HYDRO_STATUS_BADMETA;
             }
             continue;
         }
-        const double lam = rate ? 1.0 / a.h[s] : a.dt / a.h[s];
+        const double dtv = a.clock ? a.clock[1] : a.dt;
+        const double lam = rate ? 1.0 / a.h[s] : dtv / a.h[s];
+        Stage stg;
+        stg.U0 = a.U0 ? a.U0 + off : nullptr;
+        stg.c0 = a.c0;
+        stg.c1 = a.c1;
+        stg.identity = dtv == 0.0;
         const double *Us0 = U + off;
         double *Os0 = Uo + off;
         const int fst0 = a.fstride;
@@ -867,10 +886,10 @@ __global__ __launch_bounds__(NT, 2) void k_fused(StepArgs a, const double *__res
         int bits = 0;
 
         if (hyd)
-            subgrid_body<true>(win, xch, zl, keep, run, tid, role, nspec, Us0, Os0, fst0, lam, rate, sym,
+            subgrid_body<true>(win, xch, zl, keep, run, tid, role, nspec, Us0, Os0, fst0, lam, rate, stg, sym,
                                gamma, gm1, de, amax_l, bits);
         else
-            subgrid_body<false>(win, xch, zl, keep, run, tid, role, nspec, Us0, Os0, fst0, lam, rate, sym,
+            subgrid_body<false>(win, xch, zl, keep, run, tid, role, nspec, Us0, Os0, fst0, lam, rate, stg, sym,
                                 gamma, gm1, de, amax_l, bits);
 
         // ---- per-subgrid speed and status
@@ -892,7 +911,7 @@ __global__ __launch_bounds__(NT, 2) void k_fused(StepArgs a, const double *__res
             }
             if (!isfinite(m)) b |= HYDRO_STATUS_NONFINITE;
             amax[s] = m;
-            if (status) status[s] = rate ? (status[s] | b) : b;
+            if (status) status[s] = (rate || a.U0) ? (status[s] | b) : b;
         }
     }
 }

@@ -31,6 +31,11 @@ struct StepArgs {
     const int32_t *n_species;
     int32_t rate;   // 0: U_out = U + dt L(U); 1: U_out = L(U) on the interior
     int32_t sym;    // symmetric (Kurganov-Tadmor 2000) face speeds
+    // Runge-Kutta stage form (U0 non-null): U_out = c0 U0 + c1 (U + dt L(U)),
+    // or U0 where dt == 0; dt = clock[1] when clock is non-null, else dt.
+    const double *clock;
+    const double *U0;
+    double c0, c1;
 };
 
 inline StepArgs make_args(const hydro_params *p, const hydro_batch *b) {
@@ -45,6 +50,10 @@ inline StepArgs make_args(const hydro_params *p, const hydro_batch *b) {
     a.n_species = b->n_species;
     a.rate = 0;
     a.sym = (p->flags & HYDRO_FLAG_KT_SYMMETRIC) ? 1 : 0;
+    a.clock = nullptr;
+    a.U0 = nullptr;
+    a.c0 = 0.0;
+    a.c1 = 1.0;
     return a;
 }
 

@@ -22,6 +22,7 @@ EXPORTS = [
     "hydro_plan_create", "hydro_plan_set_dt", "hydro_plan_launch", "hydro_plan_destroy",
     "hydro_fill_ghosts", "hydro_rate", "hydro_cfl_dt", "hydro_rk_update",
     "hydro_rk3_create", "hydro_rk3_launch", "hydro_rk3_destroy", "hydro_tau_resync",
+    "hydro_rk_stage",
 ]
 
 STATUS_RHO, STATUS_P, STATUS_NONFINITE, STATUS_BADMETA = 1, 2, 4, 8
@@ -89,6 +90,7 @@ def lib():
         L.hydro_rk3_launch.argtypes = [vp, ctypes.c_int, vp]
         L.hydro_rk3_destroy.argtypes = [vp]
         L.hydro_tau_resync.argtypes = [P, B, vp, vp]
+        L.hydro_rk_stage.argtypes = [P, B, vp, vp, vp, dbl, dbl, vp, vp, vp, vp]
         _lib = L
         del i32
     return _lib
@@ -293,6 +295,14 @@ def rate(prm: Params, batch: Batch, U_in, R, amax, status=None, stream=None):
 def cfl_dt(batch: Batch, amax, cfl, t_end, clock, stream=None):
     check(lib().hydro_cfl_dt(ctypes.byref(batch), _ptr(amax), float(cfl), float(t_end),
                              _ptr(clock), _stream(stream)))
+
+
+def rk_stage(prm: Params, batch: Batch, U_in, U_out, U0, a, b, clock, amax, status=None,
+             stream=None):
+    """Fused stage: U_out = a U0 + b (U_in + dt L(U_in)), dt = clock[1] (device)."""
+    check(lib().hydro_rk_stage(ctypes.byref(prm), ctypes.byref(batch), _ptr(U_in), _ptr(U_out),
+                               _ptr(U0), float(a), float(b), _ptr(clock), _ptr(amax),
+                               _ptr(status), _stream(stream)))
 
 
 def rk_update(batch: Batch, a, U0, b, Uk, R, clock, U_out, stream=None):
