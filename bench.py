@@ -169,6 +169,7 @@ def serving_run(torch, hydro, serving, b, db, peak_subgrids_per_s, n_requests, b
     128^3 batch at offered loads 0.3/0.6/0.9 of the measured batched peak."""
     n_slots = serving.slots_for_budget(int(budget_gb * 1e9))
     be = serving.GpuBackend(n_slots, catalogue=db)
+    be.warmup(b.dt)
     work = serving.mean_work(4000, b.n_sub)
     out = {"budget_GB": budget_gb, "slots": n_slots, "requests_per_load": n_requests,
            "peak_subgrid_steps_per_s": peak_subgrids_per_s, "mean_subgrid_steps_per_request": work,

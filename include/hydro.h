@@ -140,6 +140,19 @@ int hydro_step(const hydro_params *params, const hydro_batch *batch,
                const double *U_in, double *U_out, double *amax,
                int32_t *status, void *stream);
 
+/*
+ * hydro_step_io -- hydro_step with a separate output offset per subgrid:
+ * subgrid s is read at batch->offset[s] of U_in and its interior written at
+ * out_offset[s] of U_out (device [n_sub], same alignment rule as offset).
+ * U_in and U_out may be the same buffer when no subgrid's output region
+ * overlaps any subgrid's input region (the caller's responsibility: the
+ * library does not check the device arrays for overlap).  This is how a
+ * ping-pong pool advances subgrids in both directions in one launch.
+ */
+int hydro_step_io(const hydro_params *params, const hydro_batch *batch,
+                  const int64_t *out_offset, const double *U_in, double *U_out,
+                  double *amax, int32_t *status, void *stream);
+
 /* Element counts of one subgrid's Q and F regions: 26*nf*1000 and 3*nf*576. */
 int64_t hydro_q_elems(int n_species);
 int64_t hydro_f_elems(int n_species);
@@ -175,7 +188,7 @@ int hydro_autotune(const hydro_params *params, const hydro_batch *batch,
                    int32_t *status, int reps, float *times_ms, void *stream);
 
 /* The variant hydro_step will use for a batch of n_sub subgrids (the tuned one
- * for that power-of-two bucket, else the default).  max_species is reserved:
+ * for that power-of-two bucket, else the default, variant 1).  max_species is reserved:
  * the choice does not depend on it. */
 int hydro_selected_variant(int n_sub, int max_species);
 

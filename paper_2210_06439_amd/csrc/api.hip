@@ -194,7 +194,9 @@ int hydro_selected_variant(int n_sub, int max_species) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_load_locked();
     auto it = g_tuned.find(bucket_of(n_sub));
-    return it == g_tuned.end() ? 0 : it->second;
+    // untuned: two workgroups per CU (the second wave of workgroups evens out
+    // the tail of a persistent launch)
+    return it == g_tuned.end() ? 1 : it->second;
 }
 
 int hydro_step(const hydro_params *params, const hydro_batch *batch, const double *U_in,
@@ -202,6 +204,23 @@ int hydro_step(const hydro_params *params, const hydro_batch *batch, const doubl
     if (!batch) return HYDRO_EINVAL;
     return hydro_step_variant(params, batch, U_in, U_out, amax, status,
                               hydro_selected_variant(batch->n_sub, 5), stream);
+}
+
+int hydro_step_io(const hydro_params *params, const hydro_batch *batch,
+                  const int64_t *out_offset, const double *U_in, double *U_out,
+                  double *amax, int32_t *status, void *stream) {
+    int rc = check_common(params, batch);
+    if (rc) return rc;
+    if (batch->n_sub == 0) return HYDRO_OK;
+    if (!out_offset || !U_in || !U_out || !amax || !aligned8(U_in) || !aligned8(U_out))
+        return HYDRO_EINVAL;
+    if ((rc = check_device())) return rc;
+    StepArgs a = make_args(params, batch);
+    a.out_offset = out_offset;
+    hipError_t e = launch_fused_step(a, U_in, U_out, amax, status,
+                                     hydro_selected_variant(batch->n_sub, 5),
+                                     static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HYDRO_OK : fail_hip(e);
 }
 
 int hydro_autotune(const hydro_params *params, const hydro_batch *batch, const double *U_in,

@@ -865,7 +865,8 @@ __global__ __launch_bounds__(NT, 2) void k_fused(StepArgs a, const double *__res
         const int s = order ? (a.n_sub - 1 - it) : it;
         const int nspec = a.n_species[s];
         const int64_t off = a.offset[s];
-        if (nspec < 0 || nspec > 5 || off < 0 || (off & 1)) {
+        const int64_t ooff = a.out_offset ? a.out_offset[s] : off;
+        if (nspec < 0 || nspec > 5 || off < 0 || (off & 1) || ooff < 0 || (ooff & 1)) {
             if (tid == 0) {
                 amax[s] = 0.0;
                 if (status) status[s] = (rate || a.U0 ? status[s] : 0) | HYDRO_STATUS_BADMETA;
@@ -880,7 +881,7 @@ __global__ __launch_bounds__(NT, 2) void k_fused(StepArgs a, const double *__res
         stg.c1 = a.c1;
         stg.identity = dtv == 0.0;
         const double *Us0 = U + off;
-        double *Os0 = Uo + off;
+        double *Os0 = Uo + ooff;
         const int fst0 = a.fstride;
         double amax_l = 0.0;
         int bits = 0;

@@ -36,6 +36,8 @@ struct StepArgs {
     const double *clock;
     const double *U0;
     double c0, c1;
+    // per-subgrid output offsets (null: the input offsets)
+    const int64_t *out_offset;
 };
 
 inline StepArgs make_args(const hydro_params *p, const hydro_batch *b) {
@@ -54,6 +56,7 @@ inline StepArgs make_args(const hydro_params *p, const hydro_batch *b) {
     a.U0 = nullptr;
     a.c0 = 0.0;
     a.c1 = 1.0;
+    a.out_offset = nullptr;
     return a;
 }
 

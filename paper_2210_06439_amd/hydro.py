@@ -22,7 +22,7 @@ EXPORTS = [
     "hydro_plan_create", "hydro_plan_set_dt", "hydro_plan_launch", "hydro_plan_destroy",
     "hydro_fill_ghosts", "hydro_rate", "hydro_cfl_dt", "hydro_rk_update",
     "hydro_rk3_create", "hydro_rk3_launch", "hydro_rk3_destroy", "hydro_tau_resync",
-    "hydro_rk_stage",
+    "hydro_rk_stage", "hydro_step_io",
 ]
 
 STATUS_RHO, STATUS_P, STATUS_NONFINITE, STATUS_BADMETA = 1, 2, 4, 8
@@ -91,6 +91,7 @@ def lib():
         L.hydro_rk3_destroy.argtypes = [vp]
         L.hydro_tau_resync.argtypes = [P, B, vp, vp]
         L.hydro_rk_stage.argtypes = [P, B, vp, vp, vp, dbl, dbl, vp, vp, vp, vp]
+        L.hydro_step_io.argtypes = [P, B, vp, vp, vp, vp, vp, vp]
         _lib = L
         del i32
     return _lib
@@ -200,6 +201,14 @@ def step(prm: Params, batch: Batch, U_in, U_out, amax, status=None, variant=None
         check(lib().hydro_step_variant(ctypes.byref(prm), ctypes.byref(batch), _ptr(U_in),
                                        _ptr(U_out), _ptr(amax), _ptr(status), int(variant),
                                        _stream(stream)))
+
+
+def step_io(prm: Params, batch: Batch, out_offset, U_in, U_out, amax, status=None, stream=None):
+    """Fused step writing subgrid s at out_offset[s] of U_out (which may be U_in
+    when the output regions do not overlap the input regions)."""
+    check(lib().hydro_step_io(ctypes.byref(prm), ctypes.byref(batch), _ptr(out_offset),
+                              _ptr(U_in), _ptr(U_out), _ptr(amax), _ptr(status),
+                              _stream(stream)))
 
 
 def autotune(prm: Params, batch: Batch, U_in, U_out, amax, status=None, reps=3, stream=None):
