@@ -152,3 +152,33 @@ def test_autotune_picks_a_variant_and_hydro_step_uses_it():
     ref, _, _ = gpu_step(b, variant=0)
     got, _, _ = gpu_step(b)
     assert np.array_equal(ref, got)
+
+
+def test_step_io_writes_at_output_offsets_in_one_buffer():
+    """Subgrids read from the first half of a buffer and written to the
+    second half (same pointer for input and output) give the bits of
+    hydro_step; an odd output offset flags only that subgrid."""
+    T = torch()
+    b = inputs.random_batch(5, seed=48, species=(5,))
+    db = device_batch(b)
+    ref = db.U.clone()
+    amax_r = T.zeros(db.n_sub, dtype=T.float64, device="cuda")
+    hydro.step(hydro.params(dt=b.dt), db.struct, db.U, ref, amax_r)
+    n = db.U.numel()
+    pool = T.zeros(2 * n, dtype=T.float64, device="cuda")
+    pool[:n] = db.U
+    out_off = db.offset + n
+    amax = T.zeros(db.n_sub, dtype=T.float64, device="cuda")
+    status = T.zeros(db.n_sub, dtype=T.int32, device="cuda")
+    hydro.step_io(hydro.params(dt=b.dt), db.struct, out_off, pool, pool, amax, status)
+    T.cuda.synchronize()
+    got = pool[n:].cpu().numpy()
+    r = ref.cpu().numpy()
+    for s in range(b.n_sub):
+        assert np.array_equal(b.interior(s, got), b.interior(s, r))
+    assert T.equal(amax, amax_r) and not status.any().item()
+    out_off[2] += 1
+    hydro.step_io(hydro.params(dt=b.dt), db.struct, out_off, pool, pool, amax, status)
+    T.cuda.synchronize()
+    st = status.cpu().numpy()
+    assert st[2] == hydro.STATUS_BADMETA and np.all(np.delete(st, 2) == 0)
