@@ -118,6 +118,45 @@ def timed_plan(plan, steps, warmup, torch):
     return wall, per
 
 
+def plain_batched_stages(torch, hydro, db, prm, reps=5):
+    """The unfused form with one launch per stage over the whole batch: each
+    stage's time and its algorithmic HBM rate (Q and F round-trip HBM)."""
+    n = db.n_sub
+    nf = 6 + db.n_species_host.astype(np.int64)
+    qo, qn = db.q_layout()
+    fo, fn = db.f_layout()
+    Q = torch.zeros(qn, dtype=torch.float64, device="cuda")
+    F = torch.zeros(fn, dtype=torch.float64, device="cuda")
+    amax = torch.zeros(n, dtype=torch.float64, device="cuda")
+    U_out = db.U.clone()
+    u_bytes = int(np.sum(nf * 2744 * 8))
+    q_bytes, f_bytes = qn * 8, fn * 8
+    i_bytes = int(np.sum(nf * 512 * 8))
+    stages = {
+        "reconstruct": (lambda: hydro.reconstruct(prm, db.struct, db.U, Q, qo), u_bytes + q_bytes),
+        "flux": (lambda: hydro.flux(prm, db.struct, Q, qo, F, fo, amax), q_bytes + f_bytes),
+        "divergence": (lambda: hydro.divergence(prm, db.struct, F, fo, db.U, U_out),
+                       f_bytes + 2 * i_bytes),
+    }
+    out = {}
+    stream = torch.cuda.current_stream()
+    for name, (fn_, nbytes) in stages.items():
+        fn_()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn_()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms": ms, "algorithmic_bytes": nbytes,
+                     "GB_per_s": nbytes / (ms * 1e-3) / 1e9,
+                     "hbm_frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS}
+        log(f"plain batched {name}: {ms:.3f} ms, {out[name]['GB_per_s']:.0f} GB/s")
+    return out
+
+
 def plain_vs_batched(torch, hydro, inputs, reps=3):
     """Config 2 (64^3, 512 subgrids): one subgrid per launch vs one batched launch."""
     b = inputs.config2()
@@ -157,6 +196,7 @@ def plain_vs_batched(torch, hydro, inputs, reps=3):
         dt = (time.perf_counter() - t0) / reps
         out[name] = {"ms": dt * 1e3, "cell_updates_per_s": b.cell_updates / dt}
         log(f"config2 {name}: {dt * 1e3:.2f} ms")
+    out["plain_batched_stages"] = plain_batched_stages(torch, hydro, db, prm)
     out["speedup_batched_vs_per_subgrid_unfused"] = (
         out["per_subgrid_unfused"]["ms"] / out["batched_fused"]["ms"])
     out["speedup_batched_vs_per_subgrid_fused"] = (
