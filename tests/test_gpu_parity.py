@@ -155,3 +155,21 @@ def test_config4_mixed_species_launch():
         S = field_scales(np.array(b.block(s)))
         assert float(mixed_rel(b.interior(s, Ug), sub.interior(n, Ur), S).max()) <= TOL
     assert rel(ag[idx], ar) <= 1e-13
+
+
+@pytest.mark.parametrize("variant", [None, 2])
+def test_config4_maximum_batch_sampled(variant):
+    """The largest uneven batch (8192 subgrids, levels 0-4, 0 or 5 species),
+    in the tuned launch shape and in one workgroup per subgrid: sampled
+    subgrids against the oracle, every status word clear."""
+    b = inputs.config4(launch=9, n_override=8192)
+    Ug, ag, sg = gpu_step(b, variant=variant)
+    assert np.all(sg == 0) and np.all(ag > 0)
+    idx = np.unique(np.concatenate([[0, b.n_sub - 1],
+                                    np.random.default_rng(7).choice(b.n_sub, 14, replace=False)]))
+    sub = b.subset(idx)
+    Ur, ar, sr = ref_step(sub, dt=b.dt)
+    for n, s in enumerate(idx):
+        S = field_scales(np.array(b.block(s)))
+        assert float(mixed_rel(b.interior(s, Ug), sub.interior(n, Ur), S).max()) <= TOL
+    assert rel(ag[idx], ar) <= 1e-13
