@@ -160,6 +160,11 @@ int64_t hydro_f_elems(int n_species);
 /* Text for a return code (static storage; HIP detail for HYDRO_ELAUNCH). */
 const char *hydro_strerror(int code);
 
+/* Device memory the library holds between calls: always 0.  No entry point
+ * allocates device memory; every buffer (including the unfused form's Q and
+ * F, and the work buffers of the time integration) belongs to the caller. */
+int64_t hydro_workspace_bytes(void);
+
 /* ---------------------------------------------------------------------------
  * Launch variants and the autotuner.  The fused step has several launch
  * shapes (workgroups per CU, subgrid scheduling order); all of them compute

@@ -121,6 +121,7 @@ extern "C" {
 
 int64_t hydro_q_elems(int n_species) { return (int64_t)26 * (6 + n_species) * QCELL; }
 int64_t hydro_f_elems(int n_species) { return (int64_t)3 * (6 + n_species) * NFACE; }
+int64_t hydro_workspace_bytes(void) { return 0; }
 
 const char *hydro_strerror(int code) {
     switch (code) {

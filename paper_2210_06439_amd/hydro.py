@@ -22,7 +22,7 @@ EXPORTS = [
     "hydro_plan_create", "hydro_plan_set_dt", "hydro_plan_launch", "hydro_plan_destroy",
     "hydro_fill_ghosts", "hydro_rate", "hydro_cfl_dt", "hydro_rk_update",
     "hydro_rk3_create", "hydro_rk3_launch", "hydro_rk3_destroy", "hydro_tau_resync",
-    "hydro_rk_stage", "hydro_step_io",
+    "hydro_rk_stage", "hydro_step_io", "hydro_workspace_bytes",
 ]
 
 STATUS_RHO, STATUS_P, STATUS_NONFINITE, STATUS_BADMETA = 1, 2, 4, 8
@@ -72,6 +72,8 @@ def lib():
         L.hydro_q_elems.restype = i64
         L.hydro_f_elems.argtypes = [ctypes.c_int]
         L.hydro_f_elems.restype = i64
+        L.hydro_workspace_bytes.argtypes = []
+        L.hydro_workspace_bytes.restype = i64
         L.hydro_strerror.argtypes = [ctypes.c_int]
         L.hydro_strerror.restype = ctypes.c_char_p
         L.hydro_variant_name.argtypes = [ctypes.c_int]

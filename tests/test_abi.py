@@ -36,6 +36,7 @@ def test_size_helpers_without_gpu():
     if not os.path.exists(hydro.LIB_PATH):
         pytest.skip("libhydro.so not built")
     assert hydro.q_elems(5) == 286000 and hydro.f_elems(5) == 19008
+    assert hydro.lib().hydro_workspace_bytes() == 0
     assert hydro.lib().hydro_strerror(-1) == b"invalid argument"
 
 
