@@ -88,6 +88,7 @@ def _f64(a):
 
 
 KT_SYMMETRIC = 1   # flags bit: one speed max(|u_n| + c) for both directions
+VELOCITY = 2       # flags bit: PPM of v = s / rho; point momentum = rho_q * v_q
 
 
 def params(gamma=5.0 / 3.0, de_switch=1e-3, dt=0.0, flags=0):
@@ -163,14 +164,14 @@ def packed_offsets(sizes):
     return off
 
 
-def reconstruct(U, offset, h, n_species, fstride, gamma=5.0 / 3.0, de_switch=1e-3):
+def reconstruct(U, offset, h, n_species, fstride, gamma=5.0 / 3.0, de_switch=1e-3, flags=0):
     """Q for every subgrid, packed; returns (Q, q_offset)."""
     U = _f64(U)
     ba = _BatchArgs(offset, h, n_species, fstride)
     q_off = packed_offsets([q_elems(ns) for ns in ba.n_species])
     total = int(q_off[-1] + q_elems(ba.n_species[-1])) if len(q_off) else 0
     Q = np.zeros(total)
-    prm = params(gamma, de_switch)
+    prm = params(gamma, de_switch, flags=flags)
     rc = lib().hydro_ref_reconstruct(ctypes.byref(prm), ctypes.byref(ba.struct), _dp(U), _dp(Q),
                                      q_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
     assert rc == 0, rc

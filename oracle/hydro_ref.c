@@ -26,9 +26,10 @@
  *       over the face's 9 surface points, integrated with the tensor
  *       Simpson (3-point closed Newton-Cotes) rule.
  *   O5  divergence and forward-Euler update of the 8^3 interior.
- *   Options: the symmetric-speed (Kurganov-Tadmor 2000) flux, and the
- *   re-synchronisation of the entropy tracer from the total energy after a
- *   stage (both outside the paper's description; variants of the method).
+ *   Options: the symmetric-speed (Kurganov-Tadmor 2000) flux, PPM of the
+ *   velocities instead of the momenta, and the re-synchronisation of the
+ *   entropy tracer from the total energy after a stage (all outside the
+ *   paper's description; variants of the method).
  *
  * Floating point: IEEE binary64, compiled with -ffp-contract=off; every
  * operation is written in the order that is evaluated.
@@ -48,7 +49,7 @@ typedef struct {
     double gamma;      /* ratio of specific heats                             */
     double de_switch;  /* dual-energy switch: use tau^gamma if e_i < eps * E  */
     double dt;         /* time step of the forward-Euler stage                */
-    uint32_t flags;    /* bit 0: symmetric speeds (REF_FLAG_KT_SYMMETRIC)     */
+    uint32_t flags;    /* REF_FLAG_* bits                                     */
 } hydro_ref_params;
 
 typedef struct {
@@ -66,9 +67,18 @@ enum { REF_OK = 0, REF_EINVAL = -1 };
  * a+ = a and a- = -a (the face flux becomes the local Lax-Friedrichs one). */
 enum { REF_FLAG_KT_SYMMETRIC = 1 };
 
+/* Velocity reconstruction: for the three momentum fields, PPM runs on the
+ * cell velocities v = s / rho along the line, and the momentum at a
+ * quadrature point is the product of the density reconstructed at that
+ * point and the reconstructed velocity.  Every other field is reconstructed
+ * as it is. */
+enum { REF_FLAG_VELOCITY = 2 };
+
+static const uint32_t REF_FLAGS_KNOWN = REF_FLAG_KT_SYMMETRIC | REF_FLAG_VELOCITY;
+
 static int check_params(const hydro_ref_params *prm)
 {
-    return (prm && (prm->flags & ~(uint32_t)REF_FLAG_KT_SYMMETRIC) == 0) ? REF_OK : REF_EINVAL;
+    return (prm && (prm->flags & ~REF_FLAGS_KNOWN) == 0) ? REF_OK : REF_EINVAL;
 }
 
 #define NB 14            /* cells per dimension incl. 3 ghost layers each side */
@@ -283,11 +293,16 @@ static int check_batch(const hydro_ref_batch *b)
 
 /* ---- per-subgrid stages ------------------------------------------------- */
 
-/* O2 over one subgrid: Q for cells [2,12)^3, all 26 directions, nf fields. */
-static void reconstruct_subgrid(const double *U, int fstride, int nf, double *Q)
+/* O2 over one subgrid: Q for cells [2,12)^3, all 26 directions, nf fields.
+ * Density is reconstructed first, so that the velocity option can scale the
+ * reconstructed velocities by the density at the same point. */
+static void reconstruct_subgrid(const double *U, int fstride, int nf, uint32_t flags,
+                                double *Q)
 {
+    const double *Urho = U + (int64_t)F_RHO * fstride;
     for (int f = 0; f < nf; f++) {
         const double *Uf = U + (int64_t)f * fstride;
+        int vel = (flags & REF_FLAG_VELOCITY) && f >= F_SX && f < F_SX + 3;
         for (int dz = -1; dz <= 1; dz++)
         for (int dy = -1; dy <= 1; dy++)
         for (int dx = -1; dx <= 1; dx++) {
@@ -298,10 +313,16 @@ static void reconstruct_subgrid(const double *U, int fstride, int nf, double *Q)
             for (int j = 2; j < 12; j++)
             for (int i = 2; i < 12; i++) {
                 double u[5];
-                for (int m = -2; m <= 2; m++)
-                    u[m + 2] = Uf[cell_index(i + m * dx, j + m * dy, k + m * dz)];
+                for (int m = -2; m <= 2; m++) {
+                    int c = cell_index(i + m * dx, j + m * dy, k + m * dz);
+                    u[m + 2] = vel ? Uf[c] / Urho[c] : Uf[c];
+                }
                 double qp, qm;
                 hydro_ref_ppm1d(u, &qp, &qm);
+                if (vel) {
+                    qp = Q[q_index(F_RHO, sp, i, j, k)] * qp;
+                    qm = Q[q_index(F_RHO, sm, i, j, k)] * qm;
+                }
                 Q[q_index(f, sp, i, j, k)] = qp;
                 Q[q_index(f, sm, i, j, k)] = qm;
             }
@@ -404,7 +425,7 @@ int hydro_ref_reconstruct(const hydro_ref_params *prm, const hydro_ref_batch *b,
     if (check_params(prm) != REF_OK || check_batch(b) != REF_OK) return REF_EINVAL;
     if (b->n_sub > 0 && (!U || !Q || !q_offset)) return REF_EINVAL;
     for (int s = 0; s < b->n_sub; s++)
-        reconstruct_subgrid(U + b->offset[s], b->fstride, 6 + b->n_species[s],
+        reconstruct_subgrid(U + b->offset[s], b->fstride, 6 + b->n_species[s], prm->flags,
                             Q + q_offset[s]);
     return REF_OK;
 }
@@ -448,7 +469,7 @@ int hydro_ref_step(const hydro_ref_params *prm, const hydro_ref_batch *b,
     for (int s = 0; s < b->n_sub; s++) {
         int nf = 6 + b->n_species[s];
         const double *U = U_in + b->offset[s];
-        reconstruct_subgrid(U, b->fstride, nf, Q);
+        reconstruct_subgrid(U, b->fstride, nf, prm->flags, Q);
         double a;
         int bits = flux_subgrid(prm, Q, nf, F, &a);
         bits |= divergence_subgrid(F, U, U_out + b->offset[s], b->fstride, nf,

@@ -55,7 +55,7 @@ def test_symmetric_plain_bitwise():
 def test_unknown_flag_is_rejected():
     b = inputs.config1()
     with pytest.raises(hydro.HydroError):
-        gpu_step(b, flags=2)
+        gpu_step(b, flags=8)
 
 
 def test_tau_resync_matches_oracle():

@@ -1,5 +1,6 @@
 """Method variants of the oracle: the symmetric-speed (Kurganov-Tadmor 2000)
-central flux and the entropy-tracer re-synchronisation after a stage."""
+central flux, reconstruction of the velocities instead of the momenta, and
+the entropy-tracer re-synchronisation after a stage."""
 import ctypes
 
 import numpy as np
@@ -97,13 +98,132 @@ def test_symmetric_step_keeps_uniform_state_and_conserves():
 
 def test_unknown_flag_rejected():
     b = inputs.config1()
-    prm = oracle.params(flags=2)
+    prm = oracle.params(flags=8)
     ba = oracle._BatchArgs(b.offset, b.h, b.n_species, b.fstride)
     out = np.zeros_like(b.U)
     amax = np.zeros(1)
     rc = oracle.raw_call("hydro_ref_step", ctypes.byref(prm), ctypes.byref(ba.struct),
                          oracle._dp(b.U), oracle._dp(out), oracle._dp(amax), None)
     assert rc == -1
+
+
+# ---- velocity reconstruction ---------------------------------------------------
+
+NB = 14
+VEL = oracle.VELOCITY
+DIRS = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)
+        if (dx, dy, dz) != (0, 0, 0)]
+
+
+def _slot(dx, dy, dz):
+    n = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1)
+    return n if n < 13 else n - 1
+
+
+def _block_from_velocity(rho, v, rng, nf=11):
+    """[nf, z, y, x] block with the given density and velocity fields, random
+    positive pressure and species."""
+    p = rng.uniform(0.5, 2.0, rho.shape)
+    sp = [rho * w for w in rng.uniform(0.0, 0.2, (nf - 6,) + rho.shape)]
+    return inputs.conserved_from_primitive(rho, v[0], v[1], v[2], p, sp)
+
+
+def _recon(blk, flags):
+    b = inputs.pack_blocks([blk], [0.125])
+    Q, _ = oracle.reconstruct(b.U, b.offset, b.h, b.n_species, b.fstride, flags=flags)
+    return Q.reshape(blk.shape[0], 26, 10, 10, 10)
+
+
+def test_velocity_uniform_gives_density_times_velocity_bitwise():
+    """Density k/64 and dyadic velocities make s = rho v and s / rho exact, and
+    PPM of a constant returns the constant: every point momentum is the
+    point density times v, rounded once."""
+    rng = np.random.default_rng(60)
+    rho = rng.integers(32, 129, (NB, NB, NB)) / 64.0
+    v0 = np.array([0.375, -0.25, 1.5])
+    blk = _block_from_velocity(rho, v0[:, None, None, None] * np.ones((3, NB, NB, NB)), rng)
+    assert np.array_equal(blk[1] / blk[0], np.full_like(rho, v0[0]))
+    Q = _recon(blk, VEL)
+    for a in range(3):
+        assert np.array_equal(Q[1 + a], Q[0] * v0[a]), a
+
+
+def test_velocity_linear_profile_reconstructed_at_each_point():
+    """A velocity linear in the cell index is reconstructed exactly by PPM,
+    whatever the density does: at the point c + d/2 the momentum is
+    rho_q(c, d) * v(c + d/2), up to the rounding of s = rho v and s / rho.
+    Reconstructing the momenta themselves misses this by far."""
+    rng = np.random.default_rng(61)
+    k, j, i = np.meshgrid(np.arange(NB), np.arange(NB), np.arange(NB), indexing="ij")
+    rho = rng.uniform(0.5, 2.0, (NB, NB, NB))
+    coef = np.array([[-0.4, 0.07, 0.0, 0.0],      # v_x = c0 + c1 i + c2 j + c3 k
+                     [0.3, 0.0, -0.05, 0.02],
+                     [0.1, 0.03, 0.04, -0.06]])
+    v = np.stack([c[0] + c[1] * i + c[2] * j + c[3] * k for c in coef])
+    blk = _block_from_velocity(rho, v, rng)
+    Qv, Qc = _recon(blk, VEL), _recon(blk, 0)
+    cells = np.meshgrid(np.arange(2, 12), np.arange(2, 12), np.arange(2, 12), indexing="ij")
+    ck, cj, ci = (x.astype(float) for x in cells)
+    worst_v = worst_c = 0.0
+    for d in DIRS:
+        n = _slot(*d)
+        for a in range(3):
+            c = coef[a]
+            vq = c[0] + c[1] * (ci + 0.5 * d[0]) + c[2] * (cj + 0.5 * d[1]) + c[3] * (ck + 0.5 * d[2])
+            want = Qv[0, n] * vq
+            scale = Qv[0, n] * np.max(np.abs(v[a]))
+            worst_v = max(worst_v, float(np.max(np.abs(Qv[1 + a, n] - want) / scale)))
+            worst_c = max(worst_c, float(np.max(np.abs(Qc[1 + a, n] - Qc[0, n] * vq) / scale)))
+    assert worst_v <= 1e-14, worst_v
+    assert worst_c > 1e-3, worst_c
+
+
+def test_velocity_flag_leaves_other_fields_alone():
+    b = inputs.config3(N=16).subset([0, 5])
+    Q0, _ = oracle.reconstruct(b.U, b.offset, b.h, b.n_species, b.fstride)
+    Q1, _ = oracle.reconstruct(b.U, b.offset, b.h, b.n_species, b.fstride, flags=VEL)
+    Q0, Q1 = Q0.reshape(2, 11, 26, 1000), Q1.reshape(2, 11, 26, 1000)
+    keep = [0, 4, 5, 6, 7, 8, 9, 10]
+    assert np.array_equal(Q0[:, keep], Q1[:, keep])
+    assert not np.array_equal(Q0[:, 1:4], Q1[:, 1:4])
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_velocity_step_mirror_symmetry_bitwise(axis):
+    b = inputs.config1(seed=21)
+    blk = np.array(b.block(0))
+
+    def mirror(x):
+        out = np.flip(x, axis=3 - axis).copy()
+        out[1 + axis] *= -1.0
+        return out
+
+    Uo, amax, _ = oracle.step(b.U, b.offset, b.h, b.n_species, b.fstride, b.dt, flags=VEL)
+    bm = inputs.pack_blocks([mirror(blk)], [b.h[0]], dt=b.dt)
+    Um, amax_m, _ = oracle.step(bm.U, bm.offset, bm.h, bm.n_species, bm.fstride, bm.dt, flags=VEL)
+    assert np.array_equal(np.array(b.block(0, Uo)), mirror(np.array(bm.block(0, Um))))
+    assert amax[0] == amax_m[0]
+
+
+def test_velocity_step_conserves_on_a_periodic_box():
+    """A rotating-star box made periodic: the shared faces telescope with the
+    option as without it."""
+    from mesh_util import box_batch, interiors_to_global
+    c3 = inputs.config3(N=16)
+    G = interiors_to_global(c3, c3.U, (2, 2, 2))
+    b = box_batch(G, (2, 2, 2), float(c3.h[0]), (True, True, True), dt=float(c3.dt))
+    U1, _, st = oracle.step(b.U, b.offset, b.h, b.n_species, b.fstride, b.dt, flags=VEL)
+    U0, _, _ = oracle.step(b.U, b.offset, b.h, b.n_species, b.fstride, b.dt)
+    assert np.all(st == 0)
+    # a momentum's scale is sum(sqrt(rho E)) (the z momentum starts at zero)
+    mom = sum(float(np.sum(np.sqrt(b.interior(s)[0] * b.interior(s)[4]))) for s in range(b.n_sub))
+    for f in range(11):
+        tin = sum(float(np.sum(b.interior(s)[f])) for s in range(b.n_sub))
+        tout = sum(float(np.sum(b.interior(s, U1)[f])) for s in range(b.n_sub))
+        mag = mom if f in (1, 2, 3) else sum(float(np.sum(np.abs(b.interior(s)[f])))
+                                            for s in range(b.n_sub))
+        assert abs(tout - tin) <= 1e-13 * mag, f
+    assert np.max(np.abs(U1 - U0)) > 1e-9
 
 
 def _resync_case():
