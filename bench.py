@@ -320,6 +320,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-rk3", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--rk3-steps", type=int, default=10)
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-budget-gb", type=float, default=64.0)
@@ -373,6 +374,22 @@ def main():
     log(f"config3 fused: {ms_per_step:.3f} ms/step wall, kernel {kern_ms:.3f} ms, "
         f"{value:.3e} cell-updates/s, {achieved_tf:.1f} TFLOP/s, {achieved_gbps:.0f} GB/s")
     plan.close()
+    variants = None
+    if not args.no_variants:
+        # the method variants on the same batch, each captured the same way
+        variants = {}
+        for name, fl in (("kt_symmetric", hydro.KT_SYMMETRIC), ("velocity", hydro.VELOCITY),
+                         ("velocity+kt_symmetric", hydro.VELOCITY | hydro.KT_SYMMETRIC)):
+            vplan = hydro.Plan(hydro.params(dt=b.dt, flags=fl), db.struct, db.U, U_out, amax,
+                               status)
+            vwall, vper = timed_plan(vplan, max(5, args.steps // 2), args.warmup, torch)
+            vplan.close()
+            vms = float(np.mean(vper))
+            variants[name] = {"flags": fl, "kernel_ms": vms,
+                              "cell_updates_per_s": b.cell_updates / (vms * 1e-3),
+                              "relative_to_default": kern_ms / vms,
+                              "nonzero_status": int(status.any().item())}
+            log(f"variant {name}: kernel {vms:.3f} ms ({kern_ms / vms:.3f} of the default rate)")
     traffic, why = traffic_per_launch()
     if traffic is None:
         log(f"traffic: null ({why})")
@@ -408,6 +425,8 @@ def main():
                 "traffic_bytes_per_launch": None if traffic is None else traffic["bytes"],
                 "traffic_over_algorithmic": None if traffic is None else traffic["bytes"] / nbytes},
     }
+    if variants is not None:
+        result["variants"] = variants
     del U_out
     torch.cuda.empty_cache()
     if not args.no_serving:

@@ -62,6 +62,18 @@ enum { HYDRO_STATUS_RHO = 1, HYDRO_STATUS_P = 2, HYDRO_STATUS_NONFINITE = 4,
  * hence amax are the same either way. */
 enum { HYDRO_FLAG_KT_SYMMETRIC = 1 };
 
+/* HYDRO_FLAG_VELOCITY: reconstruct the velocities instead of the momenta
+ * (a variant of the piecewise-parabolic reconstruction of Sec. II,
+ * "Solvers", which names the evolved variables).  For the three momentum
+ * fields, PPM runs on v = s / rho of the cells along each line, and the
+ * momentum at a quadrature point is the density reconstructed at that point
+ * times the reconstructed velocity.  All other fields, the flux, the
+ * divergence and every layout are unchanged.  Honoured by every entry point
+ * that reconstructs: hydro_reconstruct, hydro_step, hydro_step_io,
+ * hydro_rate, hydro_rk_stage and the plans and RK3 graphs built from
+ * params with the flag. */
+enum { HYDRO_FLAG_VELOCITY = 2 };
+
 typedef struct {
     double gamma;      /* ratio of specific heats (5/3 for the paper's gas)       */
     double de_switch;  /* dual-energy switch eps: p from tau^gamma where the

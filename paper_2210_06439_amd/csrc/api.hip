@@ -50,7 +50,7 @@ int check_batch(const hydro_batch *b) {
 
 int check_common(const hydro_params *p, const hydro_batch *b) {
     if (!p || check_batch(b)) return HYDRO_EINVAL;
-    if (p->flags & ~(uint32_t)HYDRO_FLAG_KT_SYMMETRIC) return HYDRO_EINVAL;
+    if (p->flags & ~(uint32_t)(HYDRO_FLAG_KT_SYMMETRIC | HYDRO_FLAG_VELOCITY)) return HYDRO_EINVAL;
     return HYDRO_OK;
 }
 

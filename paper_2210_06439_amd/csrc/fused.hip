@@ -245,12 +245,15 @@ __device__ __forceinline__ void ppm_at(const double *win, const Line5 &l, int f,
 // Hydro fields along one line: reconstructed values and the point states at
 // both ends, written to the exchange slots as they are formed (component
 // stride 64) when `store`; with `both` false only the + point is formed.
+// With VEL the window holds the velocities s / rho in the momentum slots:
+// their PPM values are the point velocities, and the point momenta are those
+// times the point density.
 struct PlusState {
     double q[6];
     double vx, vy, p, cs;
 };
 
-template <bool store, bool both>
+template <bool store, bool both, bool VEL>
 __device__ __forceinline__ PlusState produce_hydro(const double *win, const Line5 &l,
                                                    double *pp, double *pm, double gamma,
                                                    double gm1, double de, int &bits) {
@@ -263,23 +266,38 @@ __device__ __forceinline__ PlusState produce_hydro(const double *win, const Line
     const double rhop = qp, rhom = qm;
     const double rp = recip(qp), rm = both ? recip(qm) : 1.0;
     ppm_at(win, l, 1, qp, qm);
+    const double wxp = qp, wxm = qm;
+    if (VEL) {
+        qp = rhop * wxp;
+        qm = rhom * wxm;
+    }
     ps.q[1] = qp;
     if (store) pp[64] = qp;
     if (both) pm[64] = qm;
-    const double vxp = qp * rp, vxm = qm * rm;
+    const double vxp = VEL ? wxp : qp * rp, vxm = VEL ? wxm : qm * rm;
     double ekp = qp * vxp, ekm = qm * vxm;
     ppm_at(win, l, 2, qp, qm);
+    const double wyp = qp, wym = qm;
+    if (VEL) {
+        qp = rhop * wyp;
+        qm = rhom * wym;
+    }
     ps.q[2] = qp;
     if (store) pp[2 * 64] = qp;
     if (both) pm[2 * 64] = qm;
-    const double vyp = qp * rp, vym = qm * rm;
+    const double vyp = VEL ? wyp : qp * rp, vym = VEL ? wym : qm * rm;
     ekp = fma(qp, vyp, ekp);
     ekm = fma(qm, vym, ekm);
     ppm_at(win, l, 3, qp, qm);
+    const double wzp = qp, wzm = qm;
+    if (VEL) {
+        qp = rhop * wzp;
+        qm = rhom * wzm;
+    }
     ps.q[3] = qp;
     if (store) pp[3 * 64] = qp;
     if (both) pm[3 * 64] = qm;
-    const double vzp = qp * rp, vzm = qm * rm;
+    const double vzp = VEL ? wzp : qp * rp, vzm = VEL ? wzm : qm * rm;
     ekp = fma(qp, vzp, ekp);
     ekm = fma(qm, vzm, ekm);
     ppm_at(win, l, 4, qp, qm);
@@ -459,10 +477,13 @@ struct Stage {
 };
 
 // chk collects 0 * v over the outputs: it stays 0 unless some v is not finite.
+// With VEL the momenta are read from the input (the window holds velocities).
+template <bool VEL>
 __device__ __forceinline__ void update_cell(const double *win, const double *keep, int lane,
                                             int kc, int ci, int cj, int f0, int f1,
                                             const double *Fz, double lam, bool rate,
-                                            const Stage &stg, double *Os, int fst, double &chk) {
+                                            const Stage &stg, const double *Us, double *Os,
+                                            int fst, double &chk) {
     const int cidx = opaque_v(kc * NPLANE + cj * NB + ci);
     const int fs = opaque_s(fst);
 #pragma unroll
@@ -470,7 +491,9 @@ __device__ __forceinline__ void update_cell(const double *win, const double *kee
         if (f >= f0 && f < f1) {
             const double dfz = Fz[f] - keep[f * 64 + lane];
             const double sxy = keep[(NF_MAX + f) * 64 + lane];
-            const double u = win[(kc % SLOTS) * SLOT_D + f * NPLANE + cj * NB + ci];
+            const double u = (VEL && f >= 1 && f <= 3)
+                                 ? Us[f * fs + cidx]
+                                 : win[(kc % SLOTS) * SLOT_D + f * NPLANE + cj * NB + ci];
             double v = (rate ? 0.0 : u) - lam * (sxy + dfz);
             if (stg.U0) {
                 const double u0 = stg.U0[f * fs + cidx];
@@ -484,7 +507,7 @@ __device__ __forceinline__ void update_cell(const double *win, const double *kee
 // The work of one subgrid for one field group (HYD: hydro fields and point
 // states; else: species).  Both instantiations execute the same sequence of
 // barriers, so the hydro and species waves of a workgroup stay in step.
-template <bool HYD>
+template <bool HYD, bool VEL>
 __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *zl, double *keep,
                                              double *run, int tid, int role, int nspec,
                                              const double *Us0, double *Os0, int fst0,
@@ -499,6 +522,12 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
     // without an element load a valid address and store into the slot's
     // dummy word, so the loads carry no branches and issue back to back.
     int g_off[5], l_off[5];
+    // With VEL a momentum element is stored as s / rho: its thread also loads
+    // the density of the same cell.  Momenta are elements [NPLANE, 4 NPLANE),
+    // which only the first two of a thread's five elements can be.
+    static_assert(4 * NPLANE <= 2 * NT, "momentum elements must be among q = 0, 1");
+    int r_off[2];
+    bool mom[2];
 #pragma unroll
     for (int q = 0; q < 5; q++) {
         const int e = tid + q * NT;
@@ -506,6 +535,10 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
         const bool ok = e < nf * NPLANE;
         g_off[q] = ok ? f * fst0 + c : 0;
         l_off[q] = ok ? f * NPLANE + c : NF_MAX * NPLANE;
+        if (q < 2) {
+            mom[q] = VEL && ok && f >= 1 && f <= 3;
+            r_off[q] = c;
+        }
     }
 
     lds_barrier();   // the previous subgrid's LDS reads are done
@@ -516,14 +549,27 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
         for (int pl = 0; pl < SLOTS; pl++)
 #pragma unroll
             for (int q = 0; q < 5; q++) v[pl][q] = Us0[g_off[q] + pl * NPLANE];
+        if (VEL) {
+#pragma unroll
+            for (int pl = 0; pl < SLOTS; pl++)
+#pragma unroll
+                for (int q = 0; q < 2; q++) {
+                    const double rho = Us0[r_off[q] + pl * NPLANE];
+                    if (mom[q]) v[pl][q] = v[pl][q] / rho;
+                }
+        }
 #pragma unroll
         for (int pl = 0; pl < SLOTS; pl++)
 #pragma unroll
             for (int q = 0; q < 5; q++) win[pl * SLOT_D + l_off[q]] = v[pl][q];
     }
-    double pf[5];
+    double pf[5], pr[2];
 #pragma unroll
     for (int q = 0; q < 5; q++) pf[q] = Us0[g_off[q] + 5 * NPLANE];
+    if (VEL) {
+#pragma unroll
+        for (int q = 0; q < 2; q++) pr[q] = Us0[r_off[q] + 5 * NPLANE];
+    }
     lds_barrier();
 
     double acc[2][NH];       // [0]: face + (or the ring / layer face), [1]: face -
@@ -554,7 +600,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                 if (t < 9) {
                     const Line5 l = line5(ci, cj, k, t % 3 - 1, t / 3 - 1, k == 2 ? 1 : -1);
                     if (HYD) {
-                        produce_hydro<true, false>(win, l, pp, pp, gamma, gm1, de, bits);
+                        produce_hydro<true, false, VEL>(win, l, pp, pp, gamma, gm1, de, bits);
                     } else if (nspec > 0) {
 #pragma unroll
                         for (int f = 6; f < NF_MAX; f++) {
@@ -591,7 +637,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                 if (L >= 0) {
                     const Line5 l = line5(ci, cj, k, ldx(L), ldy(L), ldz(L));
                     if (HYD) {
-                        produce_hydro<true, true>(win, l, pp, pm, gamma, gm1, de, bits);
+                        produce_hydro<true, true, VEL>(win, l, pp, pm, gamma, gm1, de, bits);
                         if (nspec > 0) {   // the last species field, to balance the pair
                             double qp, qm;
                             ppm_at(win, l, NF_MAX - 1, qp, qm);
@@ -647,7 +693,8 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                 const Line5 l = line5(ri, rj, k, dx, dy, t / 3 - 1);
                 if (HYD) {
                     const PlusState ps =
-                        produce_hydro<false, false>(win, l, nullptr, nullptr, gamma, gm1, de, bits);
+                        produce_hydro<false, false, VEL>(win, l, nullptr, nullptr, gamma, gm1, de,
+                                                        bits);
                     const double un = r_axis == 0 ? ps.vx : ps.vy;
                     acc_h_vals(acc[0], ps.q, un, ps.p, ps.cs, wt);
                     run[lane] = un;
@@ -686,11 +733,20 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
         // next step's reads; after the first face layer a barrier does.
         if (k + 3 <= 13) {
             double *dst = win + ((k + 3) % SLOTS) * SLOT_D;
+            if (VEL) {
+#pragma unroll
+                for (int q = 0; q < 2; q++)
+                    if (mom[q]) pf[q] = pf[q] / pr[q];
+            }
 #pragma unroll
             for (int q = 0; q < 5; q++) dst[l_off[q]] = pf[q];
             if (k + 4 <= 13) {
 #pragma unroll
                 for (int q = 0; q < 5; q++) pf[q] = Us[g_off[q] + (k + 4) * NPLANE];
+                if (VEL) {
+#pragma unroll
+                    for (int q = 0; q < 2; q++) pr[q] = Us[r_off[q] + (k + 4) * NPLANE];
+                }
             }
         }
         if (layer) lds_barrier();
@@ -721,8 +777,8 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                                                       xch[ZB_OFF + 3 * 64 + lane], sym);
                         combine_s(acc[0], zl + lane, 64, false, sp, nspec, Fz);
                     }
-                    update_cell(win, keep, lane, 10, ci, cj, f0, f1, Fz, lam, rate, stg, Os, fst,
-                                chk);
+                    update_cell<VEL>(win, keep, lane, 10, ci, cj, f0, f1, Fz, lam, rate, stg,
+                                     Us, Os, fst, chk);
                 }
             }
             continue;
@@ -802,8 +858,9 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                                               sym);
                 combine_s(acc[1], zl + lane, 64, false, sp, nspec, Fz);
             }
-            if (k >= 4) update_cell(win, keep, lane, k - 1, ci, cj, f0, f1, Fz, lam, rate, stg, Os, fst,
-                                    chk);
+            if (k >= 4)
+                update_cell<VEL>(win, keep, lane, k - 1, ci, cj, f0, f1, Fz, lam, rate, stg, Us,
+                                 Os, fst, chk);
 #pragma unroll
             for (int f = 0; f < NF_MAX; f++)
                 if (f >= f0 && f < f1) keep[f * 64 + lane] = Fz[f];
@@ -840,6 +897,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
 
 // ---- the kernel ---------------------------------------------------------------
 
+template <bool VEL>
 __global__ __launch_bounds__(NT, 2) void k_fused(StepArgs a, const double *__restrict__ U,
                                                  double *Uo,
                                                  double *__restrict__ amax,
@@ -887,10 +945,10 @@ __global__ __launch_bounds__(NT, 2) void k_fused(StepArgs a, const double *__res
         int bits = 0;
 
         if (hyd)
-            subgrid_body<true>(win, xch, zl, keep, run, tid, role, nspec, Us0, Os0, fst0, lam, rate, stg, sym,
+            subgrid_body<true, VEL>(win, xch, zl, keep, run, tid, role, nspec, Us0, Os0, fst0, lam, rate, stg, sym,
                                gamma, gm1, de, amax_l, bits);
         else
-            subgrid_body<false>(win, xch, zl, keep, run, tid, role, nspec, Us0, Os0, fst0, lam, rate, stg, sym,
+            subgrid_body<false, VEL>(win, xch, zl, keep, run, tid, role, nspec, Us0, Os0, fst0, lam, rate, stg, sym,
                                 gamma, gm1, de, amax_l, bits);
 
         // ---- per-subgrid speed and status
@@ -961,8 +1019,12 @@ int fused_variant_order(int v) {
 hipError_t launch_fused_step(const StepArgs &a, const double *U_in, double *U_out,
                              double *amax, int32_t *status, int variant, hipStream_t st) {
     if (a.n_sub == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fused, grid_of(a, variant), dim3(NT), 0, st, a, U_in, U_out, amax,
-                       status, kVariants[variant].order);
+    if (a.vel)
+        hipLaunchKernelGGL(k_fused<true>, grid_of(a, variant), dim3(NT), 0, st, a, U_in, U_out,
+                           amax, status, kVariants[variant].order);
+    else
+        hipLaunchKernelGGL(k_fused<false>, grid_of(a, variant), dim3(NT), 0, st, a, U_in, U_out,
+                           amax, status, kVariants[variant].order);
     return hipGetLastError();
 }
 
@@ -970,7 +1032,8 @@ hipError_t fused_kernel_node_params(const StepArgs &a, const double *U_in, doubl
                                     double *amax, int32_t *status, int variant,
                                     hipKernelNodeParams *out, void **args) {
     // args must point at storage for the kernel's arguments, filled by the caller
-    out->func = reinterpret_cast<void *>(k_fused);
+    out->func = a.vel ? reinterpret_cast<void *>(k_fused<true>)
+                      : reinterpret_cast<void *>(k_fused<false>);
     out->gridDim = grid_of(a, variant);
     out->blockDim = dim3(NT);
     out->sharedMemBytes = 0;

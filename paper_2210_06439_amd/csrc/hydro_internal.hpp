@@ -31,6 +31,7 @@ struct StepArgs {
     const int32_t *n_species;
     int32_t rate;   // 0: U_out = U + dt L(U); 1: U_out = L(U) on the interior
     int32_t sym;    // symmetric (Kurganov-Tadmor 2000) face speeds
+    int32_t vel;    // PPM of the velocities s / rho instead of the momenta
     // Runge-Kutta stage form (U0 non-null): U_out = c0 U0 + c1 (U + dt L(U)),
     // or U0 where dt == 0; dt = clock[1] when clock is non-null, else dt.
     const double *clock;
@@ -52,6 +53,7 @@ inline StepArgs make_args(const hydro_params *p, const hydro_batch *b) {
     a.n_species = b->n_species;
     a.rate = 0;
     a.sym = (p->flags & HYDRO_FLAG_KT_SYMMETRIC) ? 1 : 0;
+    a.vel = (p->flags & HYDRO_FLAG_VELOCITY) ? 1 : 0;
     a.clock = nullptr;
     a.U0 = nullptr;
     a.c0 = 0.0;

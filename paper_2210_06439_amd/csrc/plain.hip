@@ -101,12 +101,31 @@ __global__ __launch_bounds__(256) void k_reconstruct(StepArgs a, const double *_
     const int sm = 12 - line;          // slot of -d
     const int step = (dz * NB + dy) * NB + dx;
     const double *Uf = U + off + (int64_t)f * a.fstride;
+    const double *Ur = U + off;                      // density
     double *Qf = Q + q_offset[s] + (int64_t)f * 26 * QCELL;
+    const bool vel = a.vel && f >= 1 && f <= 3;
     for (int c = threadIdx.x; c < QCELL; c += blockDim.x) {
         int i = c % QN + 2, j = (c / QN) % QN + 2, k = c / (QN * QN) + 2;
         int ci = (k * NB + j) * NB + i;
         double qp, qm;
-        ppm(Uf[ci - 2 * step], Uf[ci - step], Uf[ci], Uf[ci + step], Uf[ci + 2 * step], qp, qm);
+        if (vel) {
+            // velocity option: PPM of s / rho, times the point density (the
+            // density's PPM is formed again here, as in its own block)
+            double r[5], w[5];
+            for (int m = 0; m < 5; m++) {
+                const int cm = ci + (m - 2) * step;
+                r[m] = Ur[cm];
+                w[m] = Uf[cm] / r[m];
+            }
+            double rp, rm;
+            ppm(r[0], r[1], r[2], r[3], r[4], rp, rm);
+            ppm(w[0], w[1], w[2], w[3], w[4], qp, qm);
+            qp = rp * qp;
+            qm = rm * qm;
+        } else {
+            ppm(Uf[ci - 2 * step], Uf[ci - step], Uf[ci], Uf[ci + step], Uf[ci + 2 * step], qp,
+                qm);
+        }
         Qf[sp * QCELL + c] = qp;
         Qf[sm * QCELL + c] = qm;
     }

@@ -1,6 +1,7 @@
 """Method variants on the GPU against the oracle: the symmetric-speed
-(Kurganov-Tadmor 2000) flux in the fused and the plain paths, and the
-entropy-tracer re-synchronisation."""
+(Kurganov-Tadmor 2000) flux and the velocity reconstruction in the fused and
+the plain paths (and in the captured forms), and the entropy-tracer
+re-synchronisation."""
 import numpy as np
 import pytest
 
@@ -12,6 +13,7 @@ from paper_2210_06439_amd import hydro, inputs
 pytestmark = pytest.mark.gpu
 
 SYM = hydro.KT_SYMMETRIC
+VEL = hydro.VELOCITY
 
 
 def _flow_batch():
@@ -50,6 +52,92 @@ def test_symmetric_plain_bitwise():
     _, _, Ug, ag, _ = gpu_plain(b, flags=SYM)
     Ur, ar, _ = oracle.step(b.U, b.offset, b.h, b.n_species, b.fstride, b.dt, flags=SYM)
     assert max_err_step(b, Ug, Ur) <= 1e-12 and rel(ag, ar) <= 1e-13
+
+
+@pytest.mark.parametrize("flags", [VEL, VEL | SYM])
+def test_velocity_fused_matches_oracle(flags):
+    b = _flow_batch()
+    Ug, ag, sg = gpu_step(b, flags=flags)
+    Ur, ar, sr = oracle.step(b.U, b.offset, b.h, b.n_species, b.fstride, b.dt, flags=flags)
+    assert max_err_step(b, Ug, Ur) <= 1e-12
+    assert rel(ag, ar) <= 1e-13 and np.array_equal(sg, sr)
+    U0, _, _ = gpu_step(b, flags=flags & SYM)
+    assert max_err_step(b, U0, Ur) > 1e-9
+
+
+def test_velocity_fused_launch_shapes_agree_bitwise():
+    b = _flow_batch()
+    ref = gpu_step(b, flags=VEL, variant=0)
+    for v in range(1, hydro.variant_count()):
+        got = gpu_step(b, flags=VEL, variant=v)
+        assert all(np.array_equal(x, y) for x, y in zip(got, ref)), v
+
+
+def test_velocity_plain_matches_oracle():
+    """Q is bitwise (divisions and PPM in the oracle's order); the step is
+    bitwise where no point takes the dual-energy pow, else within 1e-12."""
+    b = _flow_batch()
+    Qg, Fg, Ug, ag, sg = gpu_plain(b, flags=VEL)
+    Q, qo = oracle.reconstruct(b.U, b.offset, b.h, b.n_species, b.fstride, flags=VEL)
+    assert np.array_equal(Qg, Q)
+    Ur, ar, sr = oracle.step(b.U, b.offset, b.h, b.n_species, b.fstride, b.dt, flags=VEL)
+    assert max_err_step(b, Ug, Ur) <= 1e-12 and rel(ag, ar) <= 1e-13
+    assert np.array_equal(sg, sr)
+    rb = inputs.random_batch(4, seed=92, species=(0, 5))
+    _, _, Ug, ag, _ = gpu_plain(rb, flags=VEL)
+    Ur, ar, _ = oracle.step(rb.U, rb.offset, rb.h, rb.n_species, rb.fstride, rb.dt, flags=VEL)
+    for s in range(rb.n_sub):
+        assert np.array_equal(rb.interior(s, Ug), rb.interior(s, Ur))
+    assert np.array_equal(ag, ar)
+
+
+def test_velocity_graph_plan_matches_eager():
+    T = torch()
+    b = _flow_batch()
+    db = device_batch(b)
+    ref = gpu_step(b, flags=VEL)
+    U_out = db.U.clone()
+    amax = T.zeros(db.n_sub, dtype=T.float64, device="cuda")
+    status = T.zeros(db.n_sub, dtype=T.int32, device="cuda")
+    plan = hydro.Plan(hydro.params(dt=b.dt, flags=VEL), db.struct, db.U, U_out, amax, status)
+    for _ in range(2):
+        U_out.fill_(0.0)
+        plan.launch()
+        T.cuda.synchronize()
+        Uo = U_out.cpu().numpy()
+        for s in range(b.n_sub):
+            assert np.array_equal(b.interior(s, Uo), b.interior(s, ref[0]))
+        assert np.array_equal(amax.cpu().numpy(), ref[1])
+    plan.close()
+
+
+def test_velocity_rk3_matches_oracle_driver():
+    """Device-resident RK3 steps with the option on a periodic rotating-star
+    box, against the test-side RK3 driver around the oracle."""
+    from driver import rk3_evolve
+    from mesh_util import box_batch, interiors_to_global, refill
+    T = torch()
+    c3 = inputs.config3(N=16)
+    G = interiors_to_global(c3, c3.U, (2, 2, 2))
+    b = box_batch(G, (2, 2, 2), float(c3.h[0]), (True, True, True), dt=float(c3.dt))
+    fill = refill(b, (2, 2, 2), (True, True, True))
+
+    def step(U, dt):
+        Uo, amax, st = oracle.step(U, b.offset, b.h, b.n_species, b.fstride, dt, flags=VEL)
+        assert np.all(st == 0)
+        return Uo, amax
+
+    t_end = 1.0
+    Uo, n_or = rk3_evolve(b, step, t_end, fill, max_steps=3)
+    db = device_batch(b)
+    gm = hydro.DeviceGhostMap(*hydro.box_ghost_map(2, 2, 2))
+    rk = hydro.RK3(hydro.params(flags=VEL), db, gm, db.U, cfl=0.4, t_end=t_end)
+    rk.launch(n_or)
+    T.cuda.synchronize()
+    assert int(rk.clock[2].item()) == n_or == 3
+    assert not rk.status.any().item()
+    assert max_err_step(b, db.U.cpu().numpy(), Uo) <= 1e-12 * 3 * n_or
+    rk.close()
 
 
 def test_unknown_flag_is_rejected():
