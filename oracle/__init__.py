@@ -60,6 +60,7 @@ def lib():
         lp = ctypes.POINTER(ctypes.c_int64)
         P, B = ctypes.POINTER(Params), ctypes.POINTER(Batch)
         L.hydro_ref_ppm1d.argtypes = [dp, dp, dp]
+        L.hydro_ref_ppm1d_cw.argtypes = [P, dp, dp, dp, dp, ctypes.c_int, dp, dp]
         L.hydro_ref_state_flux.argtypes = [P, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, dp, ip]
         L.hydro_ref_face.argtypes = [P, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, ip]
         L.hydro_ref_reconstruct.argtypes = [P, B, dp, dp, lp]
@@ -71,7 +72,7 @@ def lib():
         L.hydro_ref_q_elems.restype = ctypes.c_int64
         L.hydro_ref_f_elems.argtypes = [ctypes.c_int]
         L.hydro_ref_f_elems.restype = ctypes.c_int64
-        for name in ("hydro_ref_ppm1d", "hydro_ref_state_flux", "hydro_ref_face",
+        for name in ("hydro_ref_ppm1d", "hydro_ref_ppm1d_cw", "hydro_ref_state_flux", "hydro_ref_face",
                      "hydro_ref_reconstruct", "hydro_ref_flux", "hydro_ref_divergence",
                      "hydro_ref_step", "hydro_ref_tau_resync"):
             getattr(L, name).restype = ctypes.c_int
@@ -89,6 +90,8 @@ def _f64(a):
 
 KT_SYMMETRIC = 1   # flags bit: one speed max(|u_n| + c) for both directions
 VELOCITY = 2       # flags bit: PPM of v = s / rho; point momentum = rho_q * v_q
+STEEPEN = 4        # flags bit: Colella-Woodward contact steepening (density)
+FLATTEN = 8        # flags bit: Colella-Woodward flattening in strong compressions
 
 
 def params(gamma=5.0 / 3.0, de_switch=1e-3, dt=0.0, flags=0):
@@ -115,6 +118,20 @@ def ppm1d(u):
     assert u.shape == (5,)
     qp, qm = ctypes.c_double(), ctypes.c_double()
     rc = lib().hydro_ref_ppm1d(_dp(u), ctypes.byref(qp), ctypes.byref(qm))
+    assert rc == 0
+    return qp.value, qm.value
+
+
+def ppm1d_cw(u, rho, p, un, is_density, flags, gamma=5.0 / 3.0):
+    """PPM of one line with the Colella-Woodward options in `flags`; rho, p
+    and un are the densities, pressures and line velocities of the same five
+    cells.  Returns (q+, q-)."""
+    arrs = [_f64(x) for x in (u, rho, p, un)]
+    assert all(a.shape == (5,) for a in arrs)
+    qp, qm = ctypes.c_double(), ctypes.c_double()
+    prm = params(gamma, flags=flags)
+    rc = lib().hydro_ref_ppm1d_cw(ctypes.byref(prm), *[_dp(a) for a in arrs], int(is_density),
+                                  ctypes.byref(qp), ctypes.byref(qm))
     assert rc == 0
     return qp.value, qm.value
 

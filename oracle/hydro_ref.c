@@ -27,9 +27,10 @@
  *       Simpson (3-point closed Newton-Cotes) rule.
  *   O5  divergence and forward-Euler update of the 8^3 interior.
  *   Options: the symmetric-speed (Kurganov-Tadmor 2000) flux, PPM of the
- *   velocities instead of the momenta, and the re-synchronisation of the
- *   entropy tracer from the total energy after a stage (all outside the
- *   paper's description; variants of the method).
+ *   velocities instead of the momenta, Colella-Woodward contact steepening
+ *   and flattening, and the re-synchronisation of the entropy tracer from the
+ *   total energy after a stage (all outside the paper's description;
+ *   variants of the method).
  *
  * Floating point: IEEE binary64, compiled with -ffp-contract=off; every
  * operation is written in the order that is evaluated.
@@ -74,7 +75,25 @@ enum { REF_FLAG_KT_SYMMETRIC = 1 };
  * as it is. */
 enum { REF_FLAG_VELOCITY = 2 };
 
-static const uint32_t REF_FLAGS_KNOWN = REF_FLAG_KT_SYMMETRIC | REF_FLAG_VELOCITY;
+/* Colella-Woodward (1984) refinements of the interface values, applied
+ * before the monotonicity constraint (their Sec. 3 and 4):
+ *  - contact steepening (density only): near a contact, where the density
+ *    jump is large against the pressure jump and the second differences on
+ *    the two sides have opposite signs, the interface values move toward the
+ *    linear extrapolations of the neighbouring cells;
+ *  - flattening (all fields): in a strong compression the interface values
+ *    move toward the cell value.
+ * Both need the cell pressures along the line (ideal gas with the
+ * dual-energy switch, as at the quadrature points) and, for flattening, the
+ * velocity along the line direction. */
+enum { REF_FLAG_STEEPEN = 4, REF_FLAG_FLATTEN = 8 };
+
+static const uint32_t REF_FLAGS_KNOWN =
+    REF_FLAG_KT_SYMMETRIC | REF_FLAG_VELOCITY | REF_FLAG_STEEPEN | REF_FLAG_FLATTEN;
+
+/* The constants recommended with the method (Colella & Woodward 1984). */
+static const double CW_ETA1 = 20.0, CW_ETA2 = 0.05, CW_EPS1 = 0.01, CW_K0 = 0.1;
+static const double CW_EPS_SHOCK = 0.33, CW_OMEGA1 = 0.75, CW_OMEGA2 = 10.0;
 
 static int check_params(const hydro_ref_params *prm)
 {
@@ -119,10 +138,12 @@ static double mc_slope(double ul, double uc, double ur)
 }
 
 /*
- * PPM on the five values u[0..4] = u_{-2..2} of one line; returns the value
- * at the +half face (q+) and at the -half face (q-) of the middle cell.
+ * PPM on the five values u[0..4] = u_{-2..2} of one line with the steepening
+ * weight eta and the flattening weight flat (both 0 for classic PPM);
+ * returns the value at the +half face (q+) and at the -half face (q-) of the
+ * middle cell.
  */
-int hydro_ref_ppm1d(const double *u, double *qp_out, double *qm_out)
+static void ppm_core(const double *u, double eta, double flat, double *qp_out, double *qm_out)
 {
     const double sixth = 1.0 / 6.0;
     double s_m = mc_slope(u[0], u[1], u[2]);   /* slope at m = -1 */
@@ -131,6 +152,18 @@ int hydro_ref_ppm1d(const double *u, double *qp_out, double *qm_out)
     double u0 = u[2];
     double qp = 0.5 * (u0 + u[3]) - (s_p - s_0) * sixth;
     double qm = 0.5 * (u[1] + u0) - (s_0 - s_m) * sixth;
+    if (eta > 0.0) {
+        /* steepening: toward the neighbours' linear profiles at the faces */
+        double dm = u[1] + 0.5 * s_m;
+        double dp = u[3] - 0.5 * s_p;
+        qm = qm * (1.0 - eta) + dm * eta;
+        qp = qp * (1.0 - eta) + dp * eta;
+    }
+    if (flat > 0.0) {
+        /* flattening: toward the cell value */
+        qm = flat * u0 + (1.0 - flat) * qm;
+        qp = flat * u0 + (1.0 - flat) * qp;
+    }
     if ((qp - u0) * (u0 - qm) <= 0.0) {
         /* u0 is a local extremum: the parabola is flattened */
         qp = u0;
@@ -146,6 +179,72 @@ int hydro_ref_ppm1d(const double *u, double *qp_out, double *qm_out)
     }
     *qp_out = qp;
     *qm_out = qm;
+}
+
+int hydro_ref_ppm1d(const double *u, double *qp_out, double *qm_out)
+{
+    ppm_core(u, 0.0, 0.0, qp_out, qm_out);
+    return REF_OK;
+}
+
+/*
+ * Steepening weight of the middle cell from the densities rho[0..4] and
+ * pressures p[0..4] of the line (rho_{j-2..j+2}).  The second differences
+ * D = rho_{m+1} - 2 rho_m + rho_{m-1} at m = j-1 and j+1 must have opposite
+ * signs, the density jump rho_{j+1} - rho_{j-1} must exceed eps1 times the
+ * smaller density, and the relative density jump times gamma K0 must be at
+ * least the relative pressure jump (a contact, not a shock).  Then, on a
+ * uniform grid, eta~ = -(D_{j+1} - D_{j-1}) / (6 (rho_{j+1} - rho_{j-1})) and
+ * eta = max(0, min(eta1 (eta~ - eta2), 1)).
+ */
+static double steepen_weight(double gamma, const double *rho, const double *p)
+{
+    double d2m = rho[2] - 2.0 * rho[1] + rho[0];
+    double d2p = rho[4] - 2.0 * rho[3] + rho[2];
+    double drho = rho[3] - rho[1];
+    if (!(d2p * d2m < 0.0)) return 0.0;
+    if (!(fabs(drho) - CW_EPS1 * fmin(fabs(rho[3]), fabs(rho[1])) > 0.0)) return 0.0;
+    double jump_rho = gamma * CW_K0 * fabs(drho) / fmin(rho[3], rho[1]);
+    double jump_p = fabs(p[3] - p[1]) / fmin(p[3], p[1]);
+    if (!(jump_rho >= jump_p)) return 0.0;
+    double et = -(d2p - d2m) / (6.0 * drho);
+    return fmax(0.0, fmin(CW_ETA1 * (et - CW_ETA2), 1.0));
+}
+
+/*
+ * Flattening weight of the middle cell from the pressures p[0..4] and the
+ * velocities un[0..4] along the line direction: nonzero only in a
+ * compression (un_{j-1} > un_{j+1}) with a relative pressure jump
+ * |p_{j+1} - p_{j-1}| / min(p_{j+1}, p_{j-1}) above eps; then
+ * max(0, min(1, omega2 ((p_{j+1} - p_{j-1}) / (p_{j+2} - p_{j-2}) - omega1))).
+ * (The method also takes the larger weight of the upstream neighbour; that
+ * needs pressures three cells away, beyond the ghost layers of the cells
+ * reconstructed here, so the cell's own weight is used.)
+ */
+static double flatten_weight(const double *p, const double *un)
+{
+    double dp1 = p[3] - p[1];
+    if (!(un[1] - un[3] > 0.0)) return 0.0;
+    if (!(fabs(dp1) / fmin(p[3], p[1]) > CW_EPS_SHOCK)) return 0.0;
+    double ratio = dp1 / (p[4] - p[0]);
+    return fmax(0.0, fmin(1.0, CW_OMEGA2 * (ratio - CW_OMEGA1)));
+}
+
+/*
+ * One line with the Colella-Woodward options of prm->flags: u[5] are the
+ * field's values, rho[5], p[5] and un[5] the densities, pressures and
+ * velocities along the line of the same cells; `is_density` enables the
+ * steepening.
+ */
+int hydro_ref_ppm1d_cw(const hydro_ref_params *prm, const double *u, const double *rho,
+                       const double *p, const double *un, int is_density,
+                       double *qp_out, double *qm_out)
+{
+    if (!prm || !u || !rho || !p || !un || !qp_out || !qm_out) return REF_EINVAL;
+    double eta = 0.0, flat = 0.0;
+    if ((prm->flags & REF_FLAG_STEEPEN) && is_density) eta = steepen_weight(prm->gamma, rho, p);
+    if (prm->flags & REF_FLAG_FLATTEN) flat = flatten_weight(p, un);
+    ppm_core(u, eta, flat, qp_out, qm_out);
     return REF_OK;
 }
 
@@ -293,12 +392,32 @@ static int check_batch(const hydro_ref_batch *b)
 
 /* ---- per-subgrid stages ------------------------------------------------- */
 
+/* Pressure and velocity of one cell, with the point-state formulas of O3. */
+static void cell_state(const hydro_ref_params *prm, const double *U, int fstride, int c,
+                       double *p, double v[3])
+{
+    const int64_t fs = fstride;
+    double rho = U[F_RHO * fs + c];
+    double sx = U[(F_SX + 0) * fs + c], sy = U[(F_SX + 1) * fs + c], sz = U[(F_SX + 2) * fs + c];
+    double r = 1.0 / rho;
+    v[0] = sx * r;
+    v[1] = sy * r;
+    v[2] = sz * r;
+    double ek = 0.5 * ((sx * v[0] + sy * v[1]) + sz * v[2]);
+    double E = U[F_EGAS * fs + c];
+    double ei = E - ek;
+    if (ei < prm->de_switch * E) ei = pow(U[F_TAU * fs + c], prm->gamma);
+    *p = (prm->gamma - 1.0) * ei;
+}
+
 /* O2 over one subgrid: Q for cells [2,12)^3, all 26 directions, nf fields.
  * Density is reconstructed first, so that the velocity option can scale the
  * reconstructed velocities by the density at the same point. */
-static void reconstruct_subgrid(const double *U, int fstride, int nf, uint32_t flags,
-                                double *Q)
+static void reconstruct_subgrid(const hydro_ref_params *prm, const double *U, int fstride,
+                                int nf, double *Q)
 {
+    const uint32_t flags = prm->flags;
+    const int cw = (flags & (REF_FLAG_STEEPEN | REF_FLAG_FLATTEN)) != 0;
     const double *Urho = U + (int64_t)F_RHO * fstride;
     for (int f = 0; f < nf; f++) {
         const double *Uf = U + (int64_t)f * fstride;
@@ -312,13 +431,22 @@ static void reconstruct_subgrid(const double *U, int fstride, int nf, uint32_t f
             for (int k = 2; k < 12; k++)
             for (int j = 2; j < 12; j++)
             for (int i = 2; i < 12; i++) {
-                double u[5];
+                double u[5], rho[5], p[5], un[5];
                 for (int m = -2; m <= 2; m++) {
                     int c = cell_index(i + m * dx, j + m * dy, k + m * dz);
                     u[m + 2] = vel ? Uf[c] / Urho[c] : Uf[c];
+                    if (cw) {
+                        double v[3];
+                        cell_state(prm, U, fstride, c, &p[m + 2], v);
+                        rho[m + 2] = Urho[c];
+                        un[m + 2] = (dx * v[0] + dy * v[1]) + dz * v[2];
+                    }
                 }
                 double qp, qm;
-                hydro_ref_ppm1d(u, &qp, &qm);
+                if (cw)
+                    hydro_ref_ppm1d_cw(prm, u, rho, p, un, f == F_RHO, &qp, &qm);
+                else
+                    hydro_ref_ppm1d(u, &qp, &qm);
                 if (vel) {
                     qp = Q[q_index(F_RHO, sp, i, j, k)] * qp;
                     qm = Q[q_index(F_RHO, sm, i, j, k)] * qm;
@@ -425,7 +553,7 @@ int hydro_ref_reconstruct(const hydro_ref_params *prm, const hydro_ref_batch *b,
     if (check_params(prm) != REF_OK || check_batch(b) != REF_OK) return REF_EINVAL;
     if (b->n_sub > 0 && (!U || !Q || !q_offset)) return REF_EINVAL;
     for (int s = 0; s < b->n_sub; s++)
-        reconstruct_subgrid(U + b->offset[s], b->fstride, 6 + b->n_species[s], prm->flags,
+        reconstruct_subgrid(prm, U + b->offset[s], b->fstride, 6 + b->n_species[s],
                             Q + q_offset[s]);
     return REF_OK;
 }
@@ -469,7 +597,7 @@ int hydro_ref_step(const hydro_ref_params *prm, const hydro_ref_batch *b,
     for (int s = 0; s < b->n_sub; s++) {
         int nf = 6 + b->n_species[s];
         const double *U = U_in + b->offset[s];
-        reconstruct_subgrid(U, b->fstride, nf, prm->flags, Q);
+        reconstruct_subgrid(prm, U, b->fstride, nf, Q);
         double a;
         int bits = flux_subgrid(prm, Q, nf, F, &a);
         bits |= divergence_subgrid(F, U, U_out + b->offset[s], b->fstride, nf,

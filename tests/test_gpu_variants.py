@@ -143,7 +143,7 @@ def test_velocity_rk3_matches_oracle_driver():
 def test_unknown_flag_is_rejected():
     b = inputs.config1()
     with pytest.raises(hydro.HydroError):
-        gpu_step(b, flags=8)
+        gpu_step(b, flags=16)
 
 
 def test_tau_resync_matches_oracle():

@@ -1,0 +1,246 @@
+"""Colella-Woodward (1984) contact steepening and flattening in the oracle's
+PPM: hand-computed single-line cases with exact rational answers (full and
+partial weights, each gate of the two detectors), exactness on smooth data,
+mirror symmetry, an advected contact that stays sharper, and Sod's tube."""
+import numpy as np
+import pytest
+
+import oracle
+from driver import density_profile, rk3_evolve, sod_refill
+from paper_2210_06439_amd import inputs
+import riemann
+
+ST, FL = oracle.STEEPEN, oracle.FLATTEN
+ONES = np.ones(5)
+ZERO = np.zeros(5)
+
+
+def line(u, rho=None, p=ONES, un=ZERO, density=True, flags=ST | FL):
+    rho = u if rho is None else rho
+    return oracle.ppm1d_cw(u, rho, p, un, density, flags)
+
+
+# ---- steepening ------------------------------------------------------------------
+
+def test_smeared_contact_is_fully_steepened():
+    """rho = 1, 1, 1.5, 2, 2 at uniform pressure: D_{j-1} = 1/2, D_{j+1} = -1/2,
+    eta~ = 1/6, so eta = min(20 (1/6 - 0.05), 1) = 1 and the interface values
+    are the neighbours' (flat) profiles: q- = 1, q+ = 2.  Classic PPM gives
+    7/4 + 1/12 and 5/4 - 1/12."""
+    u = np.array([1.0, 1.0, 1.5, 2.0, 2.0])
+    assert line(u) == (2.0, 1.0)
+    qp, qm = line(u, flags=0)
+    assert abs(qp - (1.75 + 1.0 / 12.0)) <= 4e-16 and abs(qm - (1.25 - 1.0 / 12.0)) <= 4e-16
+    assert oracle.ppm1d(u) == (qp, qm)
+    # only the density is steepened
+    assert line(u, rho=u, density=False) == (qp, qm)
+
+
+def test_partial_steepening_rational_case():
+    """rho = 0.95, 1, 1.25, 2, 2.5: D = 0.2 and -0.25, eta~ = 0.45 / 6 = 0.075,
+    eta = 1/2.  Slopes 0.1, 0.5, 0.625 give classic q- = 1.125 - 0.4/6 and
+    q+ = 1.625 - 0.125/6; the steepened q- = (q- + 1.05)/2 = 253/240 and
+    q+ = (q+ + 1.6875)/2, after which the overshoot test resets
+    q+ = 3 (1.25) - 2 q- = 394/240."""
+    u = np.array([0.95, 1.0, 1.25, 2.0, 2.5])
+    qp, qm = line(u, flags=ST)
+    assert abs(qm - 253.0 / 240.0) <= 1e-15 and abs(qp - 394.0 / 240.0) <= 1e-15
+
+
+def test_steepening_gates():
+    u = np.array([1.0, 1.0, 1.5, 2.0, 2.0])
+    classic = oracle.ppm1d(u)
+    # a pressure jump as large as the density jump: a shock, not a contact
+    # (gamma K0 |drho| / min rho = 1/6 < |dp| / min p = 1)
+    assert line(u, p=np.array([1.0, 1.0, 1.5, 2.0, 2.0]), flags=ST) == classic
+    # a pressure jump just under gamma K0 |drho| / min rho keeps the steepening
+    assert line(u, p=np.array([1.0, 1.0, 1.0, 1.16, 1.16]), flags=ST) == (2.0, 1.0)
+    # second differences of the same sign (a parabola): no contact
+    v = np.array([1.0, 1.25, 1.75, 2.5, 3.5])
+    assert line(v, flags=ST) == oracle.ppm1d(v)
+    # a jump under eps1 = 1% of the density: left alone
+    w = 1.0 + 0.004 * np.array([0.0, 0.0, 1.0, 2.0, 2.0])
+    assert line(w, flags=ST) == oracle.ppm1d(w)
+
+
+# ---- flattening --------------------------------------------------------------------
+
+def test_strong_compression_is_fully_flattened():
+    """p = 1, 1, 1, 10, 10 and u_{j-1} > u_{j+1}: the jump ratio is 9/9 = 1,
+    so the weight is min(1, 10 (1 - 0.75)) = 1 and every field's interface
+    values are the cell value."""
+    p = np.array([1.0, 1.0, 1.0, 10.0, 10.0])
+    un = np.array([0.0, 1.0, 0.5, 0.0, 0.0])
+    for u in (np.array([0.3, 0.5, 0.9, 1.0, 1.4]), np.array([5.0, 4.0, 2.0, 1.5, 1.0])):
+        assert line(u, rho=ONES, p=p, un=un, density=False, flags=FL) == (u[2], u[2])
+    # an expansion with the same pressures is not flattened
+    u = np.array([0.3, 0.5, 0.9, 1.0, 1.4])
+    assert line(u, rho=ONES, p=p, un=-un, density=False, flags=FL) == oracle.ppm1d(u)
+
+
+def test_partial_flattening_rational_case():
+    """p = 1, 2, 5, 15, 17: (15 - 2) / (17 - 1) = 13/16, weight
+    10 (13/16 - 3/4) = 5/8.  Linear u = 1..5 (classic faces 2.5 and 3.5)
+    moves 5/8 of the way to 3: q- = 2.8125, q+ = 3.1875, exactly."""
+    p = np.array([1.0, 2.0, 5.0, 15.0, 17.0])
+    un = np.array([0.0, 0.2, 0.0, -0.2, 0.0])
+    u = np.array([1.0, 2.0, 3.0, 4.0, 5.0])
+    assert line(u, rho=ONES, p=p, un=un, density=False, flags=FL) == (3.1875, 2.8125)
+
+
+def test_flattening_gates():
+    u = np.array([1.0, 2.0, 3.0, 4.0, 5.0])
+    un = np.array([0.0, 0.2, 0.0, -0.2, 0.0])
+    classic = oracle.ppm1d(u)
+    # relative pressure jump 0.3 < eps = 0.33: not a shock
+    p = np.array([1.0, 1.0, 1.15, 1.3, 1.3])
+    assert line(u, rho=ONES, p=p, un=un, density=False, flags=FL) == classic
+    # a smooth pressure rise (ratio 1/2 < omega1): weight 0
+    p = np.array([1.0, 2.0, 3.0, 4.0, 5.0])
+    assert line(u, rho=ONES, p=p, un=un, density=False, flags=FL) == classic
+    # a falling pressure (shock facing the other way) is detected the same
+    p = np.array([17.0, 15.0, 5.0, 2.0, 1.0])
+    assert line(u, rho=ONES, p=p, un=un, density=False, flags=FL) == (3.1875, 2.8125)
+
+
+def test_reversal_swaps_faces_with_both_options():
+    rng = np.random.default_rng(70)
+    for _ in range(300):
+        u = rng.uniform(0.5, 2.0, 5)
+        p = rng.uniform(0.2, 3.0, 5)
+        un = rng.normal(0.0, 1.0, 5)
+        qp, qm = line(u, rho=u, p=p, un=un)
+        # the mirrored line: values reversed, velocities reversed and negated
+        rp, rm = line(u[::-1].copy(), rho=u[::-1].copy(), p=p[::-1].copy(),
+                      un=-un[::-1].copy())
+        assert (rp, rm) == (qm, qp)
+
+
+# ---- whole subgrids ------------------------------------------------------------------
+
+NB = 14
+
+
+def test_smooth_subgrid_data_unchanged_by_the_options():
+    """Linear conserved fields: second differences vanish (no steepening) and
+    the pressure rises smoothly (jump ratio near 1/2: no flattening), so Q is
+    bitwise the classic one."""
+    rng = np.random.default_rng(71)
+    k, j, i = np.meshgrid(np.arange(NB), np.arange(NB), np.arange(NB), indexing="ij")
+    a = np.array([1.0, 0.1, -0.2, 0.05, 3.0, 1.2, 0.1, 0.1, 0.1, 0.1, 0.1])
+    beta = rng.uniform(-0.02, 0.02, (11, 3))
+    blk = np.stack([a[f] + beta[f, 0] * i + beta[f, 1] * j + beta[f, 2] * k for f in range(11)])
+    b = inputs.pack_blocks([blk], [0.125])
+    Q0, _ = oracle.reconstruct(b.U, b.offset, b.h, b.n_species, b.fstride)
+    Q1, _ = oracle.reconstruct(b.U, b.offset, b.h, b.n_species, b.fstride, flags=ST | FL)
+    assert np.array_equal(Q0, Q1)
+
+
+def test_options_act_on_a_rough_subgrid():
+    b = inputs.config1(seed=72)
+    Q0, _ = oracle.reconstruct(b.U, b.offset, b.h, b.n_species, b.fstride)
+    Qs, _ = oracle.reconstruct(b.U, b.offset, b.h, b.n_species, b.fstride, flags=ST)
+    Qf, _ = oracle.reconstruct(b.U, b.offset, b.h, b.n_species, b.fstride, flags=FL)
+    Q0, Qs, Qf = (q.reshape(11, 26, 1000) for q in (Q0, Qs, Qf))
+    # steepening touches the density only
+    assert np.array_equal(Qs[1:], Q0[1:]) and not np.array_equal(Qs[0], Q0[0])
+    assert not np.array_equal(Qf[1:], Q0[1:])
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_step_mirror_symmetry_with_options(axis):
+    b = inputs.config1(seed=21)
+    blk = np.array(b.block(0))
+
+    def mirror(x):
+        out = np.flip(x, axis=3 - axis).copy()
+        out[1 + axis] *= -1.0
+        return out
+
+    Uo, amax, _ = oracle.step(b.U, b.offset, b.h, b.n_species, b.fstride, b.dt, flags=ST | FL)
+    bm = inputs.pack_blocks([mirror(blk)], [b.h[0]], dt=b.dt)
+    Um, amax_m, _ = oracle.step(bm.U, bm.offset, bm.h, bm.n_species, bm.fstride, bm.dt,
+                                flags=ST | FL)
+    assert np.array_equal(np.array(b.block(0, Uo)), mirror(np.array(bm.block(0, Um))))
+    assert amax[0] == amax_m[0]
+
+
+# ---- evolution: an advected contact and Sod's tube ------------------------------------
+
+GAMMA = 5.0 / 3.0
+LEFT, RIGHT = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
+NG, NI = 3, 8
+
+
+def _contact_chain(N):
+    """A density square wave (2 on [1/4, 3/4), 1 elsewhere) in uniform flow
+    u = 1 at uniform pressure 1, periodic along x: a pure contact pair, whose
+    exact solution after t = 1/2 is the same wave shifted by 1/2."""
+    h = 1.0 / N
+    blocks = []
+    for s in range(N // NI):
+        x = np.mod((s * NI + np.arange(NB) - NG + 0.5) * h, 1.0)
+        rho1 = np.where((x >= 0.25) & (x < 0.75), 2.0, 1.0)
+        rho = np.broadcast_to(rho1.reshape(1, 1, NB), (NB, NB, NB)).copy()
+        one, zero = np.ones_like(rho), np.zeros_like(rho)
+        blocks.append(inputs.conserved_from_primitive(rho, one, zero, zero, one, []))
+    return inputs.pack_blocks(blocks, [h] * (N // NI))
+
+
+def _evolve(b, flags, t_end, refill):
+    def step(U, dt):
+        Uo, amax, st = oracle.step(U, b.offset, b.h, b.n_species, b.fstride, dt, flags=flags)
+        assert np.all(st == 0)
+        return Uo, amax
+
+    U, _ = rk3_evolve(b, step, t_end, refill)
+    return U
+
+
+def test_advected_contact_stays_sharper_with_steepening():
+    """After the contacts have moved 16 cells (N = 32), classic PPM spreads
+    each over 4 cells (density strictly between 1.05 and 1.95) and steepening
+    keeps each to 2; the L1 error falls by a third.  No cell is compressed, so
+    flattening changes nothing."""
+    N = 32
+    x = (np.arange(N) + 0.5) / N
+    exact = np.where((x >= 0.25) & (x < 0.75), 1.0, 2.0)
+    out = {}
+    for fl in (0, ST, ST | FL):
+        b = _contact_chain(N)
+        U = _evolve(b, fl, 0.5, lambda U, b=b: inputs.fill_ghosts_periodic_chain(b, U, 0, False))
+        out[fl] = np.concatenate([b.interior(s, U)[0][0, 0, :] for s in range(b.n_sub)])
+
+    def spread(r):
+        return int(np.sum((r > 1.05) & (r < 1.95)))
+
+    def l1(r):
+        return float(np.mean(np.abs(r - exact)))
+
+    assert spread(out[0]) == 8 and spread(out[ST]) == 4, (spread(out[0]), spread(out[ST]))
+    assert l1(out[ST]) < 0.75 * l1(out[0]), (l1(out[ST]), l1(out[0]))
+    assert np.array_equal(out[ST | FL], out[ST])
+
+
+def _sod(N, flags, t_end=0.2):
+    b = inputs.sod_chain(N, axis=0)
+    U = _evolve(b, flags, t_end, sod_refill(b, 0))
+    rho = density_profile(b, U, 0)
+    edges = np.arange(N + 1) / N
+    exact = riemann.cell_average_density(edges, t_end, 0.5, LEFT, RIGHT, GAMMA)
+    return rho, exact
+
+
+def test_sod_with_the_options():
+    """Flattening acts at the shock (the profile changes) without raising the
+    L1 error by more than 5%; with both options the error is no larger than
+    the classic scheme's, and the density stays within the initial bounds."""
+    N = 64
+    rho0, exact = _sod(N, 0)
+    rho_f, _ = _sod(N, FL)
+    rho_sf, _ = _sod(N, ST | FL)
+    l1 = [float(np.mean(np.abs(r - exact))) for r in (rho0, rho_f, rho_sf)]
+    assert not np.array_equal(rho_f, rho0)
+    assert l1[1] <= 1.05 * l1[0] and l1[2] <= l1[0], l1
+    for r in (rho_f, rho_sf):
+        assert r.min() >= 0.125 * (1 - 1e-9) and r.max() <= 1.0 + 1e-9

@@ -98,7 +98,7 @@ def test_symmetric_step_keeps_uniform_state_and_conserves():
 
 def test_unknown_flag_rejected():
     b = inputs.config1()
-    prm = oracle.params(flags=8)
+    prm = oracle.params(flags=16)
     ba = oracle._BatchArgs(b.offset, b.h, b.n_species, b.fstride)
     out = np.zeros_like(b.U)
     amax = np.zeros(1)
