@@ -132,11 +132,16 @@ def plain_batched_stages(torch, hydro, db, prm, reps=5):
     u_bytes = int(np.sum(nf * 2744 * 8))
     q_bytes, f_bytes = qn * 8, fn * 8
     i_bytes = int(np.sum(nf * 512 * 8))
+    prm_cw = hydro.params(gamma=prm.gamma, de_switch=prm.de_switch, dt=prm.dt,
+                          flags=prm.flags | hydro.STEEPEN | hydro.FLATTEN)
     stages = {
         "reconstruct": (lambda: hydro.reconstruct(prm, db.struct, db.U, Q, qo), u_bytes + q_bytes),
         "flux": (lambda: hydro.flux(prm, db.struct, Q, qo, F, fo, amax), q_bytes + f_bytes),
         "divergence": (lambda: hydro.divergence(prm, db.struct, F, fo, db.U, U_out),
                        f_bytes + 2 * i_bytes),
+        # the Colella-Woodward options run in this form only
+        "reconstruct_steepen_flatten": (lambda: hydro.reconstruct(prm_cw, db.struct, db.U, Q, qo),
+                                        u_bytes + q_bytes),
     }
     out = {}
     stream = torch.cuda.current_stream()

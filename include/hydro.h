@@ -74,6 +74,31 @@ enum { HYDRO_FLAG_KT_SYMMETRIC = 1 };
  * params with the flag. */
 enum { HYDRO_FLAG_VELOCITY = 2 };
 
+/* HYDRO_FLAG_STEEPEN, HYDRO_FLAG_FLATTEN: the Colella-Woodward (1984)
+ * refinements of the piecewise-parabolic reconstruction, applied to the
+ * interface values of each line before the monotonicity constraint.
+ *   STEEPEN (density only): near a contact -- the density's second
+ *   differences on the two sides of the cell have opposite signs, the
+ *   density jump rho_{j+1} - rho_{j-1} exceeds 1% of the smaller density, and
+ *   gamma K0 |jump| / min(rho) >= |p_{j+1} - p_{j-1}| / min(p) with K0 = 0.1 --
+ *   the interface values move toward the neighbours' linear profiles with the
+ *   weight eta = clamp(20 (eta~ - 0.05), 0, 1),
+ *   eta~ = -(D_{j+1} - D_{j-1}) / (6 (rho_{j+1} - rho_{j-1})).
+ *   FLATTEN (all fields): in a compression along the line (u_{j-1} > u_{j+1},
+ *   u the velocity along the line direction) with
+ *   |p_{j+1} - p_{j-1}| / min(p) > 0.33, the interface values move toward the
+ *   cell value with the weight
+ *   clamp(10 ((p_{j+1} - p_{j-1}) / (p_{j+2} - p_{j-2}) - 0.75), 0, 1).
+ * Pressures are the cells' own (ideal gas with the dual-energy switch).  The
+ * method's extra step that takes the larger flattening weight of the upstream
+ * neighbour needs pressures three cells away, beyond the ghost layers of the
+ * reconstructed cells; the cell's own weight is used.  These two options are
+ * honoured by the plain form (hydro_reconstruct); the fused entry points
+ * (hydro_step, hydro_step_variant, hydro_step_io, hydro_autotune,
+ * hydro_plan_create, hydro_rate, hydro_rk_stage, hydro_rk3_create) return
+ * HYDRO_EINVAL for them. */
+enum { HYDRO_FLAG_STEEPEN = 4, HYDRO_FLAG_FLATTEN = 8 };
+
 typedef struct {
     double gamma;      /* ratio of specific heats (5/3 for the paper's gas)       */
     double de_switch;  /* dual-energy switch eps: p from tau^gamma where the

@@ -50,7 +50,18 @@ int check_batch(const hydro_batch *b) {
 
 int check_common(const hydro_params *p, const hydro_batch *b) {
     if (!p || check_batch(b)) return HYDRO_EINVAL;
-    if (p->flags & ~(uint32_t)(HYDRO_FLAG_KT_SYMMETRIC | HYDRO_FLAG_VELOCITY)) return HYDRO_EINVAL;
+    if (p->flags & ~(uint32_t)(HYDRO_FLAG_KT_SYMMETRIC | HYDRO_FLAG_VELOCITY | HYDRO_FLAG_STEEPEN |
+                               HYDRO_FLAG_FLATTEN))
+        return HYDRO_EINVAL;
+    return HYDRO_OK;
+}
+
+// The fused kernel has no room for the cell pressures the Colella-Woodward
+// options need: its entry points refuse them.
+int check_fused(const hydro_params *p, const hydro_batch *b) {
+    int rc = check_common(p, b);
+    if (rc) return rc;
+    if (p->flags & (HYDRO_FLAG_STEEPEN | HYDRO_FLAG_FLATTEN)) return HYDRO_EINVAL;
     return HYDRO_OK;
 }
 
@@ -178,7 +189,7 @@ const char *hydro_variant_name(int variant) { return fused_variant_name(variant)
 
 int hydro_step_variant(const hydro_params *params, const hydro_batch *batch, const double *U_in,
                        double *U_out, double *amax, int32_t *status, int variant, void *stream) {
-    int rc = check_common(params, batch);
+    int rc = check_fused(params, batch);
     if (rc) return rc;
     if (variant < 0 || variant >= fused_variant_count()) return HYDRO_EINVAL;
     if (batch->n_sub == 0) return HYDRO_OK;
@@ -210,7 +221,7 @@ int hydro_step(const hydro_params *params, const hydro_batch *batch, const doubl
 int hydro_step_io(const hydro_params *params, const hydro_batch *batch,
                   const int64_t *out_offset, const double *U_in, double *U_out,
                   double *amax, int32_t *status, void *stream) {
-    int rc = check_common(params, batch);
+    int rc = check_fused(params, batch);
     if (rc) return rc;
     if (batch->n_sub == 0) return HYDRO_OK;
     if (!out_offset || !U_in || !U_out || !amax || !aligned8(U_in) || !aligned8(U_out))
@@ -227,7 +238,7 @@ int hydro_step_io(const hydro_params *params, const hydro_batch *batch,
 int hydro_autotune(const hydro_params *params, const hydro_batch *batch, const double *U_in,
                    double *U_out, double *amax, int32_t *status, int reps, float *times_ms,
                    void *stream) {
-    int rc = check_common(params, batch);
+    int rc = check_fused(params, batch);
     if (rc) return rc;
     if (batch->n_sub == 0 || reps < 1) return HYDRO_EINVAL;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -274,7 +285,7 @@ int hydro_plan_create(const hydro_params *params, const hydro_batch *batch, cons
                       double *U_out, double *amax, int32_t *status, void *stream,
                       hydro_plan **plan_out) {
     (void)stream;
-    int rc = check_common(params, batch);
+    int rc = check_fused(params, batch);
     if (rc) return rc;
     if (!plan_out || batch->n_sub == 0 || !U_in || !U_out || !amax || U_in == U_out)
         return HYDRO_EINVAL;
@@ -344,7 +355,7 @@ int hydro_fill_ghosts(const hydro_batch *batch, const hydro_ghost_map *map, doub
 
 int hydro_rate(const hydro_params *params, const hydro_batch *batch, const double *U_in,
                double *R, double *amax, int32_t *status, void *stream) {
-    int rc = check_common(params, batch);
+    int rc = check_fused(params, batch);
     if (rc) return rc;
     if (batch->n_sub == 0) return HYDRO_OK;
     if (!U_in || !R || !amax || U_in == R || !aligned8(U_in) || !aligned8(R)) return HYDRO_EINVAL;
@@ -371,7 +382,7 @@ int hydro_cfl_dt(const hydro_batch *batch, const double *amax, double cfl, doubl
 int hydro_rk_stage(const hydro_params *params, const hydro_batch *batch, const double *U_in,
                    double *U_out, const double *U0, double a, double b, const double *clock,
                    double *amax, int32_t *status, void *stream) {
-    int rc = check_common(params, batch);
+    int rc = check_fused(params, batch);
     if (rc) return rc;
     if (batch->n_sub == 0) return HYDRO_OK;
     if (!U_in || !U_out || !U0 || !clock || !amax || U_in == U_out || !aligned8(U_in) ||
@@ -453,7 +464,7 @@ int hydro_rk3_create(const hydro_params *params, const hydro_batch *batch,
                      double *amax, int32_t *status, double *clock, double cfl, double t_end,
                      void *stream, hydro_rk3 **plan_out) {
     (void)stream;
-    int rc = check_common(params, batch);
+    int rc = check_fused(params, batch);
     if (rc) return rc;
     if (!plan_out || batch->n_sub == 0 || !map || !map->src || !map->mode || !U || !U1 || !U2 ||
         !R || !amax || !clock || !(cfl > 0.0))

@@ -32,6 +32,7 @@ struct StepArgs {
     int32_t rate;   // 0: U_out = U + dt L(U); 1: U_out = L(U) on the interior
     int32_t sym;    // symmetric (Kurganov-Tadmor 2000) face speeds
     int32_t vel;    // PPM of the velocities s / rho instead of the momenta
+    int32_t steepen, flatten;   // Colella-Woodward options (plain path only)
     // Runge-Kutta stage form (U0 non-null): U_out = c0 U0 + c1 (U + dt L(U)),
     // or U0 where dt == 0; dt = clock[1] when clock is non-null, else dt.
     const double *clock;
@@ -54,6 +55,8 @@ inline StepArgs make_args(const hydro_params *p, const hydro_batch *b) {
     a.rate = 0;
     a.sym = (p->flags & HYDRO_FLAG_KT_SYMMETRIC) ? 1 : 0;
     a.vel = (p->flags & HYDRO_FLAG_VELOCITY) ? 1 : 0;
+    a.steepen = (p->flags & HYDRO_FLAG_STEEPEN) ? 1 : 0;
+    a.flatten = (p->flags & HYDRO_FLAG_FLATTEN) ? 1 : 0;
     a.clock = nullptr;
     a.U0 = nullptr;
     a.c0 = 0.0;

@@ -82,6 +82,97 @@ __device__ inline void ppm(double um2, double um1, double u0, double up1, double
     }
 }
 
+// ---- Colella-Woodward (1984) refinements of the interface values ------------
+// Contact steepening (density) and flattening (all fields), applied to the
+// fourth-order interface values before the monotonicity constraint.  They
+// need the pressures of the five cells of the line (ideal gas with the
+// dual-energy switch, the point-state formulas) and the velocities along the
+// line direction; the constants are the ones recommended with the method.
+
+constexpr double CW_ETA1 = 20.0, CW_ETA2 = 0.05, CW_EPS1 = 0.01, CW_K0 = 0.1;
+constexpr double CW_EPS_SHOCK = 0.33, CW_OMEGA1 = 0.75, CW_OMEGA2 = 10.0;
+
+// Pressure and velocity along (dx, dy, dz) of cell c of a subgrid.
+__device__ inline void cell_p_un(const StepArgs &a, const double *Us, int c, int dx, int dy,
+                                 int dz, double &p, double &un) {
+    const int64_t fs = a.fstride;
+    const double rho = Us[c];
+    const double sx = Us[fs + c], sy = Us[2 * fs + c], sz = Us[3 * fs + c];
+    const double r = 1.0 / rho;
+    const double vx = sx * r, vy = sy * r, vz = sz * r;
+    const double ek = 0.5 * ((sx * vx + sy * vy) + sz * vz);
+    const double E = Us[4 * fs + c];
+    double ei = E - ek;
+    if (ei < a.de_switch * E) ei = pow(Us[5 * fs + c], a.gamma);
+    p = (a.gamma - 1.0) * ei;
+    un = (dx * vx + dy * vy) + dz * vz;
+}
+
+// Steepening weight of the middle cell: a contact (opposite second
+// differences of the density on the two sides, a density jump above eps1 of
+// the smaller density and at least the relative pressure jump / (gamma K0)),
+// then eta = clamp(eta1 (eta~ - eta2), 0, 1) with
+// eta~ = -(D_{j+1} - D_{j-1}) / (6 (rho_{j+1} - rho_{j-1})).
+__device__ inline double steepen_weight(double gamma, const double *rho, const double *p) {
+    const double d2m = rho[2] - 2.0 * rho[1] + rho[0];
+    const double d2p = rho[4] - 2.0 * rho[3] + rho[2];
+    const double drho = rho[3] - rho[1];
+    if (!(d2p * d2m < 0.0)) return 0.0;
+    if (!(fabs(drho) - CW_EPS1 * fmin(fabs(rho[3]), fabs(rho[1])) > 0.0)) return 0.0;
+    const double jump_rho = gamma * CW_K0 * fabs(drho) / fmin(rho[3], rho[1]);
+    const double jump_p = fabs(p[3] - p[1]) / fmin(p[3], p[1]);
+    if (!(jump_rho >= jump_p)) return 0.0;
+    const double et = -(d2p - d2m) / (6.0 * drho);
+    return fmax(0.0, fmin(CW_ETA1 * (et - CW_ETA2), 1.0));
+}
+
+// Flattening weight of the middle cell: in a compression along the line with
+// a relative pressure jump above eps,
+// clamp(omega2 ((p_{j+1} - p_{j-1}) / (p_{j+2} - p_{j-2}) - omega1), 0, 1).
+// (The neighbour's weight, which needs pressures three cells away, beyond
+// the ghost layers of the reconstructed cells, is not taken.)
+__device__ inline double flatten_weight(const double *p, const double *un) {
+    const double dp1 = p[3] - p[1];
+    if (!(un[1] - un[3] > 0.0)) return 0.0;
+    if (!(fabs(dp1) / fmin(p[3], p[1]) > CW_EPS_SHOCK)) return 0.0;
+    const double ratio = dp1 / (p[4] - p[0]);
+    return fmax(0.0, fmin(1.0, CW_OMEGA2 * (ratio - CW_OMEGA1)));
+}
+
+// PPM with the steepening weight eta and the flattening weight flat.
+__device__ inline void ppm_cw(const double *u, double eta, double flat, double &qp,
+                              double &qm) {
+    const double sixth = 1.0 / 6.0;
+    const double s_m = mc_slope(u[0], u[1], u[2]);
+    const double s_0 = mc_slope(u[1], u[2], u[3]);
+    const double s_p = mc_slope(u[2], u[3], u[4]);
+    const double u0 = u[2];
+    qp = 0.5 * (u0 + u[3]) - (s_p - s_0) * sixth;
+    qm = 0.5 * (u[1] + u0) - (s_0 - s_m) * sixth;
+    if (eta > 0.0) {
+        const double dm = u[1] + 0.5 * s_m;
+        const double dp = u[3] - 0.5 * s_p;
+        qm = qm * (1.0 - eta) + dm * eta;
+        qp = qp * (1.0 - eta) + dp * eta;
+    }
+    if (flat > 0.0) {
+        qm = flat * u0 + (1.0 - flat) * qm;
+        qp = flat * u0 + (1.0 - flat) * qp;
+    }
+    if ((qp - u0) * (u0 - qm) <= 0.0) {
+        qp = u0;
+        qm = u0;
+    } else {
+        const double dq = qp - qm;
+        const double m6 = 6.0 * (u0 - 0.5 * (qm + qp));
+        if (dq * m6 > dq * dq) {
+            qm = 3.0 * u0 - 2.0 * qp;
+        } else if (-(dq * dq) > dq * m6) {
+            qp = 3.0 * u0 - 2.0 * qm;
+        }
+    }
+}
+
 // One block per (subgrid, field, line); threads stride over the 1000 cells.
 __global__ __launch_bounds__(256) void k_reconstruct(StepArgs a, const double *__restrict__ U,
                                                      double *__restrict__ Q,
@@ -104,11 +195,30 @@ __global__ __launch_bounds__(256) void k_reconstruct(StepArgs a, const double *_
     const double *Ur = U + off;                      // density
     double *Qf = Q + q_offset[s] + (int64_t)f * 26 * QCELL;
     const bool vel = a.vel && f >= 1 && f <= 3;
+    const bool cw = a.steepen || a.flatten;
     for (int c = threadIdx.x; c < QCELL; c += blockDim.x) {
         int i = c % QN + 2, j = (c / QN) % QN + 2, k = c / (QN * QN) + 2;
         int ci = (k * NB + j) * NB + i;
         double qp, qm;
-        if (vel) {
+        if (cw) {
+            double u[5], rho[5], p[5], un[5];
+            for (int m = 0; m < 5; m++) {
+                const int cm = ci + (m - 2) * step;
+                rho[m] = Ur[cm];
+                u[m] = vel ? Uf[cm] / rho[m] : Uf[cm];
+                cell_p_un(a, Ur, cm, dx, dy, dz, p[m], un[m]);
+            }
+            const double eta = (a.steepen && f == 0) ? steepen_weight(a.gamma, rho, p) : 0.0;
+            const double flat = a.flatten ? flatten_weight(p, un) : 0.0;
+            ppm_cw(u, eta, flat, qp, qm);
+            if (vel) {
+                // the density's own values at the two points, with the same weights
+                double rp, rm;
+                ppm_cw(rho, a.steepen ? steepen_weight(a.gamma, rho, p) : 0.0, flat, rp, rm);
+                qp = rp * qp;
+                qm = rm * qm;
+            }
+        } else if (vel) {
             // velocity option: PPM of s / rho, times the point density (the
             // density's PPM is formed again here, as in its own block)
             double r[5], w[5];

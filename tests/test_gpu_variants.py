@@ -1,7 +1,7 @@
 """Method variants on the GPU against the oracle: the symmetric-speed
 (Kurganov-Tadmor 2000) flux and the velocity reconstruction in the fused and
-the plain paths (and in the captured forms), and the entropy-tracer
-re-synchronisation."""
+the plain paths (and in the captured forms), Colella-Woodward steepening and
+flattening in the plain path, and the entropy-tracer re-synchronisation."""
 import numpy as np
 import pytest
 
@@ -14,6 +14,7 @@ pytestmark = pytest.mark.gpu
 
 SYM = hydro.KT_SYMMETRIC
 VEL = hydro.VELOCITY
+ST, FL = hydro.STEEPEN, hydro.FLATTEN
 
 
 def _flow_batch():
@@ -138,6 +139,46 @@ def test_velocity_rk3_matches_oracle_driver():
     assert not rk.status.any().item()
     assert max_err_step(b, db.U.cpu().numpy(), Uo) <= 1e-12 * 3 * n_or
     rk.close()
+
+
+@pytest.mark.parametrize("flags", [ST, FL, ST | FL, ST | FL | VEL, ST | FL | SYM])
+def test_cw_options_plain_matches_oracle(flags):
+    """Random states (both detectors fire often, no dual-energy pow): Q, F and
+    the step are bitwise the oracle's.  Rotating-star subgrids (the pow of
+    the dual-energy cells comes from each side's libm): within 1e-12."""
+    rb = inputs.random_batch(4, seed=93, species=(0, 5))
+    Qg, Fg, Ug, ag, sg = gpu_plain(rb, flags=flags)
+    Q, qo = oracle.reconstruct(rb.U, rb.offset, rb.h, rb.n_species, rb.fstride, flags=flags)
+    assert np.array_equal(Qg, Q)
+    Q0, _ = oracle.reconstruct(rb.U, rb.offset, rb.h, rb.n_species, rb.fstride,
+                               flags=flags & (VEL | SYM))
+    assert not np.array_equal(Q, Q0)
+    Ur, ar, sr = oracle.step(rb.U, rb.offset, rb.h, rb.n_species, rb.fstride, rb.dt, flags=flags)
+    for s in range(rb.n_sub):
+        assert np.array_equal(rb.interior(s, Ug), rb.interior(s, Ur))
+    assert np.array_equal(ag, ar) and np.array_equal(sg, sr)
+    b = _flow_batch()
+    Qg, _, Ug, ag, sg = gpu_plain(b, flags=flags)
+    Q, _ = oracle.reconstruct(b.U, b.offset, b.h, b.n_species, b.fstride, flags=flags)
+    assert np.max(np.abs(Qg - Q) / np.maximum(np.abs(Q), 1e-300)) <= 1e-12
+    Ur, ar, sr = oracle.step(b.U, b.offset, b.h, b.n_species, b.fstride, b.dt, flags=flags)
+    assert max_err_step(b, Ug, Ur) <= 1e-12 and rel(ag, ar) <= 1e-13
+    assert np.array_equal(sg, sr)
+
+
+@pytest.mark.parametrize("flags", [ST, FL, ST | VEL])
+def test_cw_options_refused_by_the_fused_forms(flags):
+    T = torch()
+    b = inputs.config1()
+    db = device_batch(b)
+    with pytest.raises(hydro.HydroError):
+        gpu_step(b, flags=flags, db=db)
+    out = db.U.clone()
+    amax = T.zeros(db.n_sub, dtype=T.float64, device="cuda")
+    with pytest.raises(hydro.HydroError):
+        hydro.rate(hydro.params(flags=flags), db.struct, db.U, out, amax)
+    with pytest.raises(hydro.HydroError):
+        hydro.Plan(hydro.params(dt=b.dt, flags=flags), db.struct, db.U, out, amax)
 
 
 def test_unknown_flag_is_rejected():
