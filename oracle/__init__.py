@@ -21,18 +21,26 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hydro_ref.c")
 _LIB = os.path.join(_HERE, "libhydro_ref.so")
+SUBGRID_SIZES = (8, 16)     # interior cells per dimension; 8 is the default
 
 CFLAGS = ["-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
           "-fno-fast-math", "-Wall", "-Wextra"]
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc into ``oracle/libhydro_ref.so``."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.run(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"], check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+def lib_path(n: int = 8) -> str:
+    return _LIB if n == 8 else os.path.join(_HERE, f"libhydro_ref_n{n}.so")
+
+
+def build(force: bool = False, n: int | None = None) -> str:
+    """Compile the oracle with gcc into ``oracle/libhydro_ref.so`` (subgrid
+    size 8) and ``libhydro_ref_n16.so`` (size 16); returns the size-n path."""
+    for m in (SUBGRID_SIZES if n is None else (n,)):
+        path = lib_path(m)
+        if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+            tmp = path + ".tmp"
+            subprocess.run(["gcc", *CFLAGS, f"-DREF_N={m}", "-o", tmp, _SRC, "-lm"], check=True)
+            os.replace(tmp, path)
+    return lib_path(8 if n is None else n)
 
 
 class Params(ctypes.Structure):
@@ -47,14 +55,13 @@ class Batch(ctypes.Structure):
                 ("n_species", ctypes.POINTER(ctypes.c_int32))]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        build()
-        L = ctypes.CDLL(_LIB)
+def lib(n: int = 8):
+    if n not in _libs:
+        assert n in SUBGRID_SIZES, n
+        L = ctypes.CDLL(build(n=n))
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int32)
         lp = ctypes.POINTER(ctypes.c_int64)
@@ -72,12 +79,15 @@ def lib():
         L.hydro_ref_q_elems.restype = ctypes.c_int64
         L.hydro_ref_f_elems.argtypes = [ctypes.c_int]
         L.hydro_ref_f_elems.restype = ctypes.c_int64
+        L.hydro_ref_subgrid_n.argtypes = []
+        L.hydro_ref_subgrid_n.restype = ctypes.c_int
+        assert L.hydro_ref_subgrid_n() == n
         for name in ("hydro_ref_ppm1d", "hydro_ref_ppm1d_cw", "hydro_ref_state_flux", "hydro_ref_face",
                      "hydro_ref_reconstruct", "hydro_ref_flux", "hydro_ref_divergence",
                      "hydro_ref_step", "hydro_ref_tau_resync"):
             getattr(L, name).restype = ctypes.c_int
-        _lib = L
-    return _lib
+        _libs[n] = L
+    return _libs[n]
 
 
 def _dp(a):
@@ -166,12 +176,12 @@ def face(VL, VR, axis, gamma=5.0 / 3.0, de_switch=1e-3, flags=0):
     return Fbar, a.value, st.value
 
 
-def q_elems(n_species):
-    return int(lib().hydro_ref_q_elems(int(n_species)))
+def q_elems(n_species, n=8):
+    return int(lib(n).hydro_ref_q_elems(int(n_species)))
 
 
-def f_elems(n_species):
-    return int(lib().hydro_ref_f_elems(int(n_species)))
+def f_elems(n_species, n=8):
+    return int(lib(n).hydro_ref_f_elems(int(n_species)))
 
 
 def packed_offsets(sizes):
@@ -181,32 +191,34 @@ def packed_offsets(sizes):
     return off
 
 
-def reconstruct(U, offset, h, n_species, fstride, gamma=5.0 / 3.0, de_switch=1e-3, flags=0):
-    """Q for every subgrid, packed; returns (Q, q_offset)."""
+def reconstruct(U, offset, h, n_species, fstride, gamma=5.0 / 3.0, de_switch=1e-3, flags=0,
+                n=8):
+    """Q for every subgrid, packed; returns (Q, q_offset).  n: subgrid size."""
     U = _f64(U)
     ba = _BatchArgs(offset, h, n_species, fstride)
-    q_off = packed_offsets([q_elems(ns) for ns in ba.n_species])
-    total = int(q_off[-1] + q_elems(ba.n_species[-1])) if len(q_off) else 0
+    q_off = packed_offsets([q_elems(ns, n) for ns in ba.n_species])
+    total = int(q_off[-1] + q_elems(ba.n_species[-1], n)) if len(q_off) else 0
     Q = np.zeros(total)
     prm = params(gamma, de_switch, flags=flags)
-    rc = lib().hydro_ref_reconstruct(ctypes.byref(prm), ctypes.byref(ba.struct), _dp(U), _dp(Q),
+    rc = lib(n).hydro_ref_reconstruct(ctypes.byref(prm), ctypes.byref(ba.struct), _dp(U), _dp(Q),
                                      q_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
     assert rc == 0, rc
     return Q, q_off
 
 
-def flux(Q, q_offset, offset, h, n_species, fstride, gamma=5.0 / 3.0, de_switch=1e-3, flags=0):
+def flux(Q, q_offset, offset, h, n_species, fstride, gamma=5.0 / 3.0, de_switch=1e-3, flags=0,
+         n=8):
     """Face fluxes; returns (F, f_offset, amax, status)."""
     Q = _f64(Q)
     q_offset = np.ascontiguousarray(q_offset, dtype=np.int64)
     ba = _BatchArgs(offset, h, n_species, fstride)
-    f_off = packed_offsets([f_elems(ns) for ns in ba.n_species])
-    total = int(f_off[-1] + f_elems(ba.n_species[-1])) if len(f_off) else 0
+    f_off = packed_offsets([f_elems(ns, n) for ns in ba.n_species])
+    total = int(f_off[-1] + f_elems(ba.n_species[-1], n)) if len(f_off) else 0
     F = np.zeros(total)
     amax = np.zeros(len(ba.offset))
     status = np.zeros(len(ba.offset), dtype=np.int32)
     prm = params(gamma, de_switch, flags=flags)
-    rc = lib().hydro_ref_flux(ctypes.byref(prm), ctypes.byref(ba.struct), _dp(Q),
+    rc = lib(n).hydro_ref_flux(ctypes.byref(prm), ctypes.byref(ba.struct), _dp(Q),
                               q_offset.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(F),
                               f_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(amax),
                               status.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
@@ -215,32 +227,33 @@ def flux(Q, q_offset, offset, h, n_species, fstride, gamma=5.0 / 3.0, de_switch=
 
 
 def divergence(F, f_offset, U_in, offset, h, n_species, fstride, dt,
-               gamma=5.0 / 3.0, de_switch=1e-3):
+               gamma=5.0 / 3.0, de_switch=1e-3, n=8):
     """U_out from face fluxes; ghosts of U_out are copied from U_in."""
     F, U_in = _f64(F), _f64(U_in)
     f_offset = np.ascontiguousarray(f_offset, dtype=np.int64)
     ba = _BatchArgs(offset, h, n_species, fstride)
     U_out = U_in.copy()
     prm = params(gamma, de_switch, dt)
-    rc = lib().hydro_ref_divergence(ctypes.byref(prm), ctypes.byref(ba.struct), _dp(F),
+    rc = lib(n).hydro_ref_divergence(ctypes.byref(prm), ctypes.byref(ba.struct), _dp(F),
                                     f_offset.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                     _dp(U_in), _dp(U_out))
     assert rc == 0, rc
     return U_out
 
 
-def step(U_in, offset, h, n_species, fstride, dt, gamma=5.0 / 3.0, de_switch=1e-3, flags=0):
+def step(U_in, offset, h, n_species, fstride, dt, gamma=5.0 / 3.0, de_switch=1e-3, flags=0,
+         n=8):
     """One forward-Euler hydro stage; returns (U_out, amax, status).
 
     Ghost cells of U_out are copies of U_in (the step never writes them)."""
     U_in = _f64(U_in)
     ba = _BatchArgs(offset, h, n_species, fstride)
     U_out = U_in.copy()
-    n = len(ba.offset)
-    amax = np.zeros(n)
-    status = np.zeros(n, dtype=np.int32)
+    nsub = len(ba.offset)
+    amax = np.zeros(nsub)
+    status = np.zeros(nsub, dtype=np.int32)
     prm = params(gamma, de_switch, dt, flags)
-    rc = lib().hydro_ref_step(ctypes.byref(prm), ctypes.byref(ba.struct), _dp(U_in),
+    rc = lib(n).hydro_ref_step(ctypes.byref(prm), ctypes.byref(ba.struct), _dp(U_in),
                               _dp(U_out), _dp(amax),
                               status.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
     assert rc == 0, rc

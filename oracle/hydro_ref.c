@@ -25,7 +25,11 @@
  *   O4  central-upwind flux with one-sided speeds a+/a- taken per face
  *       over the face's 9 surface points, integrated with the tensor
  *       Simpson (3-point closed Newton-Cotes) rule.
- *   O5  divergence and forward-Euler update of the 8^3 interior.
+ *   O5  divergence and forward-Euler update of the N^3 interior.
+ *
+ * Subgrid size (Sec. II, "Data-Structure": 8^3 cells by default, a
+ * compile-time choice): REF_N interior cells per dimension, 8 unless the
+ * file is compiled with -DREF_N=<n>; 3 ghost layers on each side.
  *   Options: the symmetric-speed (Kurganov-Tadmor 2000) flux, PPM of the
  *   velocities instead of the momenta, Colella-Woodward contact steepening
  *   and flattening, and the re-synchronisation of the entropy tracer from the
@@ -100,11 +104,16 @@ static int check_params(const hydro_ref_params *prm)
     return (prm && (prm->flags & ~REF_FLAGS_KNOWN) == 0) ? REF_OK : REF_EINVAL;
 }
 
-#define NB 14            /* cells per dimension incl. 3 ghost layers each side */
+#ifndef REF_N
+#define REF_N 8          /* interior cells per dimension                        */
+#endif
+#define NB (REF_N + 6)   /* cells per dimension incl. 3 ghost layers each side */
 #define NC (NB * NB * NB)
-#define QN 10            /* reconstructed cells per dimension: [2,12)          */
+#define IL 3             /* interior cells are [IL, IH) in each dimension       */
+#define IH (3 + REF_N)
+#define QN (REF_N + 2)   /* reconstructed cells per dimension: [2, IH + 1)      */
 #define QC (QN * QN * QN)
-#define NFACE 576        /* faces per axis: 9 x 8 x 8                          */
+#define NFACE ((REF_N + 1) * REF_N * REF_N)   /* faces per axis                 */
 
 static const int F_RHO = 0, F_SX = 1, F_EGAS = 4, F_TAU = 5;
 
@@ -410,7 +419,7 @@ static void cell_state(const hydro_ref_params *prm, const double *U, int fstride
     *p = (prm->gamma - 1.0) * ei;
 }
 
-/* O2 over one subgrid: Q for cells [2,12)^3, all 26 directions, nf fields.
+/* O2 over one subgrid: Q for cells [2, IH+1)^3, all 26 directions, nf fields.
  * Density is reconstructed first, so that the velocity option can scale the
  * reconstructed velocities by the density at the same point. */
 static void reconstruct_subgrid(const hydro_ref_params *prm, const double *U, int fstride,
@@ -428,9 +437,9 @@ static void reconstruct_subgrid(const hydro_ref_params *prm, const double *U, in
             int n = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1);
             if (n <= 13) continue;                   /* only the 13 lines */
             int sp = dir_slot(dx, dy, dz), sm = dir_slot(-dx, -dy, -dz);
-            for (int k = 2; k < 12; k++)
-            for (int j = 2; j < 12; j++)
-            for (int i = 2; i < 12; i++) {
+            for (int k = 2; k <= IH; k++)
+            for (int j = 2; j <= IH; j++)
+            for (int i = 2; i <= IH; i++) {
                 double u[5], rho[5], p[5], un[5];
                 for (int m = -2; m <= 2; m++) {
                     int c = cell_index(i + m * dx, j + m * dy, k + m * dz);
@@ -458,15 +467,17 @@ static void reconstruct_subgrid(const hydro_ref_params *prm, const double *U, in
     }
 }
 
-/* Index of the face with left cell (i,j,k) on `axis` inside its 576-box. */
+/* Index of the face with left cell (i,j,k) on `axis` inside its box of
+ * (N+1) x N x N faces (extent N+1 along the axis, x fastest). */
 static int face_index(int axis, int i, int j, int k)
 {
-    if (axis == 0) return ((k - 3) * 8 + (j - 3)) * 9 + (i - 2);
-    if (axis == 1) return ((k - 3) * 9 + (j - 2)) * 8 + (i - 3);
-    return ((k - 2) * 8 + (j - 3)) * 8 + (i - 3);
+    const int n = REF_N;
+    if (axis == 0) return ((k - IL) * n + (j - IL)) * (n + 1) + (i - 2);
+    if (axis == 1) return ((k - IL) * (n + 1) + (j - 2)) * n + (i - IL);
+    return ((k - 2) * n + (j - IL)) * n + (i - IL);
 }
 
-/* O4 over one subgrid: F[f][axis][576] and the subgrid's max face speed. */
+/* O4 over one subgrid: F[f][axis][NFACE] and the subgrid's max face speed. */
 static int flux_subgrid(const hydro_ref_params *prm, const double *Q, int nf,
                         double *F, double *amax_out)
 {
@@ -476,9 +487,8 @@ static int flux_subgrid(const hydro_ref_params *prm, const double *Q, int nf,
     for (int axis = 0; axis < 3; axis++) {
         int b = axis == 0 ? 1 : 0;                  /* tangential axes, b < b2 */
         int b2 = axis == 2 ? 1 : 2;
-        int lo[3] = {3, 3, 3}, hi[3] = {11, 11, 11};
-        lo[axis] = 2;                               /* left cells 2..10 */
-        hi[axis] = 11;
+        int lo[3] = {IL, IL, IL}, hi[3] = {IH, IH, IH};
+        lo[axis] = 2;                               /* left cells 2..IH-1 */
         for (int k = lo[2]; k < hi[2]; k++)
         for (int j = lo[1]; j < hi[1]; j++)
         for (int i = lo[0]; i < hi[0]; i++) {
@@ -515,7 +525,7 @@ static int flux_subgrid(const hydro_ref_params *prm, const double *Q, int nf,
     return bits;
 }
 
-/* O5 over one subgrid: U_out = U - (dt/h) ((dFx + dFy) + dFz) on [3,11)^3. */
+/* O5 over one subgrid: U_out = U - (dt/h) ((dFx + dFy) + dFz) on [IL,IH)^3. */
 static int divergence_subgrid(const double *F, const double *U, double *Uo,
                               int fstride, int nf, double dt, double h)
 {
@@ -524,9 +534,9 @@ static int divergence_subgrid(const double *F, const double *U, double *Uo,
     for (int f = 0; f < nf; f++) {
         const double *Uf = U + (int64_t)f * fstride;
         double *Of = Uo + (int64_t)f * fstride;
-        for (int k = 3; k < 11; k++)
-        for (int j = 3; j < 11; j++)
-        for (int i = 3; i < 11; i++) {
+        for (int k = IL; k < IH; k++)
+        for (int j = IL; j < IH; j++)
+        for (int i = IL; i < IH; i++) {
             const double *Fx = F + (f * 3 + 0) * NFACE;
             const double *Fy = F + (f * 3 + 1) * NFACE;
             const double *Fz = F + (f * 3 + 2) * NFACE;
@@ -544,6 +554,7 @@ static int divergence_subgrid(const double *F, const double *U, double *Uo,
 
 /* ---- the four entry points ------------------------------------------------ */
 
+int hydro_ref_subgrid_n(void) { return REF_N; }
 int64_t hydro_ref_q_elems(int n_species) { return (int64_t)26 * (6 + n_species) * QC; }
 int64_t hydro_ref_f_elems(int n_species) { return (int64_t)3 * (6 + n_species) * NFACE; }
 
@@ -625,9 +636,9 @@ int hydro_ref_tau_resync(const hydro_ref_params *prm, const hydro_ref_batch *b, 
     for (int s = 0; s < b->n_sub; s++) {
         double *Us = U + b->offset[s];
         const int64_t fs = b->fstride;
-        for (int k = 3; k < 11; k++)
-            for (int j = 3; j < 11; j++)
-                for (int i = 3; i < 11; i++) {
+        for (int k = IL; k < IH; k++)
+            for (int j = IL; j < IH; j++)
+                for (int i = IL; i < IH; i++) {
                     const int c = cell_index(i, j, k);
                     const double rho = Us[F_RHO * fs + c];
                     const double sx = Us[(F_SX + 0) * fs + c];

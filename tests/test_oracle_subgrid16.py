@@ -1,0 +1,113 @@
+"""The oracle built for 16^3 subgrids (the subgrid size is a compile-time
+choice, Sec. II "Data-Structure").  The step is local -- every interior cell
+depends only on the cells within three of it -- so one 16^3 subgrid and the
+eight 8^3 subgrids that tile it, cut from the same padded field, must give
+bitwise the same interiors, the same largest face speed and the same status
+bits.  That ties the size-16 build to the pinned size-8 one."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2210_06439_amd import inputs
+
+SYM, VEL, ST, FL = oracle.KT_SYMMETRIC, oracle.VELOCITY, oracle.STEEPEN, oracle.FLATTEN
+
+
+def _padded_field(seed, nf=11, n=16):
+    """Physical states on (n+6)^3 cells: a smooth flow plus cell noise and a
+    few density and pressure jumps, so every limiter branch and both
+    Colella-Woodward detectors fire."""
+    rng = np.random.default_rng(seed)
+    m = n + 6
+    k, j, i = np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij")
+    rho = 1.0 + 0.3 * np.sin(0.5 * i + 0.3 * j) + rng.uniform(0.0, 0.2, (m, m, m))
+    rho = np.where(i + j > 20, 3.0 * rho, rho)
+    p = 1.0 + 0.2 * np.cos(0.4 * k) + rng.uniform(0.0, 0.1, (m, m, m))
+    p = np.where(k > 12, 8.0 * p, p)
+    v = [0.3 * np.sin(0.2 * k + a) + rng.normal(0.0, 0.1, (m, m, m)) for a in range(3)]
+    v[2] = v[2] - np.where(k > 12, 0.8, 0.0)      # a compression across the pressure jump
+    sp = [rho * w for w in rng.uniform(0.0, 0.2, (nf - 6, m, m, m))]
+    return inputs.conserved_from_primitive(rho, v[0], v[1], v[2], p, sp)
+
+
+def _pack(blocks, n, h, dt):
+    """Pack [nf, n+6, n+6, n+6] blocks with a field stride of (n+6)^3 rounded
+    up to 16 doubles."""
+    nb = n + 6
+    fs = (nb ** 3 + 15) // 16 * 16
+    nf = blocks[0].shape[0]
+    U = np.zeros(len(blocks) * nf * fs)
+    off = np.arange(len(blocks), dtype=np.int64) * nf * fs
+    for b, o in zip(blocks, off):
+        for f in range(nf):
+            U[o + f * fs:o + f * fs + nb ** 3] = b[f].ravel()
+    return U, off, np.full(len(blocks), h), np.full(len(blocks), nf - 6, np.int32), fs
+
+
+def _interior(U, off, fs, nf, n, s):
+    nb = n + 6
+    return np.stack([U[off[s] + f * fs:off[s] + f * fs + nb ** 3].reshape(nb, nb, nb)
+                     [3:3 + n, 3:3 + n, 3:3 + n] for f in range(nf)])
+
+
+@pytest.mark.parametrize("flags", [0, SYM, VEL, ST | FL, VEL | ST | FL])
+def test_one_16_cube_equals_its_eight_8_cubes(flags):
+    P = _padded_field(80 + flags)
+    nf, h, dt = P.shape[0], 1.0 / 64, 2e-4
+    U16, off16, h16, ns16, fs16 = _pack([P], 16, h, dt)
+    Uo16, a16, st16 = oracle.step(U16, off16, h16, ns16, fs16, dt, flags=flags, n=16)
+    tiles = [P[:, bz * 8:bz * 8 + 14, by * 8:by * 8 + 14, bx * 8:bx * 8 + 14]
+             for bz in (0, 1) for by in (0, 1) for bx in (0, 1)]
+    U8, off8, h8, ns8, fs8 = _pack(tiles, 8, h, dt)
+    Uo8, a8, st8 = oracle.step(U8, off8, h8, ns8, fs8, dt, flags=flags)
+    big = _interior(Uo16, off16, fs16, nf, 16, 0)
+    t = 0
+    for bz in (0, 1):
+        for by in (0, 1):
+            for bx in (0, 1):
+                small = _interior(Uo8, off8, fs8, nf, 8, t)
+                assert np.array_equal(big[:, bz * 8:bz * 8 + 8, by * 8:by * 8 + 8,
+                                          bx * 8:bx * 8 + 8], small), (flags, t)
+                t += 1
+    assert a16[0] == np.max(a8)
+    assert st16[0] == np.bitwise_or.reduce(st8)
+    # and the step did something
+    assert not np.array_equal(big, P[:, 3:19, 3:19, 3:19])
+
+
+def test_layout_sizes():
+    for ns in (0, 5):
+        nf = 6 + ns
+        assert oracle.q_elems(ns, n=16) == 26 * nf * 18 ** 3
+        assert oracle.f_elems(ns, n=16) == 3 * nf * 17 * 16 * 16
+        assert oracle.q_elems(ns) == 26 * nf * 10 ** 3
+        assert oracle.f_elems(ns) == 3 * nf * 9 * 8 * 8
+
+
+def test_uniform_16_cube_unchanged():
+    V = np.array([1.3, 0.2, -0.1, 0.05, 2.7, 1.1, 0.2, 0.3, 0.4, 0.2, 0.2])
+    blk = np.broadcast_to(V[:, None, None, None], (11, 22, 22, 22)).copy()
+    U, off, h, ns, fs = _pack([blk], 16, 0.1, 0.01)
+    Uo, amax, st = oracle.step(U, off, h, ns, fs, 0.01, n=16)
+    assert np.array_equal(Uo, U) and st[0] == 0 and amax[0] > 0
+
+
+def test_undersized_field_stride_rejected():
+    import ctypes
+    ba = oracle._BatchArgs([0], [0.1], [0], 14 ** 3)       # a size-8 stride
+    prm = oracle.params()
+    out = np.zeros(6 * 22 ** 3)
+    amax = np.zeros(1)
+    rc = oracle.lib(16).hydro_ref_step(ctypes.byref(prm), ctypes.byref(ba.struct),
+                                       oracle._dp(out), oracle._dp(out.copy()),
+                                       oracle._dp(amax), None)
+    assert rc == -1
+
+
+def test_the_field_exercises_the_options():
+    P = _padded_field(90)
+    U, off, h, ns, fs = _pack([P], 16, 1.0 / 64, 2e-4)
+    Q0, _ = oracle.reconstruct(U, off, h, ns, fs, n=16)
+    for fl in (VEL, ST, FL):
+        Q1, _ = oracle.reconstruct(U, off, h, ns, fs, flags=fl, n=16)
+        assert np.count_nonzero(Q1 != Q0) > 1000, fl
