@@ -162,6 +162,49 @@ def plain_batched_stages(torch, hydro, db, prm, reps=5):
     return out
 
 
+def subgrid16_plain(torch, hydro, inputs, reps=5):
+    """The plain stages of the library built for 16^3 subgrids on the same
+    128^3 binary-star mesh (512 subgrids): time per stage and the mesh's
+    cell-update rate, beside the 8^3 build's plain stages."""
+    U, off, h, ns, fs, dt = inputs.config3_subgrid16()
+    db = hydro.DeviceBatch(U, off, h, ns, fs, n=16)
+    del U
+    prm = hydro.params(dt=dt)
+    qo, qn = db.q_layout()
+    fo, fn = db.f_layout()
+    Q = torch.zeros(qn, dtype=torch.float64, device="cuda")
+    F = torch.zeros(fn, dtype=torch.float64, device="cuda")
+    amax = torch.zeros(db.n_sub, dtype=torch.float64, device="cuda")
+    U_out = db.U.clone()
+    stages = {
+        "reconstruct": lambda: hydro.reconstruct(prm, db.struct, db.U, Q, qo, n=16),
+        "flux": lambda: hydro.flux(prm, db.struct, Q, qo, F, fo, amax, n=16),
+        "divergence": lambda: hydro.divergence(prm, db.struct, F, fo, db.U, U_out, n=16),
+    }
+    out = {"workload": "128^3 binary-star mesh: 512 subgrids of 16^3 (+3 ghosts), 11 fields"}
+    stream = torch.cuda.current_stream()
+    total = 0.0
+    for name, fn_ in stages.items():
+        fn_()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn_()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name + "_ms"] = ms
+        total += ms
+    out["ms_per_stage"] = total
+    out["cell_updates_per_s"] = db.n_sub * 16 ** 3 / (total * 1e-3)
+    log(f"plain stages at 16^3: {total:.3f} ms per stage "
+        f"({out['cell_updates_per_s']:.3e} cell-updates/s)")
+    del Q, F, U_out, db
+    torch.cuda.empty_cache()
+    return out
+
+
 def plain_vs_batched(torch, hydro, inputs, reps=3):
     """Config 2 (64^3, 512 subgrids): one subgrid per launch vs one batched launch."""
     b = inputs.config2()
@@ -454,6 +497,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_plain:
         result["plain_vs_batched"] = plain_vs_batched(torch, hydro, inputs)
+        result["subgrid16_plain"] = subgrid16_plain(torch, hydro, inputs)
     if cpu is not None:
         result["cpu_baseline"] = cpu
         result["cpu_baseline"]["gpu_over_cpu"] = value / cpu["value"]

@@ -9,6 +9,20 @@
  * on batches of 8x8x8 subgrids (Sec. II, "Data-Structure") that each carry 3
  * ghost layers, i.e. 14^3 cells per field.
  *
+ * Subgrid size.  The paper's subgrids hold 8^3 cells by default and their
+ * size is a compile-time choice (Sec. II, "Data-Structure").  Here too: the
+ * library is compiled for N interior cells per dimension, N = 8
+ * (libhydro.so) or N = 16 (libhydro_n16.so, compiled with
+ * -DHYDRO_SUBGRID_N=16), and hydro_subgrid_n() reports which.  Every size
+ * below is written for N = 8; for general N a block has N+6 cells per
+ * dimension (fstride >= (N+6)^3), the interior is [3, N+3), Q covers the
+ * cells [2, N+4)^3 ((N+2)^3 per direction), and the faces of one axis form a
+ * box of (N+1) x N x N.  The N = 16 library provides the plain stages, the
+ * entropy-tracer re-sync, the ghost fill, the CFL step size and the stage
+ * combination; its fused entry points (those that refuse the
+ * Colella-Woodward flags below) return HYDRO_EINVAL, because the fused
+ * kernel maps the 8 x 8 cells of a plane onto one 64-lane wave.
+ *
  * Conventions shared by every entry point
  * ---------------------------------------
  *  - Pointers named U, Q, F, amax, status and every array inside hydro_batch
@@ -190,9 +204,13 @@ int hydro_step_io(const hydro_params *params, const hydro_batch *batch,
                   const int64_t *out_offset, const double *U_in, double *U_out,
                   double *amax, int32_t *status, void *stream);
 
-/* Element counts of one subgrid's Q and F regions: 26*nf*1000 and 3*nf*576. */
+/* Element counts of one subgrid's Q and F regions: 26*nf*1000 and 3*nf*576
+ * (26*nf*(N+2)^3 and 3*nf*(N+1)*N*N for subgrid size N). */
 int64_t hydro_q_elems(int n_species);
 int64_t hydro_f_elems(int n_species);
+
+/* The subgrid size N this library was compiled for (8 or 16). */
+int hydro_subgrid_n(void);
 
 /* Text for a return code (static storage; HIP detail for HYDRO_ELAUNCH). */
 const char *hydro_strerror(int code);

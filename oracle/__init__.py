@@ -260,13 +260,13 @@ def step(U_in, offset, h, n_species, fstride, dt, gamma=5.0 / 3.0, de_switch=1e-
     return U_out, amax, status
 
 
-def tau_resync(U, offset, h, n_species, fstride, gamma=5.0 / 3.0, de_switch=1e-3):
+def tau_resync(U, offset, h, n_species, fstride, gamma=5.0 / 3.0, de_switch=1e-3, n=8):
     """Copy of U with the entropy tracer of every interior cell reset to
     e_i^(1/gamma) where e_i >= de_switch * E."""
     U = _f64(U).copy()
     ba = _BatchArgs(offset, h, n_species, fstride)
     prm = params(gamma, de_switch)
-    rc = lib().hydro_ref_tau_resync(ctypes.byref(prm), ctypes.byref(ba.struct), _dp(U))
+    rc = lib(n).hydro_ref_tau_resync(ctypes.byref(prm), ctypes.byref(ba.struct), _dp(U))
     assert rc == 0, rc
     return U
 

@@ -1,4 +1,7 @@
-"""Build the gfx950 hydro library: hipcc -> paper_2210_06439_amd/libhydro.so.
+"""Build the gfx950 hydro library for both subgrid sizes:
+hipcc -> paper_2210_06439_amd/libhydro.so (8^3 subgrids, every entry point)
+and paper_2210_06439_amd/libhydro_n16.so (16^3 subgrids: the plain stages and
+the time-integration helpers; the fused kernel is written for 8^3).
 
 Usage: python -m paper_2210_06439_amd.build  (always recompiles)
 """
@@ -13,7 +16,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libhydro.so")
-SOURCES = ["api.hip", "plain.hip", "fused.hip", "evolve.hip"]
+SIZES = {8: ["api.hip", "plain.hip", "fused.hip", "evolve.hip"],
+         16: ["api.hip", "plain.hip", "evolve.hip", "fused_absent.hip"]}
+SOURCES = SIZES[8]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -25,36 +30,51 @@ FLAGS = [
 ]
 
 
+def lib_path(n: int = 8) -> str:
+    return LIB if n == 8 else os.path.join(PKG, f"libhydro_n{n}.so")
+
+
 def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    objs = []
-    procs = []
-    for src in SOURCES:
-        obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-        cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
-        objs.append(obj)
+    """Compile both libraries (all sources in parallel); returns the 8^3 one."""
+    jobs = []
+    for n, sources in SIZES.items():
+        bdir = os.path.join(BUILD, f"n{n}")
+        os.makedirs(bdir, exist_ok=True)
+        objs = []
+        for src in sources:
+            obj = os.path.join(bdir, src.replace(".hip", ".o"))
+            cmd = [HIPCC, *FLAGS, f"-DHYDRO_SUBGRID_N={n}", "-c", os.path.join(CSRC, src),
+                   "-o", obj]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            jobs.append((f"{src} (N={n})",
+                         subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+            objs.append(obj)
+        SIZES_OBJS[n] = objs
     failed = []
-    for src, p in procs:
+    for name, p in jobs:
         out, _ = p.communicate()
         text = out.decode(errors="replace")
         # hipcc's host pass does not know the packed-fp32 feature flag: harmless
         lines = [ln for ln in text.splitlines() if "packed-fp32-ops" not in ln
                  and "is not a recognized feature" not in ln]
         if p.returncode != 0:
-            failed.append(src)
+            failed.append(name)
             print("\n".join(lines), file=sys.stderr)
         elif verbose and lines:
             print("\n".join(lines))
     if failed:
         raise RuntimeError(f"hipcc failed for {failed}")
-    tmp = LIB + ".tmp"
-    subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs],
-                   check=True)
-    os.replace(tmp, LIB)
+    for n in SIZES:
+        path = lib_path(n)
+        tmp = path + ".tmp"
+        subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp,
+                        *SIZES_OBJS[n]], check=True)
+        os.replace(tmp, path)
     return LIB
+
+
+SIZES_OBJS: dict = {}
 
 
 if __name__ == "__main__":

@@ -56,11 +56,12 @@ int check_common(const hydro_params *p, const hydro_batch *b) {
     return HYDRO_OK;
 }
 
-// The fused kernel has no room for the cell pressures the Colella-Woodward
-// options need: its entry points refuse them.
+// The fused kernel covers 8^3 subgrids only, and has no room for the cell
+// pressures the Colella-Woodward options need: its entry points refuse both.
 int check_fused(const hydro_params *p, const hydro_batch *b) {
     int rc = check_common(p, b);
     if (rc) return rc;
+    if (NSUB != 8) return HYDRO_EINVAL;
     if (p->flags & (HYDRO_FLAG_STEEPEN | HYDRO_FLAG_FLATTEN)) return HYDRO_EINVAL;
     return HYDRO_OK;
 }
@@ -133,6 +134,7 @@ extern "C" {
 int64_t hydro_q_elems(int n_species) { return (int64_t)26 * (6 + n_species) * QCELL; }
 int64_t hydro_f_elems(int n_species) { return (int64_t)3 * (6 + n_species) * NFACE; }
 int64_t hydro_workspace_bytes(void) { return 0; }
+int hydro_subgrid_n(void) { return NSUB; }
 
 const char *hydro_strerror(int code) {
     switch (code) {

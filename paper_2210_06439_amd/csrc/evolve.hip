@@ -9,12 +9,11 @@
 namespace hydro {
 namespace {
 
-constexpr int NG = 3;   // ghost layers
-constexpr int NI = 8;   // interior cells per dimension
+constexpr int NI = NSUB;   // interior cells per dimension
 
 // Source index along one axis of a ghost cell at index i (direction d):
 // inside the interior (d == 0) the index itself; toward a neighbour its
-// interior cell 8 cells back; at a clamped boundary the nearest interior cell.
+// interior cell N cells back; at a clamped boundary the nearest interior cell.
 __device__ __forceinline__ int ghost_src(int i, int d, bool clamp) {
     if (d == 0) return i;
     if (clamp) return i < NG ? NG : NG + NI - 1;
@@ -23,9 +22,12 @@ __device__ __forceinline__ int ghost_src(int i, int d, bool clamp) {
 
 __device__ __forceinline__ int dir_of(int i) { return i < NG ? -1 : (i >= NG + NI ? 1 : 0); }
 
-// The 2232 ghost cells of a 14^3 block, each packed as cell index (12 bits)
-// and neighbour direction slot (5 bits), built once per block in LDS.
+// The ghost cells of a block (2232 for 14^3, 6552 for 22^3), each packed as
+// cell index (14 bits) and neighbour direction slot (5 bits), built once per
+// block in LDS.
 constexpr int NGHOST = NCELL - NI * NI * NI;
+constexpr int CELL_BITS = 14;
+static_assert(NCELL <= (1 << CELL_BITS), "cell index must fit its field");
 
 // One block per (subgrid, field group): every ghost cell is copied from the
 // interior cell that the map names.  Only interior cells are read and only
@@ -46,7 +48,7 @@ __global__ __launch_bounds__(512) void k_fill_ghosts(int n_sub, int fstride,
     const int64_t off = offset[s];
     if (ns < 0 || ns > 5 || off < 0) return;
     const int nf = 6 + ns;
-    // ghost list: cell c is a ghost iff some index is outside [3, 11)
+    // ghost list: cell c is a ghost iff some index is outside [NG, NG + NI)
     for (int c = threadIdx.x; c < NCELL; c += blockDim.x) {
         const int i = c % NB, j = (c / NB) % NB, k = c / NPLANE;
         const int dx = dir_of(i), dy = dir_of(j), dz = dir_of(k);
@@ -58,7 +60,7 @@ __global__ __launch_bounds__(512) void k_fill_ghosts(int n_sub, int fstride,
         int inner = kk * NI * NI;                       // interior cells in planes below
         if (k >= NG && k < NG + NI) inner += jj * NI + ((j >= NG && j < NG + NI) ? ii : 0);
         const int n = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1);
-        ghost[c - inner] = c | (n << 12);
+        ghost[c - inner] = c | (n << CELL_BITS);
     }
     if (threadIdx.x < 27) {
         const int sb = src[s * 27 + threadIdx.x];
@@ -75,7 +77,7 @@ __global__ __launch_bounds__(512) void k_fill_ghosts(int n_sub, int fstride,
     for (int e = threadIdx.x; e < nf * NGHOST; e += blockDim.x) {
         const int f = e / NGHOST;
         const int g = ghost[e - f * NGHOST];
-        const int c = g & 0xfff, n = g >> 12;
+        const int c = g & ((1 << CELL_BITS) - 1), n = g >> CELL_BITS;
         const int64_t o2 = src_off[n];
         if (o2 < 0 || f >= src_nf[n]) {
             bad = 1;
@@ -137,17 +139,18 @@ __global__ __launch_bounds__(512) void k_rk_update(int fstride, const int64_t *_
     const int ns = n_species[s];
     const int64_t off = offset[s];
     if (ns < 0 || ns > 5 || off < 0 || f >= 6 + ns) return;
-    const int t = threadIdx.x;
-    const int i = NG + (t & 7), j = NG + ((t >> 3) & 7), k = NG + (t >> 6);
-    const int64_t idx = off + (int64_t)f * fstride + (k * NB + j) * NB + i;
     const double dt = clock[1];
-    const double u0 = U0[idx];
-    Uo[idx] = dt == 0.0 ? u0 : a * u0 + b * (Uk[idx] + dt * R[idx]);
+    for (int t = threadIdx.x; t < NINT; t += blockDim.x) {
+        const int i = NG + t % NI, j = NG + (t / NI) % NI, k = NG + t / (NI * NI);
+        const int64_t idx = off + (int64_t)f * fstride + (k * NB + j) * NB + i;
+        const double u0 = U0[idx];
+        Uo[idx] = dt == 0.0 ? u0 : a * u0 + b * (Uk[idx] + dt * R[idx]);
+    }
 }
 
 // Entropy-tracer re-synchronisation: tau = e_i^(1/gamma) where the internal
 // energy from E is reliable (e_i not below de_switch * E).  One block per
-// subgrid, a thread per interior cell; evaluated in the written order (no
+// subgrid, threads striding over the interior cells; evaluated in the written order (no
 // contraction), so the switch decides exactly as in the point state.
 __global__ __launch_bounds__(512) void k_tau_resync(StepArgs a, double *U) {
 #pragma clang fp contract(off)
@@ -155,16 +158,17 @@ __global__ __launch_bounds__(512) void k_tau_resync(StepArgs a, double *U) {
     const int ns = a.n_species[s];
     const int64_t off = a.offset[s];
     if (ns < 0 || ns > 5 || off < 0) return;
-    const int t = threadIdx.x;
-    const int i = NG + (t & 7), j = NG + ((t >> 3) & 7), k = NG + (t >> 6);
-    double *u = U + off + (k * NB + j) * NB + i;
     const int64_t fs = a.fstride;
-    const double rho = u[0], sx = u[fs], sy = u[2 * fs], sz = u[3 * fs], E = u[4 * fs];
-    const double r = 1.0 / rho;
-    const double vx = sx * r, vy = sy * r, vz = sz * r;
-    const double ek = 0.5 * ((sx * vx + sy * vy) + sz * vz);
-    const double ei = E - ek;
-    if (!(ei < a.de_switch * E)) u[5 * fs] = pow(ei, 1.0 / a.gamma);
+    for (int t = threadIdx.x; t < NINT; t += blockDim.x) {
+        const int i = NG + t % NI, j = NG + (t / NI) % NI, k = NG + t / (NI * NI);
+        double *u = U + off + (k * NB + j) * NB + i;
+        const double rho = u[0], sx = u[fs], sy = u[2 * fs], sz = u[3 * fs], E = u[4 * fs];
+        const double r = 1.0 / rho;
+        const double vx = sx * r, vy = sy * r, vz = sz * r;
+        const double ek = 0.5 * ((sx * vx + sy * vy) + sz * vz);
+        const double ei = E - ek;
+        if (!(ei < a.de_switch * E)) u[5 * fs] = pow(ei, 1.0 / a.gamma);
+    }
 }
 
 }  // namespace

@@ -28,6 +28,9 @@
 #include "hydro_internal.hpp"
 
 namespace hydro {
+
+static_assert(NSUB == 8, "the fused kernel maps the 8x8 cells of a plane onto a 64-lane wave");
+
 namespace {
 
 constexpr int NT = 512;                 // 8 waves

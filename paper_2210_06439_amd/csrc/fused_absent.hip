@@ -1,0 +1,25 @@
+// fused_absent.hip -- the fused-step symbols for builds whose subgrid size
+// the fused kernel does not cover (it maps the 8x8 cells of a plane onto one
+// 64-lane wave).  The entry points that use it refuse such builds before they
+// get here; these definitions only satisfy the linker and report failure.
+#include "hydro_internal.hpp"
+
+namespace hydro {
+
+static_assert(NSUB != 8, "the 8^3 build links fused.hip");
+
+int fused_variant_count() { return 0; }
+const char *fused_variant_name(int) { return "?"; }
+int fused_variant_order(int) { return 0; }
+
+hipError_t launch_fused_step(const StepArgs &, const double *, double *, double *, int32_t *,
+                             int, hipStream_t) {
+    return hipErrorNotSupported;
+}
+
+hipError_t fused_kernel_node_params(const StepArgs &, const double *, double *, double *,
+                                    int32_t *, int, hipKernelNodeParams *, void **) {
+    return hipErrorNotSupported;
+}
+
+}  // namespace hydro

@@ -1,7 +1,11 @@
 // hydro_internal.hpp -- internal declarations of the gfx950 hydro library.
 //
-// Geometry of one subgrid (Sec. II, "Data-Structure": 8^3 cells per leaf,
-// plus 3 ghost layers per side here): 14^3 cells per field, x fastest.
+// Geometry of one subgrid (Sec. II, "Data-Structure": 8^3 cells per leaf by
+// default, the size being a compile-time choice; 3 ghost layers per side
+// here): (N+6)^3 cells per field, x fastest.  The library is built for
+// N = 8 (libhydro.so, every entry point) and N = 16 (libhydro_n16.so, the
+// plain stages and the time-integration helpers; the fused kernel is
+// written for 8^3 subgrids).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,14 +13,22 @@
 
 #include "hydro.h"
 
+#ifndef HYDRO_SUBGRID_N
+#define HYDRO_SUBGRID_N 8
+#endif
+
 namespace hydro {
 
-constexpr int NB = 14;          // cells per dimension incl. ghosts
-constexpr int NPLANE = NB * NB; // 196 cells per z-plane
+constexpr int NSUB = HYDRO_SUBGRID_N;   // interior cells per dimension
+static_assert(NSUB == 8 || NSUB == 16, "subgrid sizes 8 and 16 are supported");
+constexpr int NG = 3;                   // ghost layers
+constexpr int NB = NSUB + 2 * NG;       // cells per dimension incl. ghosts
+constexpr int NPLANE = NB * NB;         // cells per z-plane
 constexpr int NCELL = NB * NB * NB;
-constexpr int QN = 10;          // reconstructed cells per dimension: [2,12)
+constexpr int NINT = NSUB * NSUB * NSUB;
+constexpr int QN = NSUB + 2;            // reconstructed cells per dimension: [2, NB-2)
 constexpr int QCELL = QN * QN * QN;
-constexpr int NFACE = 576;      // faces per axis: 9 x 8 x 8
+constexpr int NFACE = (NSUB + 1) * NSUB * NSUB;   // faces per axis
 constexpr int NF_MAX = 11;
 
 // Kernel-side copy of the call's scalar parameters (passed by value).

@@ -29,15 +29,17 @@ __device__ inline int dir_slot(int dx, int dy, int dz) {
     return n < 13 ? n : n - 1;
 }
 
-__device__ inline int qcell(int i, int j, int k) {   // cell in [2,12)^3 -> 0..999
+__device__ inline int qcell(int i, int j, int k) {   // cell in [2, NB-2)^3 -> 0..QCELL-1
     return ((k - 2) * QN + (j - 2)) * QN + (i - 2);
 }
 
-// Face index of the face whose left cell is (i,j,k) on `axis`.
+// Face index of the face whose left cell is (i,j,k) on `axis`: the faces of
+// an axis form a box of extent N+1 along it and N across, x fastest.
 __device__ inline int face_idx(int axis, int i, int j, int k) {
-    if (axis == 0) return ((k - 3) * 8 + (j - 3)) * 9 + (i - 2);
-    if (axis == 1) return ((k - 3) * 9 + (j - 2)) * 8 + (i - 3);
-    return ((k - 2) * 8 + (j - 3)) * 8 + (i - 3);
+    constexpr int n = NSUB;
+    if (axis == 0) return ((k - NG) * n + (j - NG)) * (n + 1) + (i - 2);
+    if (axis == 1) return ((k - NG) * (n + 1) + (j - 2)) * n + (i - NG);
+    return ((k - 2) * n + (j - NG)) * n + (i - NG);
 }
 
 __device__ inline bool meta_ok(const StepArgs &a, int s, int &nf, int64_t &off) {
@@ -173,7 +175,7 @@ __device__ inline void ppm_cw(const double *u, double eta, double flat, double &
     }
 }
 
-// One block per (subgrid, field, line); threads stride over the 1000 cells.
+// One block per (subgrid, field, line); threads stride over the QCELL cells.
 __global__ __launch_bounds__(256) void k_reconstruct(StepArgs a, const double *__restrict__ U,
                                                      double *__restrict__ Q,
                                                      const int64_t *__restrict__ q_offset) {
@@ -307,14 +309,17 @@ __global__ void k_init_outputs(int n, double *amax, int32_t *status) {
     }
 }
 
-// One block per (subgrid, 256-face chunk); 7 chunks cover 3 x 576 faces.
+// One block per (subgrid, 256-face chunk); FLUX_CHUNKS chunks cover the
+// 3 x NFACE faces.
+constexpr int FLUX_CHUNKS = (3 * NFACE + 255) / 256;
+
 __global__ __launch_bounds__(256) void k_flux(StepArgs a, const double *__restrict__ Q,
                                               const int64_t *__restrict__ q_offset,
                                               double *__restrict__ F,
                                               const int64_t *__restrict__ f_offset,
                                               double *amax, int32_t *status) {
-    const int s = blockIdx.x / 7;
-    const int chunk = blockIdx.x - s * 7;
+    const int s = blockIdx.x / FLUX_CHUNKS;
+    const int chunk = blockIdx.x - s * FLUX_CHUNKS;
     if (s >= a.n_sub) return;
     int nf;
     int64_t off;
@@ -330,13 +335,14 @@ __global__ __launch_bounds__(256) void k_flux(StepArgs a, const double *__restri
     if (face < 3 * NFACE) {
         const int axis = face / NFACE;
         const int idx = face - axis * NFACE;
+        constexpr int n = NSUB, n1 = NSUB + 1;
         int cl[3];
         if (axis == 0) {
-            cl[0] = 2 + idx % 9; cl[1] = 3 + (idx / 9) % 8; cl[2] = 3 + idx / 72;
+            cl[0] = 2 + idx % n1; cl[1] = NG + (idx / n1) % n; cl[2] = NG + idx / (n * n1);
         } else if (axis == 1) {
-            cl[0] = 3 + idx % 8; cl[1] = 2 + (idx / 8) % 9; cl[2] = 3 + idx / 72;
+            cl[0] = NG + idx % n; cl[1] = 2 + (idx / n) % n1; cl[2] = NG + idx / (n * n1);
         } else {
-            cl[0] = 3 + idx % 8; cl[1] = 3 + (idx / 8) % 8; cl[2] = 2 + idx / 64;
+            cl[0] = NG + idx % n; cl[1] = NG + (idx / n) % n; cl[2] = 2 + idx / (n * n);
         }
         int cr[3] = {cl[0], cl[1], cl[2]};
         cr[axis] += 1;
@@ -418,21 +424,23 @@ __global__ __launch_bounds__(256) void k_flux(StepArgs a, const double *__restri
     }
 }
 
-// One block per (subgrid, field, half of the 512 interior cells).
+// One block per (subgrid, field, 256 of the interior cells).
+constexpr int DIV_CHUNKS = NINT / 256;
+
 __global__ __launch_bounds__(256) void k_divergence(StepArgs a, const double *__restrict__ F,
                                                     const int64_t *__restrict__ f_offset,
                                                     const double *__restrict__ U_in,
                                                     double *__restrict__ U_out) {
-    const int per = NF_MAX * 2;
+    const int per = NF_MAX * DIV_CHUNKS;
     const int s = blockIdx.x / per;
     const int r = blockIdx.x - s * per;
-    const int f = r >> 1;
+    const int f = r / DIV_CHUNKS;
     if (s >= a.n_sub) return;
     int nf;
     int64_t off;
     if (!meta_ok(a, s, nf, off) || f >= nf) return;
-    const int c = (r & 1) * 256 + threadIdx.x;
-    const int i = 3 + c % 8, j = 3 + (c / 8) % 8, k = 3 + c / 64;
+    const int c = (r - f * DIV_CHUNKS) * 256 + threadIdx.x;
+    const int i = NG + c % NSUB, j = NG + (c / NSUB) % NSUB, k = NG + c / (NSUB * NSUB);
     const double lam = a.dt / a.h[s];
     const double *Fs = F + f_offset[s] + (int64_t)f * 3 * NFACE;
     const double *Fx = Fs, *Fy = Fs + NFACE, *Fz = Fs + 2 * NFACE;
@@ -459,15 +467,15 @@ hipError_t launch_plain_flux(const StepArgs &a, const double *Q, const int64_t *
     if (a.n_sub == 0) return hipSuccess;
     hipLaunchKernelGGL(k_init_outputs, dim3((a.n_sub + 255) / 256), dim3(256), 0, st, a.n_sub,
                        amax, status);
-    hipLaunchKernelGGL(k_flux, dim3(a.n_sub * 7), dim3(256), 0, st, a, Q, q_offset, F, f_offset,
-                       amax, status);
+    hipLaunchKernelGGL(k_flux, dim3(a.n_sub * FLUX_CHUNKS), dim3(256), 0, st, a, Q, q_offset, F,
+                       f_offset, amax, status);
     return hipGetLastError();
 }
 
 hipError_t launch_plain_divergence(const StepArgs &a, const double *F, const int64_t *f_offset,
                                    const double *U_in, double *U_out, hipStream_t st) {
     if (a.n_sub == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_divergence, dim3(a.n_sub * NF_MAX * 2), dim3(256), 0, st, a, F,
+    hipLaunchKernelGGL(k_divergence, dim3(a.n_sub * NF_MAX * DIV_CHUNKS), dim3(256), 0, st, a, F,
                        f_offset, U_in, U_out);
     return hipGetLastError();
 }

@@ -22,7 +22,7 @@ EXPORTS = [
     "hydro_plan_create", "hydro_plan_set_dt", "hydro_plan_launch", "hydro_plan_destroy",
     "hydro_fill_ghosts", "hydro_rate", "hydro_cfl_dt", "hydro_rk_update",
     "hydro_rk3_create", "hydro_rk3_launch", "hydro_rk3_destroy", "hydro_tau_resync",
-    "hydro_rk_stage", "hydro_step_io", "hydro_workspace_bytes",
+    "hydro_rk_stage", "hydro_step_io", "hydro_workspace_bytes", "hydro_subgrid_n",
 ]
 
 STATUS_RHO, STATUS_P, STATUS_NONFINITE, STATUS_BADMETA = 1, 2, 4, 8
@@ -51,16 +51,24 @@ class GhostMap(ctypes.Structure):
     _fields_ = [("src", ctypes.c_void_p), ("mode", ctypes.c_void_p)]
 
 
-_lib = None
+SUBGRID_SIZES = (8, 16)
+_libs = {}
 
 
-def lib():
-    """Load libhydro.so (raises if it is missing: the product has no CPU path)."""
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            raise HydroError(f"{LIB_PATH} is not built; run python -m paper_2210_06439_amd.build")
-        L = ctypes.CDLL(LIB_PATH)
+def lib_path(n: int = 8) -> str:
+    return LIB_PATH if n == 8 else os.path.join(_PKG, f"libhydro_n{n}.so")
+
+
+def lib(n: int = 8):
+    """Load the library for subgrid size n: libhydro.so (8) or libhydro_n16.so
+    (raises if it is missing: the product has no CPU path)."""
+    if n not in _libs:
+        if n not in SUBGRID_SIZES:
+            raise HydroError(f"no library for subgrid size {n}; built sizes: {SUBGRID_SIZES}")
+        path = lib_path(n)
+        if not os.path.exists(path):
+            raise HydroError(f"{path} is not built; run python -m paper_2210_06439_amd.build")
+        L = ctypes.CDLL(path)
         vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         P, B = ctypes.POINTER(Params), ctypes.POINTER(Batch)
         L.hydro_reconstruct.argtypes = [P, B, vp, vp, vp, vp]
@@ -77,6 +85,8 @@ def lib():
         L.hydro_f_elems.restype = i64
         L.hydro_workspace_bytes.argtypes = []
         L.hydro_workspace_bytes.restype = i64
+        L.hydro_subgrid_n.argtypes = []
+        L.hydro_subgrid_n.restype = ctypes.c_int
         L.hydro_strerror.argtypes = [ctypes.c_int]
         L.hydro_strerror.restype = ctypes.c_char_p
         L.hydro_variant_name.argtypes = [ctypes.c_int]
@@ -97,9 +107,11 @@ def lib():
         L.hydro_tau_resync.argtypes = [P, B, vp, vp]
         L.hydro_rk_stage.argtypes = [P, B, vp, vp, vp, dbl, dbl, vp, vp, vp, vp]
         L.hydro_step_io.argtypes = [P, B, vp, vp, vp, vp, vp, vp]
-        _lib = L
+        if L.hydro_subgrid_n() != n:
+            raise HydroError(f"{path} reports subgrid size {L.hydro_subgrid_n()}, not {n}")
+        _libs[n] = L
         del i32
-    return _lib
+    return _libs[n]
 
 
 def check(rc: int) -> int:
@@ -123,12 +135,12 @@ def params(gamma=5.0 / 3.0, de_switch=1e-3, dt=0.0, flags=0) -> Params:
     return Params(float(gamma), float(de_switch), float(dt), int(flags))
 
 
-def q_elems(n_species: int) -> int:
-    return int(lib().hydro_q_elems(int(n_species)))
+def q_elems(n_species: int, n: int = 8) -> int:
+    return int(lib(n).hydro_q_elems(int(n_species)))
 
 
-def f_elems(n_species: int) -> int:
-    return int(lib().hydro_f_elems(int(n_species)))
+def f_elems(n_species: int, n: int = 8) -> int:
+    return int(lib(n).hydro_f_elems(int(n_species)))
 
 
 def variant_count() -> int:
@@ -142,7 +154,7 @@ def variant_name(v: int) -> str:
 class DeviceBatch:
     """A batch of subgrids resident on the GPU: field buffer + metadata."""
 
-    def __init__(self, U, offset, h, n_species, fstride):
+    def __init__(self, U, offset, h, n_species, fstride, n: int = 8):
         import torch
         dev = torch.device("cuda")
         self.U = torch.as_tensor(U, dtype=torch.float64).to(dev)
@@ -151,6 +163,7 @@ class DeviceBatch:
         self.n_species = torch.as_tensor(np.asarray(n_species, dtype=np.int32)).to(dev)
         self.n_species_host = np.asarray(n_species, dtype=np.int32).copy()
         self.fstride = int(fstride)
+        self.n = int(n)                 # subgrid size: which library the batch is for
         self.n_sub = int(len(self.n_species_host))
         self.struct = Batch(self.n_sub, self.fstride, self.offset.data_ptr(),
                             self.h.data_ptr(), self.n_species.data_ptr())
@@ -166,11 +179,11 @@ class DeviceBatch:
                      self.n_species.data_ptr() + 4 * start)
 
     def q_layout(self):
-        sizes = [q_elems(ns) for ns in self.n_species_host]
+        sizes = [q_elems(ns, self.n) for ns in self.n_species_host]
         return _packed(sizes)
 
     def f_layout(self):
-        sizes = [f_elems(ns) for ns in self.n_species_host]
+        sizes = [f_elems(ns, self.n) for ns in self.n_species_host]
         return _packed(sizes)
 
 
@@ -183,18 +196,19 @@ def _packed(sizes):
     return torch.as_tensor(off).cuda(), total
 
 
-def reconstruct(prm: Params, batch: Batch, U, Q, q_offset, stream=None):
-    check(lib().hydro_reconstruct(ctypes.byref(prm), ctypes.byref(batch), _ptr(U), _ptr(Q),
+def reconstruct(prm: Params, batch: Batch, U, Q, q_offset, stream=None, n: int = 8):
+    check(lib(n).hydro_reconstruct(ctypes.byref(prm), ctypes.byref(batch), _ptr(U), _ptr(Q),
                                   _ptr(q_offset), _stream(stream)))
 
 
-def flux(prm: Params, batch: Batch, Q, q_offset, F, f_offset, amax, status=None, stream=None):
-    check(lib().hydro_flux(ctypes.byref(prm), ctypes.byref(batch), _ptr(Q), _ptr(q_offset),
+def flux(prm: Params, batch: Batch, Q, q_offset, F, f_offset, amax, status=None, stream=None,
+         n: int = 8):
+    check(lib(n).hydro_flux(ctypes.byref(prm), ctypes.byref(batch), _ptr(Q), _ptr(q_offset),
                            _ptr(F), _ptr(f_offset), _ptr(amax), _ptr(status), _stream(stream)))
 
 
-def divergence(prm: Params, batch: Batch, F, f_offset, U_in, U_out, stream=None):
-    check(lib().hydro_divergence(ctypes.byref(prm), ctypes.byref(batch), _ptr(F),
+def divergence(prm: Params, batch: Batch, F, f_offset, U_in, U_out, stream=None, n: int = 8):
+    check(lib(n).hydro_divergence(ctypes.byref(prm), ctypes.byref(batch), _ptr(F),
                                  _ptr(f_offset), _ptr(U_in), _ptr(U_out), _stream(stream)))
 
 
@@ -296,8 +310,8 @@ class DeviceGhostMap:
         self.struct = GhostMap(self.src.data_ptr(), self.mode.data_ptr())
 
 
-def fill_ghosts(batch: Batch, gmap: DeviceGhostMap, U, status=None, stream=None):
-    check(lib().hydro_fill_ghosts(ctypes.byref(batch), ctypes.byref(gmap.struct), _ptr(U),
+def fill_ghosts(batch: Batch, gmap: DeviceGhostMap, U, status=None, stream=None, n: int = 8):
+    check(lib(n).hydro_fill_ghosts(ctypes.byref(batch), ctypes.byref(gmap.struct), _ptr(U),
                                   _ptr(status), _stream(stream)))
 
 
@@ -306,8 +320,8 @@ def rate(prm: Params, batch: Batch, U_in, R, amax, status=None, stream=None):
                            _ptr(amax), _ptr(status), _stream(stream)))
 
 
-def cfl_dt(batch: Batch, amax, cfl, t_end, clock, stream=None):
-    check(lib().hydro_cfl_dt(ctypes.byref(batch), _ptr(amax), float(cfl), float(t_end),
+def cfl_dt(batch: Batch, amax, cfl, t_end, clock, stream=None, n: int = 8):
+    check(lib(n).hydro_cfl_dt(ctypes.byref(batch), _ptr(amax), float(cfl), float(t_end),
                              _ptr(clock), _stream(stream)))
 
 
@@ -319,8 +333,8 @@ def rk_stage(prm: Params, batch: Batch, U_in, U_out, U0, a, b, clock, amax, stat
                                _ptr(status), _stream(stream)))
 
 
-def rk_update(batch: Batch, a, U0, b, Uk, R, clock, U_out, stream=None):
-    check(lib().hydro_rk_update(ctypes.byref(batch), float(a), _ptr(U0), float(b), _ptr(Uk),
+def rk_update(batch: Batch, a, U0, b, Uk, R, clock, U_out, stream=None, n: int = 8):
+    check(lib(n).hydro_rk_update(ctypes.byref(batch), float(a), _ptr(U0), float(b), _ptr(Uk),
                                 _ptr(R), _ptr(clock), _ptr(U_out), _stream(stream)))
 
 
@@ -373,7 +387,7 @@ class RK3:
             pass
 
 
-def tau_resync(prm: Params, batch: Batch, U, stream=None):
+def tau_resync(prm: Params, batch: Batch, U, stream=None, n: int = 8):
     """Entropy tracer reset to e_i^(1/gamma) where e_i >= de_switch * E (in place)."""
-    check(lib().hydro_tau_resync(ctypes.byref(prm), ctypes.byref(batch), _ptr(U),
+    check(lib(n).hydro_tau_resync(ctypes.byref(prm), ctypes.byref(batch), _ptr(U),
                                  _stream(stream)))

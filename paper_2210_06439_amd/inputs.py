@@ -281,6 +281,36 @@ def config3(seed: int = 1003, N: int = 128) -> SubgridBatch:
     return _subgrids_from_global(G, N // NI, h, dt, "config3")
 
 
+def config3_subgrid16(seed: int = 1003, N: int = 128):
+    """Config 3's field cut into 16^3 subgrids (22^3 cells per field with the
+    ghosts, field stride 10656) for the library built for that size: 512
+    subgrids at N = 128.  Returns (U, offset, h, n_species, fstride, dt)."""
+    n, nb = 16, 22
+    fstride = (nb ** 3 + 15) // 16 * 16
+    star = BinaryStar.seeded(seed)
+    h = 1.0 / N
+    c = (np.arange(N + 2 * NG) - NG + 0.5) * h
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    G, (rho, vx, vy, vz, p) = star.conserved(X, Y, Z)
+    del X, Y, Z
+    dt = cfl_dt(rho, vx, vy, vz, p, h)
+    m = N // n
+    nf = G.shape[0]
+    U = np.zeros(m ** 3 * nf * fstride)
+    offset = np.arange(m ** 3, dtype=np.int64) * nf * fstride
+    s = 0
+    for bz in range(m):
+        for by in range(m):
+            for bx in range(m):
+                blk = G[:, bz * n:bz * n + nb, by * n:by * n + nb, bx * n:bx * n + nb]
+                o = int(offset[s])
+                for f in range(nf):
+                    U[o + f * fstride:o + f * fstride + nb ** 3] = blk[f].reshape(-1)
+                s += 1
+    return (U, offset, np.full(m ** 3, h), np.full(m ** 3, nf - 6, dtype=np.int32), fstride,
+            dt)
+
+
 # ---------------------------------------------------------------- config 4 --
 
 def config4(seed: int = 1004, launch: int = 0, max_sub: int = 8192,

@@ -23,25 +23,35 @@ def test_header_declares_the_boundary():
         assert n in names
 
 
-def test_library_exports_every_declared_symbol():
-    if not os.path.exists(hydro.LIB_PATH):
-        pytest.skip("libhydro.so not built (run __graft_entry__.build())")
-    L = ctypes.CDLL(hydro.LIB_PATH)
-    missing = [n for n in declared_functions() if not hasattr(L, n)]
+@pytest.mark.parametrize("n", [8, 16])
+def test_library_exports_every_declared_symbol(n):
+    path = hydro.lib_path(n)
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not built (run __graft_entry__.build())")
+    L = ctypes.CDLL(path)
+    missing = [f for f in declared_functions() if not hasattr(L, f)]
     assert not missing, missing
     assert sorted(hydro.EXPORTS) == sorted(declared_functions())
 
 
-def test_size_helpers_without_gpu():
-    if not os.path.exists(hydro.LIB_PATH):
-        pytest.skip("libhydro.so not built")
-    assert hydro.q_elems(5) == 286000 and hydro.f_elems(5) == 19008
-    assert hydro.lib().hydro_workspace_bytes() == 0
-    assert hydro.lib().hydro_strerror(-1) == b"invalid argument"
+@pytest.mark.parametrize("n", [8, 16])
+def test_size_helpers_without_gpu(n):
+    if not os.path.exists(hydro.lib_path(n)):
+        pytest.skip("library not built")
+    L = hydro.lib(n)
+    assert L.hydro_subgrid_n() == n
+    for ns in (0, 5):
+        nf = 6 + ns
+        assert hydro.q_elems(ns, n) == 26 * nf * (n + 2) ** 3
+        assert hydro.f_elems(ns, n) == 3 * nf * (n + 1) * n * n
+    assert L.hydro_workspace_bytes() == 0
+    assert L.hydro_strerror(-1) == b"invalid argument"
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(hydro, "LIB_PATH", str(tmp_path / "missing.so"))
-    monkeypatch.setattr(hydro, "_lib", None)
+    monkeypatch.setattr(hydro, "_libs", {})
     with pytest.raises(hydro.HydroError):
         hydro.lib()
+    with pytest.raises(hydro.HydroError):
+        hydro.lib(12)

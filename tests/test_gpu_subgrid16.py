@@ -1,0 +1,173 @@
+"""The library built for 16^3 subgrids (libhydro_n16.so; the subgrid size is
+a compile-time choice, Sec. II "Data-Structure") against the oracle built for
+the same size: the plain stages bitwise, with every method option; the
+entropy-tracer re-sync, the ghost fill and the stage combination; and the
+refusal of the fused entry points, whose kernel is written for 8^3."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import torch
+from paper_2210_06439_amd import hydro
+from test_oracle_subgrid16 import _interior, _pack, _padded_field
+
+pytestmark = pytest.mark.gpu
+
+N = 16
+NB = N + 6
+SYM, VEL, ST, FL = hydro.KT_SYMMETRIC, hydro.VELOCITY, hydro.STEEPEN, hydro.FLATTEN
+EINVAL = -1
+
+
+def _batch(seeds=(80, 81), species=(5, 0), h=1.0 / 64):
+    blocks = []
+    for seed, ns in zip(seeds, species):
+        P = _padded_field(seed)
+        blocks.append(np.concatenate([P[:6], P[6:6 + ns]]))
+    # _pack takes one nf for all blocks: pack each and concatenate
+    parts = [_pack([b], N, h, 0.0) for b in blocks]
+    U = np.concatenate([p[0] for p in parts])
+    sizes = np.array([len(p[0]) for p in parts], dtype=np.int64)
+    off = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    fs = parts[0][4]
+    return U, off, np.full(len(blocks), h), np.array(species, np.int32), fs
+
+
+def _device(U, off, h, ns, fs):
+    return hydro.DeviceBatch(U, off, h, ns, fs, n=N)
+
+
+def _plain(db, dt, flags):
+    T = torch()
+    prm = hydro.params(dt=dt, flags=flags)
+    qo, qn = db.q_layout()
+    fo, fn = db.f_layout()
+    Q = T.zeros(qn, dtype=T.float64, device="cuda")
+    F = T.zeros(fn, dtype=T.float64, device="cuda")
+    amax = T.zeros(db.n_sub, dtype=T.float64, device="cuda")
+    status = T.zeros(db.n_sub, dtype=T.int32, device="cuda")
+    U_out = db.U.clone()
+    hydro.reconstruct(prm, db.struct, db.U, Q, qo, n=N)
+    hydro.flux(prm, db.struct, Q, qo, F, fo, amax, status, n=N)
+    hydro.divergence(prm, db.struct, F, fo, db.U, U_out, n=N)
+    T.cuda.synchronize()
+    return (Q.cpu().numpy(), F.cpu().numpy(), U_out.cpu().numpy(), amax.cpu().numpy(),
+            status.cpu().numpy())
+
+
+@pytest.mark.parametrize("flags", [0, SYM, VEL, ST | FL, VEL | ST | FL])
+def test_plain_stages_bitwise(flags):
+    U, off, h, ns, fs = _batch()
+    dt = 2e-4
+    Qg, Fg, Ug, ag, sg = _plain(_device(U, off, h, ns, fs), dt, flags)
+    Q, qo = oracle.reconstruct(U, off, h, ns, fs, flags=flags, n=N)
+    assert np.array_equal(Qg, Q)
+    F, fo, a, st = oracle.flux(Q, qo, off, h, ns, fs, flags=flags, n=N)
+    assert np.array_equal(Fg, F) and np.array_equal(ag, a) and np.array_equal(sg, st)
+    Ur, ar, sr = oracle.step(U, off, h, ns, fs, dt, flags=flags, n=N)
+    for s in range(len(off)):
+        nf = 6 + int(ns[s])
+        assert np.array_equal(_interior(Ug, off, fs, nf, N, s), _interior(Ur, off, fs, nf, N, s))
+    assert np.array_equal(ag, ar)
+
+
+def test_fused_entry_points_refuse_the_16_build():
+    T = torch()
+    U, off, h, ns, fs = _batch()
+    db = _device(U, off, h, ns, fs)
+    L = hydro.lib(N)
+    out = db.U.clone()
+    amax = T.zeros(db.n_sub, dtype=T.float64, device="cuda")
+    prm = hydro.params(dt=1e-4)
+    assert L.hydro_step(ctypes.byref(prm), ctypes.byref(db.struct), hydro._ptr(db.U),
+                        hydro._ptr(out), hydro._ptr(amax), None, None) == EINVAL
+    assert L.hydro_rate(ctypes.byref(prm), ctypes.byref(db.struct), hydro._ptr(db.U),
+                        hydro._ptr(out), hydro._ptr(amax), None, None) == EINVAL
+    assert L.hydro_variant_count() == 0
+    T.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), U)
+
+
+def test_tau_resync_16():
+    T = torch()
+    U, off, h, ns, fs = _batch()
+    # cold cells: lower the total energy of a slab of every subgrid
+    for s in range(len(off)):
+        e = U[off[s] + 4 * fs:off[s] + 4 * fs + NB ** 3].reshape(NB, NB, NB)
+        rho = U[off[s]:off[s] + NB ** 3].reshape(NB, NB, NB)
+        sx = U[off[s] + fs:off[s] + fs + NB ** 3].reshape(NB, NB, NB)
+        e[:, :, :8] = 0.5 * sx[:, :, :8] ** 2 / rho[:, :, :8] * (1.0 + 1e-5)
+    db = _device(U, off, h, ns, fs)
+    hydro.tau_resync(hydro.params(), db.struct, db.U, n=N)
+    T.cuda.synchronize()
+    Ug = db.U.cpu().numpy()
+    Ur = oracle.tau_resync(U, off, h, ns, fs, n=N)
+    changed = 0
+    for s in range(len(off)):
+        nf = 6 + int(ns[s])
+        g, r, i0 = (_interior(x, off, fs, nf, N, s) for x in (Ug, Ur, U))
+        assert np.array_equal(np.delete(g, 5, axis=0), np.delete(r, 5, axis=0))
+        assert np.all(np.abs(g[5] - r[5]) <= 4 * 2.0 ** -52 * np.abs(r[5]))
+        changed += int(np.count_nonzero(r[5] != i0[5]))
+        assert np.array_equal(r[5][:, :, :5], i0[5][:, :, :5])   # the cold slab keeps tau
+    # the initial tau is e_i^(1/gamma) already, so only cells whose pow rounds
+    # differently from the packing's change
+    assert changed > 100
+    # ghosts untouched
+    assert np.array_equal(Ug[off[0]:off[0] + NB ** 2], U[off[0]:off[0] + NB ** 2])
+
+
+def test_fill_ghosts_16_periodic_box():
+    """A 2 x 2 x 1 periodic box of 16^3 subgrids: after the fill every block
+    equals the wrap-padded global field cut at its position."""
+    T = torch()
+    rng = np.random.default_rng(95)
+    nx, ny, nz, nf = 2, 2, 1, 6
+    G = rng.normal(size=(nf, nz * N, ny * N, nx * N))
+    P = np.pad(G, [(0, 0), (3, 3), (3, 3), (3, 3)], mode="wrap")
+    want, start = [], []
+    for bz in range(nz):
+        for by in range(ny):
+            for bx in range(nx):
+                blk = P[:, bz * N:bz * N + NB, by * N:by * N + NB, bx * N:bx * N + NB].copy()
+                want.append(blk)
+                garbage = blk.copy()
+                garbage[:, :3] = garbage[:, -3:] = 7.5               # ghosts to be refilled
+                garbage[:, :, :3] = garbage[:, :, -3:] = 7.5
+                garbage[:, :, :, :3] = garbage[:, :, :, -3:] = 7.5
+                start.append(garbage)
+    U, off, h, ns, fs = _pack(start, N, 0.1, 0.0)
+    db = _device(U, off, h, ns, fs)
+    gm = hydro.DeviceGhostMap(*hydro.box_ghost_map(nx, ny, nz))
+    status = T.zeros(db.n_sub, dtype=T.int32, device="cuda")
+    hydro.fill_ghosts(db.struct, gm, db.U, status, n=N)
+    T.cuda.synchronize()
+    Ug = db.U.cpu().numpy()
+    assert not status.any().item()
+    for s, blk in enumerate(want):
+        got = np.stack([Ug[off[s] + f * fs:off[s] + f * fs + NB ** 3].reshape(NB, NB, NB)
+                        for f in range(nf)])
+        assert np.array_equal(got, blk), s
+
+
+def test_rk_update_16():
+    T = torch()
+    U, off, h, ns, fs = _batch()
+    db = _device(U, off, h, ns, fs)
+    rng = np.random.default_rng(96)
+    Uk = T.as_tensor(rng.normal(size=U.shape)).cuda()
+    R = T.as_tensor(rng.normal(size=U.shape)).cuda()
+    out = T.full_like(db.U, 3.25)
+    clock = T.as_tensor(np.array([0.0, 0.01, 0.0])).cuda()
+    hydro.rk_update(db.struct, 0.75, db.U, 0.25, Uk, R, clock, out, n=N)
+    T.cuda.synchronize()
+    o, uk, r = (x.cpu().numpy() for x in (out, Uk, R))
+    for s in range(len(off)):
+        nf = 6 + int(ns[s])
+        a0, ak, ar = (_interior(x, off, fs, nf, N, s) for x in (U, uk, r))
+        want = 0.75 * a0 + 0.25 * (ak + 0.01 * ar)
+        size = 0.75 * np.abs(a0) + 0.25 * (np.abs(ak) + 0.01 * np.abs(ar))
+        assert np.all(np.abs(_interior(o, off, fs, nf, N, s) - want) <= 4 * 2.0 ** -52 * size)
+    assert np.all(o[off[0]:off[0] + NB ** 2] == 3.25)            # ghosts untouched

@@ -111,3 +111,23 @@ def test_the_field_exercises_the_options():
     for fl in (VEL, ST, FL):
         Q1, _ = oracle.reconstruct(U, off, h, ns, fs, flags=fl, n=16)
         assert np.count_nonzero(Q1 != Q0) > 1000, fl
+
+
+def test_config3_cut_into_16_cubes_matches_the_8_cube_cut():
+    """The 16^3 input of the 128^3 binary-star mesh (here at 32^3) holds the
+    same cells as the 8^3 cut: every 16^3 interior is four-by-two 8^3
+    interiors, and its ghosts are the neighbouring cells of the same field."""
+    U16, off16, h16, ns16, fs16, dt16 = inputs.config3_subgrid16(N=32)
+    b8 = inputs.config3(N=32)
+    assert len(off16) == 8 and b8.n_sub == 64 and dt16 == b8.dt
+    nf = 11
+    for s in range(8):
+        bx, by, bz = s % 2, (s // 2) % 2, s // 4
+        big = np.stack([U16[off16[s] + f * fs16:off16[s] + f * fs16 + 22 ** 3].reshape(22, 22, 22)
+                        for f in range(nf)])
+        for t in range(8):
+            tx, ty, tz = t % 2, (t // 2) % 2, t // 4
+            gx, gy, gz = 2 * bx + tx, 2 * by + ty, 2 * bz + tz
+            small = np.array(b8.block((gz * 4 + gy) * 4 + gx))
+            assert np.array_equal(big[:, tz * 8:tz * 8 + 14, ty * 8:ty * 8 + 14,
+                                      tx * 8:tx * 8 + 14], small), (s, t)
