@@ -18,11 +18,11 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-12
 
 
-def ref_step(b, dt=None, idx=None):
+def ref_step(b, dt=None, idx=None, flags=0):
     dt = b.dt if dt is None else dt
     if idx is not None:
         b = b.subset(idx)
-    return oracle.step(b.U, b.offset, b.h, b.n_species, b.fstride, dt)
+    return oracle.step(b.U, b.offset, b.h, b.n_species, b.fstride, dt, flags=flags)
 
 
 def ref_plain(b):
@@ -142,6 +142,28 @@ def test_config3_full_size_sampled():
     assert rel(ag[idx], ar) <= 1e-13
     assert np.array_equal(sg[idx], sr)
     assert np.all(sg == 0)
+
+
+@pytest.mark.parametrize("flags", [hydro.KT_SYMMETRIC, hydro.VELOCITY,
+                                   hydro.VELOCITY | hydro.KT_SYMMETRIC])
+def test_config3_full_size_sampled_with_options(flags):
+    """The benchmark's variant runs: the whole 128^3 batch in one launch with
+    each fused-path option, 16 sampled subgrids (floor and dense ones
+    included) against the oracle with the same option."""
+    b = inputs.config3()
+    Ug, ag, sg = gpu_step(b, flags=flags)
+    rng = np.random.default_rng(8)
+    rho_max = np.array([b.interior(s)[0].max() for s in range(b.n_sub)])
+    idx = np.unique(np.concatenate([rng.choice(b.n_sub, 8, replace=False),
+                                    rng.choice(np.flatnonzero(rho_max < 1e-6), 4, replace=False),
+                                    rng.choice(np.flatnonzero(rho_max > 0.1), 4, replace=False)]))
+    sub = b.subset(idx)
+    Ur, ar, sr = ref_step(sub, dt=b.dt, flags=flags)
+    for n, s in enumerate(idx):
+        S = field_scales(np.array(b.block(s)))
+        assert float(mixed_rel(b.interior(s, Ug), sub.interior(n, Ur), S).max()) <= TOL, s
+    assert rel(ag[idx], ar) <= 1e-13
+    assert np.array_equal(sg[idx], sr) and np.all(sg == 0)
 
 
 def test_config4_mixed_species_launch():
