@@ -426,8 +426,10 @@ def main():
     if not args.no_variants:
         # the method variants on the same batch, each captured the same way
         variants = {}
+        cw = hydro.STEEPEN | hydro.FLATTEN
         for name, fl in (("kt_symmetric", hydro.KT_SYMMETRIC), ("velocity", hydro.VELOCITY),
-                         ("velocity+kt_symmetric", hydro.VELOCITY | hydro.KT_SYMMETRIC)):
+                         ("velocity+kt_symmetric", hydro.VELOCITY | hydro.KT_SYMMETRIC),
+                         ("steepen+flatten", cw), ("velocity+steepen+flatten", hydro.VELOCITY | cw)):
             vplan = hydro.Plan(hydro.params(dt=b.dt, flags=fl), db.struct, db.U, U_out, amax,
                                status)
             vwall, vper = timed_plan(vplan, max(5, args.steps // 2), args.warmup, torch)

@@ -19,8 +19,9 @@
  * cells [2, N+4)^3 ((N+2)^3 per direction), and the faces of one axis form a
  * box of (N+1) x N x N.  The N = 16 library provides the plain stages, the
  * entropy-tracer re-sync, the ghost fill, the CFL step size and the stage
- * combination; its fused entry points (those that refuse the
- * Colella-Woodward flags below) return HYDRO_EINVAL, because the fused
+ * combination; its fused entry points (hydro_step, hydro_step_variant,
+ * hydro_step_io, hydro_autotune, hydro_plan_create, hydro_rate,
+ * hydro_rk_stage, hydro_rk3_create) return HYDRO_EINVAL, because the fused
  * kernel maps the 8 x 8 cells of a plane onto one 64-lane wave.
  *
  * Conventions shared by every entry point
@@ -106,11 +107,9 @@ enum { HYDRO_FLAG_VELOCITY = 2 };
  * Pressures are the cells' own (ideal gas with the dual-energy switch).  The
  * method's extra step that takes the larger flattening weight of the upstream
  * neighbour needs pressures three cells away, beyond the ghost layers of the
- * reconstructed cells; the cell's own weight is used.  These two options are
- * honoured by the plain form (hydro_reconstruct); the fused entry points
- * (hydro_step, hydro_step_variant, hydro_step_io, hydro_autotune,
- * hydro_plan_create, hydro_rate, hydro_rk_stage, hydro_rk3_create) return
- * HYDRO_EINVAL for them. */
+ * reconstructed cells; the cell's own weight is used.  Honoured by every
+ * entry point that reconstructs, like HYDRO_FLAG_VELOCITY (the fused kernel
+ * forms the cell pressures of each line from its field window). */
 enum { HYDRO_FLAG_STEEPEN = 4, HYDRO_FLAG_FLATTEN = 8 };
 
 typedef struct {

@@ -56,13 +56,12 @@ int check_common(const hydro_params *p, const hydro_batch *b) {
     return HYDRO_OK;
 }
 
-// The fused kernel covers 8^3 subgrids only, and has no room for the cell
-// pressures the Colella-Woodward options need: its entry points refuse both.
+// The fused kernel covers 8^3 subgrids only: its entry points refuse other
+// builds.
 int check_fused(const hydro_params *p, const hydro_batch *b) {
     int rc = check_common(p, b);
     if (rc) return rc;
     if (NSUB != 8) return HYDRO_EINVAL;
-    if (p->flags & (HYDRO_FLAG_STEEPEN | HYDRO_FLAG_FLATTEN)) return HYDRO_EINVAL;
     return HYDRO_OK;
 }
 

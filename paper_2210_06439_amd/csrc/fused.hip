@@ -139,6 +139,34 @@ __device__ __forceinline__ void ppm_fast(double um2, double um1, double u0, doub
     qm = fma(-bn, sg, u0);
 }
 
+// ppm_fast with the Colella-Woodward weights applied to the interface offsets
+// before the monotonicity step: steepening (eta) moves q+ toward
+// u_{+1} - s_{+1}/2 and q- toward u_{-1} + s_{-1}/2, flattening (flat) moves
+// both toward u0.  With eta = flat = 0 it is ppm_fast.
+__device__ __forceinline__ void ppm_fast_w(double um2, double um1, double u0, double up1,
+                                           double up2, double eta, double flat, double &qp,
+                                           double &qm) {
+    const double sixth = 1.0 / 6.0;
+    double d0 = um1 - um2, d1 = u0 - um1, d2 = up1 - u0, d3 = up2 - up1;
+    double sm = mc_slope(d0, d1);
+    double s0 = mc_slope(d1, d2);
+    double sp = mc_slope(d2, d3);
+    double a = fma(s0 - sp, sixth, 0.5 * d2);
+    double b = fma(s0 - sm, sixth, 0.5 * d1);
+    a = fma(eta, fma(-0.5, sp, d2) - a, a);
+    b = fma(eta, fma(-0.5, sm, d1) - b, b);
+    const double keep = 1.0 - flat;
+    a *= keep;
+    b *= keep;
+    double sg = copysign(1.0, a);
+    double aa = fabs(a);
+    double sb = b * sg;
+    double bn = fmax(fmin(sb, aa + aa), 0.0);
+    double an = fmax(fmin(aa, sb + sb), 0.0);
+    qp = fma(an, sg, u0);
+    qm = fma(-bn, sg, u0);
+}
+
 // 1/x from the hardware estimate and two Newton steps (each doubles the
 // number of correct bits; the result is within an ulp of the rounded quotient).
 __device__ __forceinline__ double recip(double x) {
@@ -243,6 +271,101 @@ __device__ __forceinline__ void ppm_at(const double *win, const Line5 &l, int f,
              win[l.o[4] + fo], qp, qm);
 }
 
+// ---- Colella-Woodward steepening and flattening (the CW instantiation) ------
+
+// Weights of one line: eta (contact steepening, density only) and flat
+// (flattening, every field).
+struct CwW {
+    double eta, flat;
+};
+
+// Pressure and velocity along (dx, dy, dz) of the window cell at offset o,
+// with the point-state formulas (dual-energy switch included).  With VEL the
+// momentum slots hold velocities.
+template <bool VEL>
+__device__ __forceinline__ void cw_cell(const double *win, int o, int dx, int dy, int dz,
+                                        double gamma, double gm1, double de, double &p,
+                                        double &un) {
+    const double rho = win[o];
+    const double m1 = win[o + NPLANE], m2 = win[o + 2 * NPLANE], m3 = win[o + 3 * NPLANE];
+    double vx, vy, vz, ek;
+    if (VEL) {
+        vx = m1;
+        vy = m2;
+        vz = m3;
+        ek = 0.5 * (((rho * vx) * vx + (rho * vy) * vy) + (rho * vz) * vz);
+    } else {
+        const double r = recip(rho);
+        vx = m1 * r;
+        vy = m2 * r;
+        vz = m3 * r;
+        ek = 0.5 * ((m1 * vx + m2 * vy) + m3 * vz);
+    }
+    const double E = win[o + 4 * NPLANE];
+    double ei = E - ek;
+    if (ei < de * E) ei = tau_pow(win[o + 5 * NPLANE], gamma);
+    p = gm1 * ei;
+    un = (dx * vx + dy * vy) + dz * vz;
+}
+
+// The weights of the line l along (dx, dy, dz).  mode: bit 0 steepening, bit 1
+// flattening.  Flattening: in a compression along the line with a relative
+// pressure jump above eps, clamp(omega2 ((p_1 - p_-1) / (p_2 - p_-2) -
+// omega1), 0, 1).  Steepening: where the density's second differences on the
+// two sides have opposite signs, its jump exceeds eps1 of the smaller density
+// and gamma K0 |jump| / min rho >= |p_1 - p_-1| / min p, clamp(eta1 (eta~ -
+// eta2), 0, 1) with eta~ = -(D_1 - D_-1) / (6 (rho_1 - rho_-1)).  Both are
+// taken with selects (the lanes differ).
+template <bool VEL>
+__device__ __forceinline__ CwW cw_weights(const double *win, const Line5 &l, int dx, int dy,
+                                          int dz, double gamma, double gm1, double de, int mode,
+                                          bool need_eta) {
+    double p[5], un[5];
+#pragma unroll
+    for (int m = 0; m < 5; m++)
+        if (m != 2) cw_cell<VEL>(win, l.o[m], dx, dy, dz, gamma, gm1, de, p[m], un[m]);
+    CwW w;
+    w.eta = 0.0;
+    w.flat = 0.0;
+    if (mode & 2) {
+        const double dp1 = p[3] - p[1];
+        const bool shock = (un[1] - un[3] > 0.0) && (fabs(dp1) / fmin(p[3], p[1]) > CW_EPS_SHOCK);
+        const double ratio = dp1 / (p[4] - p[0]);
+        const double f = fmax(0.0, fmin(1.0, CW_OMEGA2 * (ratio - CW_OMEGA1)));
+        w.flat = shock ? f : 0.0;
+    }
+    if ((mode & 1) && need_eta) {
+        double r[5];
+#pragma unroll
+        for (int m = 0; m < 5; m++) r[m] = win[l.o[m]];
+        const double d2m = r[2] - 2.0 * r[1] + r[0];
+        const double d2p = r[4] - 2.0 * r[3] + r[2];
+        const double drho = r[3] - r[1];
+        const bool contact =
+            (d2p * d2m < 0.0) &&
+            (fabs(drho) - CW_EPS1 * fmin(fabs(r[3]), fabs(r[1])) > 0.0) &&
+            (gamma * CW_K0 * fabs(drho) / fmin(r[3], r[1]) >= fabs(p[3] - p[1]) / fmin(p[3], p[1]));
+        const double et = -(d2p - d2m) / (6.0 * drho);
+        const double e = fmax(0.0, fmin(CW_ETA1 * (et - CW_ETA2), 1.0));
+        w.eta = contact ? e : 0.0;
+    }
+    return w;
+}
+
+// PPM of field f along l: plain, or with the line's weights (eta for the
+// density only).
+template <bool CW>
+__device__ __forceinline__ void ppm_line(const double *win, const Line5 &l, int f, const CwW &w,
+                                         double &qp, double &qm) {
+    if (!CW) {
+        ppm_at(win, l, f, qp, qm);
+    } else {
+        const int fo = f * NPLANE;
+        ppm_fast_w(win[l.o[0] + fo], win[l.o[1] + fo], win[l.o[2] + fo], win[l.o[3] + fo],
+                   win[l.o[4] + fo], f == 0 ? w.eta : 0.0, w.flat, qp, qm);
+    }
+}
+
 // ---- producers ------------------------------------------------------------------
 
 // Hydro fields along one line: reconstructed values and the point states at
@@ -256,19 +379,20 @@ struct PlusState {
     double vx, vy, p, cs;
 };
 
-template <bool store, bool both, bool VEL>
+template <bool store, bool both, bool VEL, bool CW>
 __device__ __forceinline__ PlusState produce_hydro(const double *win, const Line5 &l,
                                                    double *pp, double *pm, double gamma,
-                                                   double gm1, double de, int &bits) {
+                                                   double gm1, double de, int &bits,
+                                                   const CwW &cw) {
     PlusState ps;
     double qp, qm;
-    ppm_at(win, l, 0, qp, qm);
+    ppm_line<CW>(win, l, 0, cw, qp, qm);
     ps.q[0] = qp;
     if (store) pp[0] = qp;
     if (both) pm[0] = qm;
     const double rhop = qp, rhom = qm;
     const double rp = recip(qp), rm = both ? recip(qm) : 1.0;
-    ppm_at(win, l, 1, qp, qm);
+    ppm_line<CW>(win, l, 1, cw, qp, qm);
     const double wxp = qp, wxm = qm;
     if (VEL) {
         qp = rhop * wxp;
@@ -279,7 +403,7 @@ __device__ __forceinline__ PlusState produce_hydro(const double *win, const Line
     if (both) pm[64] = qm;
     const double vxp = VEL ? wxp : qp * rp, vxm = VEL ? wxm : qm * rm;
     double ekp = qp * vxp, ekm = qm * vxm;
-    ppm_at(win, l, 2, qp, qm);
+    ppm_line<CW>(win, l, 2, cw, qp, qm);
     const double wyp = qp, wym = qm;
     if (VEL) {
         qp = rhop * wyp;
@@ -291,7 +415,7 @@ __device__ __forceinline__ PlusState produce_hydro(const double *win, const Line
     const double vyp = VEL ? wyp : qp * rp, vym = VEL ? wym : qm * rm;
     ekp = fma(qp, vyp, ekp);
     ekm = fma(qm, vym, ekm);
-    ppm_at(win, l, 3, qp, qm);
+    ppm_line<CW>(win, l, 3, cw, qp, qm);
     const double wzp = qp, wzm = qm;
     if (VEL) {
         qp = rhop * wzp;
@@ -303,12 +427,12 @@ __device__ __forceinline__ PlusState produce_hydro(const double *win, const Line
     const double vzp = VEL ? wzp : qp * rp, vzm = VEL ? wzm : qm * rm;
     ekp = fma(qp, vzp, ekp);
     ekm = fma(qm, vzm, ekm);
-    ppm_at(win, l, 4, qp, qm);
+    ppm_line<CW>(win, l, 4, cw, qp, qm);
     ps.q[4] = qp;
     if (store) pp[4 * 64] = qp;
     if (both) pm[4 * 64] = qm;
     const double Ep = qp, Em = qm;
-    ppm_at(win, l, 5, qp, qm);
+    ppm_line<CW>(win, l, 5, cw, qp, qm);
     ps.q[5] = qp;
     if (store) pp[5 * 64] = qp;
     if (both) pm[5 * 64] = qm;
@@ -510,14 +634,13 @@ __device__ __forceinline__ void update_cell(const double *win, const double *kee
 // The work of one subgrid for one field group (HYD: hydro fields and point
 // states; else: species).  Both instantiations execute the same sequence of
 // barriers, so the hydro and species waves of a workgroup stay in step.
-template <bool HYD, bool VEL>
+template <bool HYD, bool VEL, bool CW>
 __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *zl, double *keep,
                                              double *run, int tid, int role, int nspec,
                                              const double *Us0, double *Os0, int fst0,
                                              double lam, bool rate, const Stage &stg, bool sym,
-                                             double gamma,
-                                             double gm1,
-                                             double de, double &amax_l, int &bits) {
+                                             int cwmode, double gamma, double gm1, double de,
+                                             double &amax_l, int &bits) {
     const int nf = 6 + nspec;
     double chk = 0.0;
     const int f0 = HYD ? 0 : 6, f1 = HYD ? 6 : nf;     // this wave's fields
@@ -601,14 +724,19 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                 const int t = role + 4 * r;
                 double *pp = xch + role * PT * 64 + lane;
                 if (t < 9) {
-                    const Line5 l = line5(ci, cj, k, t % 3 - 1, t / 3 - 1, k == 2 ? 1 : -1);
+                    const int ldxv = t % 3 - 1, ldyv = t / 3 - 1, ldzv = k == 2 ? 1 : -1;
+                    const Line5 l = line5(ci, cj, k, ldxv, ldyv, ldzv);
+                    CwW cw = {0.0, 0.0};
+                    if (CW && (HYD || nspec > 0))
+                        cw = cw_weights<VEL>(win, l, ldxv, ldyv, ldzv, gamma, gm1, de, cwmode, HYD);
                     if (HYD) {
-                        produce_hydro<true, false, VEL>(win, l, pp, pp, gamma, gm1, de, bits);
+                        produce_hydro<true, false, VEL, CW>(win, l, pp, pp, gamma, gm1, de, bits,
+                                                            cw);
                     } else if (nspec > 0) {
 #pragma unroll
                         for (int f = 6; f < NF_MAX; f++) {
                             double qp, qm;
-                            ppm_at(win, l, f, qp, qm);
+                            ppm_line<CW>(win, l, f, cw, qp, qm);
                             pp[f * 64] = qp;
                         }
                     }
@@ -639,11 +767,15 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                 double *pm = xch + (role * 2 + 1) * PT * 64 + lane;
                 if (L >= 0) {
                     const Line5 l = line5(ci, cj, k, ldx(L), ldy(L), ldz(L));
+                    CwW cw = {0.0, 0.0};
+                    if (CW && (HYD || nspec > 0))
+                        cw = cw_weights<VEL>(win, l, ldx(L), ldy(L), ldz(L), gamma, gm1, de, cwmode,
+                                             HYD);
                     if (HYD) {
-                        produce_hydro<true, true, VEL>(win, l, pp, pm, gamma, gm1, de, bits);
+                        produce_hydro<true, true, VEL, CW>(win, l, pp, pm, gamma, gm1, de, bits, cw);
                         if (nspec > 0) {   // the last species field, to balance the pair
                             double qp, qm;
-                            ppm_at(win, l, NF_MAX - 1, qp, qm);
+                            ppm_line<CW>(win, l, NF_MAX - 1, cw, qp, qm);
                             pp[(NF_MAX - 1) * 64] = qp;
                             pm[(NF_MAX - 1) * 64] = qm;
                         }
@@ -651,7 +783,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
 #pragma unroll
                         for (int f = 6; f < NF_MAX - 1; f++) {
                             double qp, qm;
-                            ppm_at(win, l, f, qp, qm);
+                            ppm_line<CW>(win, l, f, cw, qp, qm);
                             pp[f * 64] = qp;
                             pm[f * 64] = qm;
                         }
@@ -694,23 +826,25 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                 const int dx = r_axis == 0 ? dn : t % 3 - 1;
                 const int dy = r_axis == 0 ? t % 3 - 1 : dn;
                 const Line5 l = line5(ri, rj, k, dx, dy, t / 3 - 1);
+                CwW cw = {0.0, 0.0};
+                if (CW && (HYD || nspec > 0))
+                    cw = cw_weights<VEL>(win, l, dx, dy, t / 3 - 1, gamma, gm1, de, cwmode, HYD);
                 if (HYD) {
-                    const PlusState ps =
-                        produce_hydro<false, false, VEL>(win, l, nullptr, nullptr, gamma, gm1, de,
-                                                        bits);
+                    const PlusState ps = produce_hydro<false, false, VEL, CW>(
+                        win, l, nullptr, nullptr, gamma, gm1, de, bits, cw);
                     const double un = r_axis == 0 ? ps.vx : ps.vy;
                     acc_h_vals(acc[0], ps.q, un, ps.p, ps.cs, wt);
                     run[lane] = un;
                     if (nspec > 0) {
                         double qp, qm;
-                        ppm_at(win, l, NF_MAX - 1, qp, qm);
+                        ppm_line<CW>(win, l, NF_MAX - 1, cw, qp, qm);
                         run[(NF_MAX - 1 - 5) * 64 + lane] = qp;
                     }
                 } else if (nspec > 0) {
 #pragma unroll
                     for (int f = 6; f < NF_MAX - 1; f++) {
                         double qp, qm;
-                        ppm_at(win, l, f, qp, qm);
+                        ppm_line<CW>(win, l, f, cw, qp, qm);
                         run[(f - 5) * 64 + lane] = qp;
                     }
                 }
@@ -900,7 +1034,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
 
 // ---- the kernel ---------------------------------------------------------------
 
-template <bool VEL>
+template <bool VEL, bool CW>
 __global__ __launch_bounds__(NT, 2) void k_fused(StepArgs a, const double *__restrict__ U,
                                                  double *Uo,
                                                  double *__restrict__ amax,
@@ -921,6 +1055,7 @@ __global__ __launch_bounds__(NT, 2) void k_fused(StepArgs a, const double *__res
     const double gamma = a.gamma, gm1 = a.gamma - 1.0, de = a.de_switch;
     const bool rate = a.rate != 0;
     const bool sym = a.sym != 0;
+    const int cwmode = (a.steepen ? 1 : 0) | (a.flatten ? 2 : 0);
 
     for (int it = blockIdx.x; it < a.n_sub; it += gridDim.x) {
         const int s = order ? (a.n_sub - 1 - it) : it;
@@ -948,11 +1083,12 @@ __global__ __launch_bounds__(NT, 2) void k_fused(StepArgs a, const double *__res
         int bits = 0;
 
         if (hyd)
-            subgrid_body<true, VEL>(win, xch, zl, keep, run, tid, role, nspec, Us0, Os0, fst0, lam, rate, stg, sym,
-                               gamma, gm1, de, amax_l, bits);
+            subgrid_body<true, VEL, CW>(win, xch, zl, keep, run, tid, role, nspec, Us0, Os0, fst0,
+                                        lam, rate, stg, sym, cwmode, gamma, gm1, de, amax_l, bits);
         else
-            subgrid_body<false, VEL>(win, xch, zl, keep, run, tid, role, nspec, Us0, Os0, fst0, lam, rate, stg, sym,
-                                gamma, gm1, de, amax_l, bits);
+            subgrid_body<false, VEL, CW>(win, xch, zl, keep, run, tid, role, nspec, Us0, Os0, fst0,
+                                         lam, rate, stg, sym, cwmode, gamma, gm1, de, amax_l,
+                                         bits);
 
         // ---- per-subgrid speed and status
         for (int o = 32; o > 0; o >>= 1) {
@@ -1002,6 +1138,17 @@ int device_cus() {
     return cus;
 }
 
+// The instantiation for the call's options: velocity reconstruction and the
+// Colella-Woodward weights each have their own kernel, so the default one
+// carries neither.
+using FusedKernel = void (*)(StepArgs, const double *, double *, double *, int32_t *, int);
+
+FusedKernel fused_kernel(const StepArgs &a) {
+    const bool cw = a.steepen || a.flatten;
+    if (a.vel) return cw ? k_fused<true, true> : k_fused<true, false>;
+    return cw ? k_fused<false, true> : k_fused<false, false>;
+}
+
 dim3 grid_of(const StepArgs &a, int v) {
     const Variant &V = kVariants[v];
     int g = V.grid_per_cu ? V.grid_per_cu * device_cus() : a.n_sub;
@@ -1022,12 +1169,8 @@ int fused_variant_order(int v) {
 hipError_t launch_fused_step(const StepArgs &a, const double *U_in, double *U_out,
                              double *amax, int32_t *status, int variant, hipStream_t st) {
     if (a.n_sub == 0) return hipSuccess;
-    if (a.vel)
-        hipLaunchKernelGGL(k_fused<true>, grid_of(a, variant), dim3(NT), 0, st, a, U_in, U_out,
-                           amax, status, kVariants[variant].order);
-    else
-        hipLaunchKernelGGL(k_fused<false>, grid_of(a, variant), dim3(NT), 0, st, a, U_in, U_out,
-                           amax, status, kVariants[variant].order);
+    hipLaunchKernelGGL(fused_kernel(a), grid_of(a, variant), dim3(NT), 0, st, a, U_in, U_out,
+                       amax, status, kVariants[variant].order);
     return hipGetLastError();
 }
 
@@ -1035,8 +1178,7 @@ hipError_t fused_kernel_node_params(const StepArgs &a, const double *U_in, doubl
                                     double *amax, int32_t *status, int variant,
                                     hipKernelNodeParams *out, void **args) {
     // args must point at storage for the kernel's arguments, filled by the caller
-    out->func = a.vel ? reinterpret_cast<void *>(k_fused<true>)
-                      : reinterpret_cast<void *>(k_fused<false>);
+    out->func = reinterpret_cast<void *>(fused_kernel(a));
     out->gridDim = grid_of(a, variant);
     out->blockDim = dim3(NT);
     out->sharedMemBytes = 0;

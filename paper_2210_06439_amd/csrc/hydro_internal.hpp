@@ -31,6 +31,12 @@ constexpr int QCELL = QN * QN * QN;
 constexpr int NFACE = (NSUB + 1) * NSUB * NSUB;   // faces per axis
 constexpr int NF_MAX = 11;
 
+// Colella-Woodward (1984) steepening and flattening constants, as recommended
+// with the method: eta1, eta2, eps1 and K0 of the contact detector, eps and
+// omega1, omega2 of the shock detector.
+constexpr double CW_ETA1 = 20.0, CW_ETA2 = 0.05, CW_EPS1 = 0.01, CW_K0 = 0.1;
+constexpr double CW_EPS_SHOCK = 0.33, CW_OMEGA1 = 0.75, CW_OMEGA2 = 10.0;
+
 // Kernel-side copy of the call's scalar parameters (passed by value).
 struct StepArgs {
     double gamma;
@@ -44,7 +50,7 @@ struct StepArgs {
     int32_t rate;   // 0: U_out = U + dt L(U); 1: U_out = L(U) on the interior
     int32_t sym;    // symmetric (Kurganov-Tadmor 2000) face speeds
     int32_t vel;    // PPM of the velocities s / rho instead of the momenta
-    int32_t steepen, flatten;   // Colella-Woodward options (plain path only)
+    int32_t steepen, flatten;   // Colella-Woodward options
     // Runge-Kutta stage form (U0 non-null): U_out = c0 U0 + c1 (U + dt L(U)),
     // or U0 where dt == 0; dt = clock[1] when clock is non-null, else dt.
     const double *clock;

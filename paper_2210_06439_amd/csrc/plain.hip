@@ -89,10 +89,7 @@ __device__ inline void ppm(double um2, double um1, double u0, double up1, double
 // fourth-order interface values before the monotonicity constraint.  They
 // need the pressures of the five cells of the line (ideal gas with the
 // dual-energy switch, the point-state formulas) and the velocities along the
-// line direction; the constants are the ones recommended with the method.
-
-constexpr double CW_ETA1 = 20.0, CW_ETA2 = 0.05, CW_EPS1 = 0.01, CW_K0 = 0.1;
-constexpr double CW_EPS_SHOCK = 0.33, CW_OMEGA1 = 0.75, CW_OMEGA2 = 10.0;
+// line direction.
 
 // Pressure and velocity along (dx, dy, dz) of cell c of a subgrid.
 __device__ inline void cell_p_un(const StepArgs &a, const double *Us, int c, int dx, int dy,

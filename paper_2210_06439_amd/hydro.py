@@ -28,8 +28,8 @@ EXPORTS = [
 STATUS_RHO, STATUS_P, STATUS_NONFINITE, STATUS_BADMETA = 1, 2, 4, 8
 KT_SYMMETRIC = 1   # params flag: one face speed max(|u_n| + c) for both directions
 VELOCITY = 2       # params flag: PPM of v = s / rho; point momentum = rho_q v_q
-STEEPEN = 4        # params flag: contact steepening of the density (plain form only)
-FLATTEN = 8        # params flag: flattening in strong compressions (plain form only)
+STEEPEN = 4        # params flag: Colella-Woodward contact steepening of the density
+FLATTEN = 8        # params flag: Colella-Woodward flattening in strong compressions
 
 
 class HydroError(RuntimeError):

@@ -80,3 +80,25 @@ def apply_map(batch, U, src, mode):
                     sblk = batch.block(sb, U)
                     blk[:, k, j, i] = sblk[:, sidx[2], sidx[1], sidx[0]]
     return out
+
+
+def generic_periodic_box(seed=97, n=16):
+    """A periodic n^3 box (8^3 subgrids) of generic flow: smooth random
+    velocity modes with cell noise, density and pressure jumps across
+    different planes.  Unlike the rigidly rotating binary star, whose velocity
+    has exactly zero divergence (so the sign of u_{j-1} - u_{j+1} on a line is
+    decided by rounding), no Colella-Woodward detector sits on its threshold
+    here."""
+    rng = np.random.default_rng(seed)
+    x = (np.arange(n) + 0.5) / n
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    rho = (1.0 + 0.3 * np.sin(2 * np.pi * (X + 0.3 * Y)) + np.where(Y > 0.5, 0.8, 0.0)
+           + rng.uniform(0.0, 0.05, X.shape))
+    p = (1.0 + 0.4 * np.cos(2 * np.pi * Z) + np.where(X > 0.5, 2.0, 0.0)
+         + rng.uniform(0.0, 0.05, X.shape))
+    v = [0.3 * np.sin(2 * np.pi * (X * a + Y * b + Z * c) + ph) + rng.normal(0.0, 0.02, X.shape)
+         for a, b, c, ph in ((1, 0, 1, 0.1), (0, 1, 1, 0.7), (1, 1, 0, 1.3))]
+    sp = [rho * w for w in rng.uniform(0.0, 0.2, (5,) + X.shape)]
+    G = inputs.conserved_from_primitive(rho, v[0], v[1], v[2], p, sp)
+    dt = inputs.cfl_dt(rho, v[0], v[1], v[2], p, 1.0 / n)
+    return box_batch(G, (n // NI,) * 3, 1.0 / n, (True, True, True), dt=dt)
