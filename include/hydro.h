@@ -305,6 +305,22 @@ int hydro_fill_ghosts(const hydro_batch *batch, const hydro_ghost_map *map, doub
                       int32_t *status, void *stream);
 
 /*
+ * hydro_step_gather -- hydro_step whose ghost cells are read through the map
+ * instead of from the blocks' own ghost layers: each ghost value is taken, as
+ * the fused kernel loads it, from the interior cell that hydro_fill_ghosts
+ * would have copied there.  The result equals hydro_fill_ghosts followed by
+ * hydro_step bit for bit, without the fill pass and without reading or
+ * writing any ghost cell of U_in.  A map entry naming no valid subgrid, or a
+ * source with fewer species than the subgrid, is replaced by the subgrid
+ * itself with every axis clamped, and HYDRO_STATUS_BADMETA is set in
+ * status[s].  The device RK3 graph (hydro_rk3_create) reads its ghosts this
+ * way.  U_out must not alias U_in.
+ */
+int hydro_step_gather(const hydro_params *params, const hydro_batch *batch,
+                      const hydro_ghost_map *map, const double *U_in, double *U_out,
+                      double *amax, int32_t *status, void *stream);
+
+/*
  * hydro_rate -- the fused stage in rate form: writes R = L(U_in) =
  * -(1/h)((dF_x + dF_y) + dF_z) on the interior of R (same layout as U_in;
  * ghosts of R are not written), amax[s] as hydro_step, and ORs the status
@@ -358,11 +374,13 @@ int hydro_rk_stage(const hydro_params *params, const hydro_batch *batch, const d
 
 /*
  * SSP-RK3 time steps captured in one hipGraph.  One replay is one step:
- *   fill(U); R = L(U); clock <- CFL(amax); U1 = U + dt R;
- *   fill(U1); U2 = 3/4 U + 1/4 (U1 + dt L(U1))      (one fused stage);
- *   fill(U2); U  = 1/3 U + 2/3 (U2 + dt L(U2))      (one fused stage).
- * U holds the state (its ghosts are refilled at the start of every step, so
- * after the last step they hold the previous step's values); U1, U2 and R
+ *   R = L(U); clock <- CFL(amax); U1 = U + dt R;
+ *   U2 = 3/4 U + 1/4 (U1 + dt L(U1))      (one fused stage);
+ *   U  = 1/3 U + 2/3 (U2 + dt L(U2))      (one fused stage).
+ * Every L reads its ghost cells through the map, as hydro_step_gather does,
+ * so no fill pass runs and no ghost cell of U, U1 or U2 is read or written:
+ * U's ghost layers keep whatever they held (call hydro_fill_ghosts to bring
+ * them up to date).  U holds the state; U1, U2 and R
  * are work buffers with U's layout; amax [n_sub]; status [n_sub] collects
  * the OR of every stage's bits (clear it before the first step); clock
  * [3] = {t, dt, n} as for hydro_cfl_dt (set t and n before the first step).  Steps past t_end have

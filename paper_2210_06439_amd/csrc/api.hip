@@ -236,6 +236,25 @@ int hydro_step_io(const hydro_params *params, const hydro_batch *batch,
     return e == hipSuccess ? HYDRO_OK : fail_hip(e);
 }
 
+int hydro_step_gather(const hydro_params *params, const hydro_batch *batch,
+                      const hydro_ghost_map *map, const double *U_in, double *U_out,
+                      double *amax, int32_t *status, void *stream) {
+    int rc = check_fused(params, batch);
+    if (rc) return rc;
+    if (batch->n_sub == 0) return HYDRO_OK;
+    if (!map || !map->src || !map->mode || !U_in || !U_out || !amax || U_in == U_out ||
+        !aligned8(U_in) || !aligned8(U_out))
+        return HYDRO_EINVAL;
+    if ((rc = check_device())) return rc;
+    StepArgs a = make_args(params, batch);
+    a.gsrc = map->src;
+    a.gmode = map->mode;
+    hipError_t e = launch_fused_step(a, U_in, U_out, amax, status,
+                                     hydro_selected_variant(batch->n_sub, 5),
+                                     static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HYDRO_OK : fail_hip(e);
+}
+
 int hydro_autotune(const hydro_params *params, const hydro_batch *batch, const double *U_in,
                    double *U_out, double *amax, int32_t *status, int reps, float *times_ms,
                    void *stream) {
@@ -428,23 +447,19 @@ int hydro_rk_update(const hydro_batch *batch, double a, const double *U0, double
 
 namespace {
 
-// One SSP-RK3 step, enqueued on `st` (recorded when st is capturing).
-hipError_t enqueue_rk3_step(const StepArgs &ra, int variant, const hydro_ghost_map *map,
-                            double *U, double *U1, double *U2, double *R, double *amax,
-                            int32_t *status, double *clock, double cfl, double t_end,
-                            hipStream_t st) {
+// One SSP-RK3 step, enqueued on `st` (recorded when st is capturing).  The
+// fused stages read their ghost cells through the map (ra.gsrc, ra.gmode), so
+// no stage needs a fill pass and the ghost layers of U, U1 and U2 are never
+// read.
+hipError_t enqueue_rk3_step(const StepArgs &ra, int variant, double *U, double *U1, double *U2,
+                            double *R, double *amax, int32_t *status, double *clock, double cfl,
+                            double t_end, hipStream_t st) {
     const int n = ra.n_sub, fs = ra.fstride;
     hipError_t e;
-    auto fill = [&](double *X) {
-        return launch_fill_ghosts(n, fs, ra.offset, ra.n_species, map->src, map->mode, X,
-                                  status, st);
-    };
-    if ((e = fill(U))) return e;
     if ((e = launch_fused_step(ra, U, R, amax, status, variant, st))) return e;
     if ((e = launch_cfl_dt(n, ra.h, amax, cfl, t_end, clock, st))) return e;
     if ((e = launch_rk_update(n, fs, ra.offset, ra.n_species, 0.0, U, 1.0, U, R, clock, U1, st)))
         return e;
-    if ((e = fill(U1))) return e;
     StepArgs sa = ra;               // fused stages with dt from the device clock
     sa.rate = 0;
     sa.clock = clock;
@@ -452,7 +467,6 @@ hipError_t enqueue_rk3_step(const StepArgs &ra, int variant, const hydro_ghost_m
     sa.c0 = 0.75;
     sa.c1 = 0.25;
     if ((e = launch_fused_step(sa, U1, U2, amax, status, variant, st))) return e;
-    if ((e = fill(U2))) return e;
     sa.c0 = 1.0 / 3.0;
     sa.c1 = 2.0 / 3.0;
     return launch_fused_step(sa, U2, U, amax, status, variant, st);
@@ -479,6 +493,8 @@ int hydro_rk3_create(const hydro_params *params, const hydro_batch *batch,
     if ((rc = check_device())) return rc;
     StepArgs ra = make_args(params, batch);
     ra.rate = 1;
+    ra.gsrc = map->src;
+    ra.gmode = map->mode;
     const int variant = hydro_selected_variant(batch->n_sub, 5);
     hipStream_t cs;
     hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
@@ -490,7 +506,7 @@ int hydro_rk3_create(const hydro_params *params, const hydro_batch *batch,
     }
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t e1 = enqueue_rk3_step(ra, variant, map, U, U1, U2, R, amax, status, clock, cfl,
+        hipError_t e1 = enqueue_rk3_step(ra, variant, U, U1, U2, R, amax, status, clock, cfl,
                                          t_end, cs);
         e = hipStreamEndCapture(cs, &p->graph);
         if (e1 != hipSuccess) e = e1;

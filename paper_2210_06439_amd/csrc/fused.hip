@@ -247,6 +247,28 @@ __device__ __forceinline__ T opaque_v(T v) {
     (void)ci; (void)cj; (void)half; (void)r_axis; (void)r_side; (void)r_pos;     \
     (void)ri; (void)rj
 
+// ---- ghost cells read through a ghost map -------------------------------------
+
+// Source of block cell (i, j, pk) of the field at offset fo when the ghost
+// layers are read through a ghost map (the ghost fill's rule, applied on
+// load): the direction of the cell's ghost region picks the table entry
+// (entry 13, the interior, is the subgrid itself); along each axis the index
+// steps N cells back into the neighbour, or clamps to the nearest interior
+// cell where the entry's mode bit for that axis is set.
+__device__ __forceinline__ const double *gather_ptr(const double *U, const int64_t *toff,
+                                                    const int *tmode, int fo, int i, int j,
+                                                    int pk) {
+    const int dx = i < NG ? -1 : (i >= NG + NSUB ? 1 : 0);
+    const int dy = j < NG ? -1 : (j >= NG + NSUB ? 1 : 0);
+    const int dz = pk < NG ? -1 : (pk >= NG + NSUB ? 1 : 0);
+    const int n = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1);
+    const int m = tmode[n];
+    const int si = dx == 0 ? i : ((m & 1) ? (dx < 0 ? NG : NG + NSUB - 1) : i - NSUB * dx);
+    const int sj = dy == 0 ? j : ((m & 2) ? (dy < 0 ? NG : NG + NSUB - 1) : j - NSUB * dy);
+    const int sk = dz == 0 ? pk : ((m & 4) ? (dz < 0 ? NG : NG + NSUB - 1) : pk - NSUB * dz);
+    return U + toff[n] + fo + (sk * NB + sj) * NB + si;
+}
+
 // ---- LDS window access --------------------------------------------------------
 
 // The five window offsets of the line through (i,j,k) along (dx,dy,dz).
@@ -634,13 +656,14 @@ __device__ __forceinline__ void update_cell(const double *win, const double *kee
 // The work of one subgrid for one field group (HYD: hydro fields and point
 // states; else: species).  Both instantiations execute the same sequence of
 // barriers, so the hydro and species waves of a workgroup stay in step.
-template <bool HYD, bool VEL, bool CW>
+template <bool HYD, bool VEL, bool CW, bool GATHER>
 __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *zl, double *keep,
                                              double *run, int tid, int role, int nspec,
                                              const double *Us0, double *Os0, int fst0,
                                              double lam, bool rate, const Stage &stg, bool sym,
                                              int cwmode, double gamma, double gm1, double de,
-                                             double &amax_l, int &bits) {
+                                             double &amax_l, int &bits, const StepArgs &a, int s,
+                                             const double *Ug, int64_t *toff, int *tmode) {
     const int nf = 6 + nspec;
     double chk = 0.0;
     const int f0 = HYD ? 0 : 6, f1 = HYD ? 6 : nf;     // this wave's fields
@@ -666,21 +689,68 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
             r_off[q] = c;
         }
     }
+    // source of element q of plane pk, and of the density of the same cell.
+    // With GATHER the element's block cell (i, j) and field are derived again
+    // from the thread index at each load (cheaper than holding them), and its
+    // source is found through the map; lanes without an element read an
+    // interior cell of the subgrid itself.
+    auto gsrc_of = [&](int q, int pk, bool field) -> const double * {
+        const int e = opaque_v(tid) + q * NT;
+        const int f = e / NPLANE, c = e - f * NPLANE;
+        const bool ok = e < nf * NPLANE;
+        return gather_ptr(Ug, toff, tmode, (ok && field) ? f * fst0 : 0, ok ? c % NB : NG,
+                          ok ? c / NB : NG, pk);
+    };
+    auto src = [&](int q, int pk) -> const double * {
+        if (!GATHER) return Us0 + g_off[q] + pk * NPLANE;
+        return gsrc_of(q, pk, true);
+    };
+    auto src_rho = [&](int q, int pk) -> const double * {
+        if (!GATHER) return Us0 + r_off[q] + pk * NPLANE;
+        return gsrc_of(q, pk, false);
+    };
 
     lds_barrier();   // the previous subgrid's LDS reads are done
+    if (GATHER) {
+        // the ghost map's 27 entries, checked: a source must be a valid
+        // subgrid with at least this subgrid's fields; otherwise (and for the
+        // interior, entry 13) the subgrid itself with every axis clamped
+        if (tid < 27) {
+            const int64_t own = Us0 - Ug;
+            int64_t o = own;
+            int m = tid == 13 ? 0 : 7;
+            if (tid != 13) {
+                const int sb = a.gsrc[s * 27 + tid];
+                bool good = sb >= 0 && sb < a.n_sub;
+                if (good) {
+                    const int ns2 = a.n_species[sb];
+                    const int64_t o2 = a.offset[sb];
+                    good = ns2 >= 0 && ns2 <= 5 && ns2 >= nspec && o2 >= 0 && !(o2 & 1);
+                    if (good) {
+                        o = o2;
+                        m = a.gmode[s * 27 + tid];
+                    }
+                }
+                if (!good) bits |= HYDRO_STATUS_BADMETA;
+            }
+            toff[tid] = o;
+            tmode[tid] = m;
+        }
+        lds_barrier();
+    }
     // window: planes 0..4, then prefetch plane 5
     {
         double v[SLOTS][5];
 #pragma unroll
         for (int pl = 0; pl < SLOTS; pl++)
 #pragma unroll
-            for (int q = 0; q < 5; q++) v[pl][q] = Us0[g_off[q] + pl * NPLANE];
+            for (int q = 0; q < 5; q++) v[pl][q] = *src(q, pl);
         if (VEL) {
 #pragma unroll
             for (int pl = 0; pl < SLOTS; pl++)
 #pragma unroll
                 for (int q = 0; q < 2; q++) {
-                    const double rho = Us0[r_off[q] + pl * NPLANE];
+                    const double rho = *src_rho(q, pl);
                     if (mom[q]) v[pl][q] = v[pl][q] / rho;
                 }
         }
@@ -691,10 +761,10 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
     }
     double pf[5], pr[2];
 #pragma unroll
-    for (int q = 0; q < 5; q++) pf[q] = Us0[g_off[q] + 5 * NPLANE];
+    for (int q = 0; q < 5; q++) pf[q] = *src(q, 5);
     if (VEL) {
 #pragma unroll
-        for (int q = 0; q < 2; q++) pr[q] = Us0[r_off[q] + 5 * NPLANE];
+        for (int q = 0; q < 2; q++) pr[q] = *src_rho(q, 5);
     }
     lds_barrier();
 
@@ -879,10 +949,10 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
             for (int q = 0; q < 5; q++) dst[l_off[q]] = pf[q];
             if (k + 4 <= 13) {
 #pragma unroll
-                for (int q = 0; q < 5; q++) pf[q] = Us[g_off[q] + (k + 4) * NPLANE];
+                for (int q = 0; q < 5; q++) pf[q] = *src(q, k + 4);
                 if (VEL) {
 #pragma unroll
-                    for (int q = 0; q < 2; q++) pr[q] = Us[r_off[q] + (k + 4) * NPLANE];
+                    for (int q = 0; q < 2; q++) pr[q] = *src_rho(q, k + 4);
                 }
             }
         }
@@ -1034,13 +1104,15 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
 
 // ---- the kernel ---------------------------------------------------------------
 
-template <bool VEL, bool CW>
+template <bool VEL, bool CW, bool GATHER>
 __global__ __launch_bounds__(NT, 2) void k_fused(StepArgs a, const double *__restrict__ U,
                                                  double *Uo,
                                                  double *__restrict__ amax,
                                                  int32_t *__restrict__ status, int order) {
     __shared__ double lds[LDS_D];
     __shared__ int red_bits[8];
+    __shared__ int64_t g_toff[GATHER ? 27 : 1];    // ghost-map table of the current subgrid
+    __shared__ int g_tmode[GATHER ? 27 : 1];
     double *win = lds;
     double *xch = lds + WIN_D;
     double *zl = xch + XCH_D;          // z-face left partials carried between steps
@@ -1083,12 +1155,13 @@ __global__ __launch_bounds__(NT, 2) void k_fused(StepArgs a, const double *__res
         int bits = 0;
 
         if (hyd)
-            subgrid_body<true, VEL, CW>(win, xch, zl, keep, run, tid, role, nspec, Us0, Os0, fst0,
-                                        lam, rate, stg, sym, cwmode, gamma, gm1, de, amax_l, bits);
+            subgrid_body<true, VEL, CW, GATHER>(win, xch, zl, keep, run, tid, role, nspec, Us0, Os0,
+                                                fst0, lam, rate, stg, sym, cwmode, gamma, gm1, de,
+                                                amax_l, bits, a, s, U, g_toff, g_tmode);
         else
-            subgrid_body<false, VEL, CW>(win, xch, zl, keep, run, tid, role, nspec, Us0, Os0, fst0,
-                                         lam, rate, stg, sym, cwmode, gamma, gm1, de, amax_l,
-                                         bits);
+            subgrid_body<false, VEL, CW, GATHER>(win, xch, zl, keep, run, tid, role, nspec, Us0,
+                                                 Os0, fst0, lam, rate, stg, sym, cwmode, gamma, gm1,
+                                                 de, amax_l, bits, a, s, U, g_toff, g_tmode);
 
         // ---- per-subgrid speed and status
         for (int o = 32; o > 0; o >>= 1) {
@@ -1143,10 +1216,15 @@ int device_cus() {
 // carries neither.
 using FusedKernel = void (*)(StepArgs, const double *, double *, double *, int32_t *, int);
 
-FusedKernel fused_kernel(const StepArgs &a) {
+template <bool GATHER>
+FusedKernel fused_kernel_g(const StepArgs &a) {
     const bool cw = a.steepen || a.flatten;
-    if (a.vel) return cw ? k_fused<true, true> : k_fused<true, false>;
-    return cw ? k_fused<false, true> : k_fused<false, false>;
+    if (a.vel) return cw ? k_fused<true, true, GATHER> : k_fused<true, false, GATHER>;
+    return cw ? k_fused<false, true, GATHER> : k_fused<false, false, GATHER>;
+}
+
+FusedKernel fused_kernel(const StepArgs &a) {
+    return a.gsrc ? fused_kernel_g<true>(a) : fused_kernel_g<false>(a);
 }
 
 dim3 grid_of(const StepArgs &a, int v) {

@@ -58,6 +58,10 @@ struct StepArgs {
     double c0, c1;
     // per-subgrid output offsets (null: the input offsets)
     const int64_t *out_offset;
+    // ghost map (27 source subgrids and mode bits per subgrid, as in
+    // hydro_ghost_map): when set, the fused step reads ghost cells from the
+    // neighbours' interiors instead of the block's own ghost layers
+    const int32_t *gsrc, *gmode;
 };
 
 inline StepArgs make_args(const hydro_params *p, const hydro_batch *b) {
@@ -80,6 +84,8 @@ inline StepArgs make_args(const hydro_params *p, const hydro_batch *b) {
     a.c0 = 0.0;
     a.c1 = 1.0;
     a.out_offset = nullptr;
+    a.gsrc = nullptr;
+    a.gmode = nullptr;
     return a;
 }
 

@@ -23,6 +23,7 @@ EXPORTS = [
     "hydro_fill_ghosts", "hydro_rate", "hydro_cfl_dt", "hydro_rk_update",
     "hydro_rk3_create", "hydro_rk3_launch", "hydro_rk3_destroy", "hydro_tau_resync",
     "hydro_rk_stage", "hydro_step_io", "hydro_workspace_bytes", "hydro_subgrid_n",
+    "hydro_step_gather",
 ]
 
 STATUS_RHO, STATUS_P, STATUS_NONFINITE, STATUS_BADMETA = 1, 2, 4, 8
@@ -107,6 +108,7 @@ def lib(n: int = 8):
         L.hydro_tau_resync.argtypes = [P, B, vp, vp]
         L.hydro_rk_stage.argtypes = [P, B, vp, vp, vp, dbl, dbl, vp, vp, vp, vp]
         L.hydro_step_io.argtypes = [P, B, vp, vp, vp, vp, vp, vp]
+        L.hydro_step_gather.argtypes = [P, B, G, vp, vp, vp, vp, vp]
         if L.hydro_subgrid_n() != n:
             raise HydroError(f"{path} reports subgrid size {L.hydro_subgrid_n()}, not {n}")
         _libs[n] = L
@@ -313,6 +315,14 @@ class DeviceGhostMap:
 def fill_ghosts(batch: Batch, gmap: DeviceGhostMap, U, status=None, stream=None, n: int = 8):
     check(lib(n).hydro_fill_ghosts(ctypes.byref(batch), ctypes.byref(gmap.struct), _ptr(U),
                                   _ptr(status), _stream(stream)))
+
+
+def step_gather(prm: Params, batch: Batch, gmap: DeviceGhostMap, U_in, U_out, amax, status=None,
+                stream=None):
+    """Fused step reading ghost cells through the ghost map (no fill pass)."""
+    check(lib().hydro_step_gather(ctypes.byref(prm), ctypes.byref(batch), ctypes.byref(gmap.struct),
+                                  _ptr(U_in), _ptr(U_out), _ptr(amax), _ptr(status),
+                                  _stream(stream)))
 
 
 def rate(prm: Params, batch: Batch, U_in, R, amax, status=None, stream=None):
