@@ -249,17 +249,17 @@ __device__ __forceinline__ T opaque_v(T v) {
 
 // ---- ghost cells read through a ghost map -------------------------------------
 
-// Source of block cell (i, j, pk) of the field at offset fo when the ghost
-// layers are read through a ghost map (the ghost fill's rule, applied on
-// load): the direction of the cell's ghost region picks the table entry
-// (entry 13, the interior, is the subgrid itself); along each axis the index
-// steps N cells back into the neighbour, or clamps to the nearest interior
-// cell where the entry's mode bit for that axis is set.
+// Source of a block cell of plane pk when the ghost layers are read through a
+// ghost map (the ghost fill's rule, applied on load).  The cell is packed in g:
+// bits 0-3 i, 4-7 j, 8-9 dx + 1, 10-11 dy + 1 (its ghost direction in x and
+// y); fo is its field's offset.  The direction picks the table entry (entry
+// 13, the interior, is the subgrid itself); along each axis the index steps
+// N cells back into the neighbour, or clamps to the nearest interior cell
+// where the entry's mode bit for that axis is set.
 __device__ __forceinline__ const double *gather_ptr(const double *U, const int64_t *toff,
-                                                    const int *tmode, int fo, int i, int j,
-                                                    int pk) {
-    const int dx = i < NG ? -1 : (i >= NG + NSUB ? 1 : 0);
-    const int dy = j < NG ? -1 : (j >= NG + NSUB ? 1 : 0);
+                                                    const int *tmode, int fo, int g, int pk) {
+    const int i = g & 15, j = (g >> 4) & 15;
+    const int dx = ((g >> 8) & 3) - 1, dy = ((g >> 10) & 3) - 1;
     const int dz = pk < NG ? -1 : (pk >= NG + NSUB ? 1 : 0);
     const int n = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1);
     const int m = tmode[n];
@@ -682,7 +682,17 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
         const int e = tid + q * NT;
         const int f = e / NPLANE, c = e - f * NPLANE;
         const bool ok = e < nf * NPLANE;
-        g_off[q] = ok ? f * fst0 + c : 0;
+        if (!GATHER) {
+            g_off[q] = ok ? f * fst0 + c : 0;
+        } else {
+            // the element's block cell, its ghost direction in x and y, and
+            // its field, packed (lanes without an element: an interior cell
+            // of field 0)
+            const int i = ok ? c % NB : NG, j = ok ? c / NB : NG;
+            const int dx = i < NG ? -1 : (i >= NG + NSUB ? 1 : 0);
+            const int dy = j < NG ? -1 : (j >= NG + NSUB ? 1 : 0);
+            g_off[q] = i | (j << 4) | ((dx + 1) << 8) | ((dy + 1) << 10) | ((ok ? f : 0) << 12);
+        }
         l_off[q] = ok ? f * NPLANE + c : NF_MAX * NPLANE;
         if (q < 2) {
             mom[q] = VEL && ok && f >= 1 && f <= 3;
@@ -690,16 +700,11 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
         }
     }
     // source of element q of plane pk, and of the density of the same cell.
-    // With GATHER the element's block cell (i, j) and field are derived again
-    // from the thread index at each load (cheaper than holding them), and its
-    // source is found through the map; lanes without an element read an
-    // interior cell of the subgrid itself.
+    // With GATHER the source is found through the map from the packed
+    // geometry (the plane's z direction is the same for the whole wave).
     auto gsrc_of = [&](int q, int pk, bool field) -> const double * {
-        const int e = opaque_v(tid) + q * NT;
-        const int f = e / NPLANE, c = e - f * NPLANE;
-        const bool ok = e < nf * NPLANE;
-        return gather_ptr(Ug, toff, tmode, (ok && field) ? f * fst0 : 0, ok ? c % NB : NG,
-                          ok ? c / NB : NG, pk);
+        const int g = opaque_v(g_off[q]);   // derived values are not hoisted and kept live
+        return gather_ptr(Ug, toff, tmode, field ? (g >> 12) * fst0 : 0, g, pk);
     };
     auto src = [&](int q, int pk) -> const double * {
         if (!GATHER) return Us0 + g_off[q] + pk * NPLANE;
