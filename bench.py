@@ -278,10 +278,20 @@ def serving_run(torch, hydro, serving, b, db, peak_subgrids_per_s, n_requests, b
 
 
 def rk3_timing(torch, hydro, db, n_per_dim, periodic, steps):
-    """Device-resident SSP-RK3 time steps: three fused stages in rate form,
-    three ghost fills from the neighbour map, the on-device CFL step size and
-    three stage combinations, replayed as one hipGraph per time step."""
+    """Device-resident SSP-RK3 time steps: three fused stages that read their
+    ghost cells through the neighbour map, the on-device CFL step size and
+    the stage combinations, replayed as one hipGraph per time step.  Also
+    times the standalone ghost fill (hydro_fill_ghosts) of the same batch."""
     gm = hydro.DeviceGhostMap(*hydro.box_ghost_map(*n_per_dim, periodic=periodic))
+    hydro.fill_ghosts(db.struct, gm, db.U)
+    torch.cuda.synchronize()
+    f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    f0.record(torch.cuda.current_stream())
+    for _ in range(5):
+        hydro.fill_ghosts(db.struct, gm, db.U)
+    f1.record(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    fill_ms = f0.elapsed_time(f1) / 5
     rk = hydro.RK3(hydro.params(), db, gm, db.U, cfl=0.4)
     rk.launch(2)
     torch.cuda.synchronize()
@@ -299,7 +309,7 @@ def rk3_timing(torch, hydro, db, n_per_dim, periodic, steps):
     return {"ms_per_time_step": ms, "stages_per_step": 3,
             "stage_cell_updates_per_s": 3 * cells / (ms * 1e-3),
             "time_steps_per_s": 1e3 / ms, "simulated_time": t_sim,
-            "nonzero_status": st}
+            "nonzero_status": st, "ghost_fill_ms": fill_ms}
 
 
 def _oracle_slice(args):

@@ -707,11 +707,11 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
         return gather_ptr(Ug, toff, tmode, field ? (g >> 12) * fst0 : 0, g, pk);
     };
     auto src = [&](int q, int pk) -> const double * {
-        if (!GATHER) return Us0 + g_off[q] + pk * NPLANE;
+        if (!GATHER) return Us0 + (g_off[q] + pk * NPLANE);   // one 64-bit add, as an index
         return gsrc_of(q, pk, true);
     };
     auto src_rho = [&](int q, int pk) -> const double * {
-        if (!GATHER) return Us0 + r_off[q] + pk * NPLANE;
+        if (!GATHER) return Us0 + (r_off[q] + pk * NPLANE);
         return gsrc_of(q, pk, false);
     };
 

@@ -47,10 +47,11 @@ struct StepArgs {
     const int64_t *offset;
     const double *h;
     const int32_t *n_species;
-    int32_t rate;   // 0: U_out = U + dt L(U); 1: U_out = L(U) on the interior
-    int32_t sym;    // symmetric (Kurganov-Tadmor 2000) face speeds
-    int32_t vel;    // PPM of the velocities s / rho instead of the momenta
-    int32_t steepen, flatten;   // Colella-Woodward options
+    uint32_t rate : 1;      // 0: U_out = U + dt L(U); 1: U_out = L(U) on the interior
+    uint32_t sym : 1;       // symmetric (Kurganov-Tadmor 2000) face speeds
+    uint32_t vel : 1;       // PPM of the velocities s / rho instead of the momenta
+    uint32_t steepen : 1;   // Colella-Woodward contact steepening
+    uint32_t flatten : 1;   // Colella-Woodward flattening
     // Runge-Kutta stage form (U0 non-null): U_out = c0 U0 + c1 (U + dt L(U)),
     // or U0 where dt == 0; dt = clock[1] when clock is non-null, else dt.
     const double *clock;
