@@ -111,6 +111,7 @@ void tune_save_locked() {
 
 struct hydro_plan {
     StepArgs args;
+    FusedArgs fargs;     // the kernel node's argument block
     const double *U_in;
     double *U_out;
     double *amax;
@@ -319,7 +320,8 @@ int hydro_plan_create(const hydro_params *params, const hydro_batch *batch, cons
     p->status = status;
     int variant = hydro_selected_variant(batch->n_sub, 5);
     p->order = fused_variant_order(variant);
-    p->kargs[0] = &p->args;
+    p->fargs = fused_args(p->args);
+    p->kargs[0] = &p->fargs;
     p->kargs[1] = &p->U_in;
     p->kargs[2] = &p->U_out;
     p->kargs[3] = &p->amax;
@@ -340,6 +342,7 @@ int hydro_plan_create(const hydro_params *params, const hydro_batch *batch, cons
 int hydro_plan_set_dt(hydro_plan *plan, double dt) {
     if (!plan) return HYDRO_EINVAL;
     plan->args.dt = dt;
+    plan->fargs.dt = dt;
     hipError_t e = hipGraphExecKernelNodeSetParams(plan->exec, plan->node, &plan->np);
     return e == hipSuccess ? HYDRO_OK : fail_hip(e);
 }

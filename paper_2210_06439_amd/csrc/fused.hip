@@ -662,7 +662,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                                              const double *Us0, double *Os0, int fst0,
                                              double lam, bool rate, const Stage &stg, bool sym,
                                              int cwmode, double gamma, double gm1, double de,
-                                             double &amax_l, int &bits, const StepArgs &a, int s,
+                                             double &amax_l, int &bits, const FusedArgs &a, int s,
                                              const double *Ug, int64_t *toff, int *tmode) {
     const int nf = 6 + nspec;
     double chk = 0.0;
@@ -1110,7 +1110,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
 // ---- the kernel ---------------------------------------------------------------
 
 template <bool VEL, bool CW, bool GATHER>
-__global__ __launch_bounds__(NT, 2) void k_fused(StepArgs a, const double *__restrict__ U,
+__global__ __launch_bounds__(NT, 2) void k_fused(FusedArgs a, const double *__restrict__ U,
                                                  double *Uo,
                                                  double *__restrict__ amax,
                                                  int32_t *__restrict__ status, int order) {
@@ -1219,7 +1219,7 @@ int device_cus() {
 // The instantiation for the call's options: velocity reconstruction and the
 // Colella-Woodward weights each have their own kernel, so the default one
 // carries neither.
-using FusedKernel = void (*)(StepArgs, const double *, double *, double *, int32_t *, int);
+using FusedKernel = void (*)(FusedArgs, const double *, double *, double *, int32_t *, int);
 
 template <bool GATHER>
 FusedKernel fused_kernel_g(const StepArgs &a) {
@@ -1252,8 +1252,8 @@ int fused_variant_order(int v) {
 hipError_t launch_fused_step(const StepArgs &a, const double *U_in, double *U_out,
                              double *amax, int32_t *status, int variant, hipStream_t st) {
     if (a.n_sub == 0) return hipSuccess;
-    hipLaunchKernelGGL(fused_kernel(a), grid_of(a, variant), dim3(NT), 0, st, a, U_in, U_out,
-                       amax, status, kVariants[variant].order);
+    hipLaunchKernelGGL(fused_kernel(a), grid_of(a, variant), dim3(NT), 0, st, fused_args(a), U_in,
+                       U_out, amax, status, kVariants[variant].order);
     return hipGetLastError();
 }
 

@@ -47,11 +47,11 @@ struct StepArgs {
     const int64_t *offset;
     const double *h;
     const int32_t *n_species;
-    uint32_t rate : 1;      // 0: U_out = U + dt L(U); 1: U_out = L(U) on the interior
-    uint32_t sym : 1;       // symmetric (Kurganov-Tadmor 2000) face speeds
-    uint32_t vel : 1;       // PPM of the velocities s / rho instead of the momenta
-    uint32_t steepen : 1;   // Colella-Woodward contact steepening
-    uint32_t flatten : 1;   // Colella-Woodward flattening
+    int32_t rate;      // 0: U_out = U + dt L(U); 1: U_out = L(U) on the interior
+    int32_t sym;       // symmetric (Kurganov-Tadmor 2000) face speeds
+    int32_t vel;       // PPM of the velocities s / rho instead of the momenta
+    int32_t steepen;   // Colella-Woodward contact steepening
+    int32_t flatten;   // Colella-Woodward flattening
     // Runge-Kutta stage form (U0 non-null): U_out = c0 U0 + c1 (U + dt L(U)),
     // or U0 where dt == 0; dt = clock[1] when clock is non-null, else dt.
     const double *clock;
@@ -64,6 +64,55 @@ struct StepArgs {
     // neighbours' interiors instead of the block's own ghost layers
     const int32_t *gsrc, *gmode;
 };
+
+// The fused kernel's copy of the same parameters, with the option flags as
+// bits: the smaller argument block suits that kernel's code generation (the
+// plain kernels keep whole ints, which suit theirs).
+struct FusedArgs {
+    double gamma;
+    double de_switch;
+    double dt;
+    int32_t n_sub;
+    int32_t fstride;
+    const int64_t *offset;
+    const double *h;
+    const int32_t *n_species;
+    uint32_t rate : 1;
+    uint32_t sym : 1;
+    uint32_t vel : 1;
+    uint32_t steepen : 1;
+    uint32_t flatten : 1;
+    const double *clock;
+    const double *U0;
+    double c0, c1;
+    const int64_t *out_offset;
+    const int32_t *gsrc, *gmode;
+};
+
+inline FusedArgs fused_args(const StepArgs &a) {
+    FusedArgs f;
+    f.gamma = a.gamma;
+    f.de_switch = a.de_switch;
+    f.dt = a.dt;
+    f.n_sub = a.n_sub;
+    f.fstride = a.fstride;
+    f.offset = a.offset;
+    f.h = a.h;
+    f.n_species = a.n_species;
+    f.rate = a.rate ? 1 : 0;
+    f.sym = a.sym ? 1 : 0;
+    f.vel = a.vel ? 1 : 0;
+    f.steepen = a.steepen ? 1 : 0;
+    f.flatten = a.flatten ? 1 : 0;
+    f.clock = a.clock;
+    f.U0 = a.U0;
+    f.c0 = a.c0;
+    f.c1 = a.c1;
+    f.out_offset = a.out_offset;
+    f.gsrc = a.gsrc;
+    f.gmode = a.gmode;
+    return f;
+}
 
 inline StepArgs make_args(const hydro_params *p, const hydro_batch *b) {
     StepArgs a;
@@ -117,7 +166,8 @@ hipError_t launch_rk_update(int n_sub, int fstride, const int64_t *offset,
 int fused_variant_order(int v);
 hipError_t launch_tau_resync(const StepArgs &a, double *U, hipStream_t st);
 
-// The kernel node's argument block, for in-place dt updates of a captured graph.
+// The kernel node's parameters, for in-place dt updates of a captured graph;
+// arg_storage[0] must point at a FusedArgs (fused_args(a)).
 hipError_t fused_kernel_node_params(const StepArgs &a, const double *U_in, double *U_out,
                                     double *amax, int32_t *status, int variant,
                                     hipKernelNodeParams *out, void **arg_storage);
