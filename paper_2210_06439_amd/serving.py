@@ -261,11 +261,12 @@ class GpuBackend:
     sessions are copied in on a second stream, which the tick waits for.  A
     catalogue (a DeviceBatch whose subgrids each fill one slot-sized region,
     offset[s] = s * nf_max * fstride) lets requests name their inputs by
-    index; host arrays are accepted too.
+    index; host arrays are accepted too.  `flags` are the method options of
+    every tick (hydro_params.flags).
     """
 
     def __init__(self, n_slots: int, catalogue=None, gamma=5.0 / 3.0, de_switch=1e-3,
-                 nf_max: int = NF_MAX, fstride: int = FSTRIDE):
+                 nf_max: int = NF_MAX, fstride: int = FSTRIDE, flags: int = 0):
         import torch
 
         from . import hydro
@@ -282,7 +283,7 @@ class GpuBackend:
             off = catalogue.offset.cpu().numpy()
             if catalogue.fstride != fstride or np.any(off != np.arange(len(off)) * self.slot_elems):
                 raise ValueError("catalogue subgrids must each fill one slot-sized region")
-        self.gamma, self.de_switch = gamma, de_switch
+        self.gamma, self.de_switch, self.flags = gamma, de_switch, int(flags)
         self.compute = torch.cuda.Stream()
         self.copy = torch.cuda.Stream()
         self._load_ev = None
@@ -431,7 +432,8 @@ class GpuBackend:
                 b["ns"][:p].copy_(b["ns_h"][:p], non_blocking=True)
                 batch = hydro.Batch(p, self.fstride, b["off"].data_ptr(), b["h"].data_ptr(),
                                     b["ns"].data_ptr())
-                hydro.step_io(hydro.params(self.gamma, self.de_switch, dt), batch, b["oo"],
+                hydro.step_io(hydro.params(self.gamma, self.de_switch, dt, self.flags), batch,
+                              b["oo"],
                               self.pool, self.pool, b["amax"], b["status"], stream=st)
                 b["status_h"][:p].copy_(b["status"][:p], non_blocking=True)
             e = torch.cuda.Event(enable_timing=True)

@@ -31,8 +31,8 @@ def _requests(b):
     return out
 
 
-def _serve(db, reqs, n_slots, dt):
-    be = serving.GpuBackend(n_slots, catalogue=db)
+def _serve(db, reqs, n_slots, dt, flags=0):
+    be = serving.GpuBackend(n_slots, catalogue=db, flags=flags)
     finals = {}
 
     def grab(req, slots, copy):
@@ -60,6 +60,30 @@ def test_alone_equals_in_the_mix_and_matches_oracle(cat):
         for s in range(r.n):
             got[int(sub.offset[s]):int(sub.offset[s]) + SLOT] = mixed[r.rid][s].reshape(-1)
         assert max_err_step(sub, got, U) <= 1e-12 * r.steps
+
+
+def test_served_with_method_options(cat):
+    """Velocity reconstruction with Colella-Woodward steepening and
+    flattening in every tick: each request matches the oracle with the same
+    options (random states: no detector sits on its threshold)."""
+    b, db = cat
+    flags = hydro.VELOCITY | hydro.STEEPEN | hydro.FLATTEN
+    reqs = _requests(b)[:5]
+    recs, out = _serve(db, reqs, 12, b.dt, flags=flags)
+    assert all(not r.rejected and r.status == 0 for r in recs)
+    for r in reqs:
+        sub = b.subset(r.source)
+        U = sub.U
+        for _ in range(r.steps):
+            U, _, _ = oracle.step(U, sub.offset, sub.h, sub.n_species, sub.fstride, b.dt,
+                                  flags=flags)
+        got = sub.U.copy()
+        for s in range(r.n):
+            got[int(sub.offset[s]):int(sub.offset[s]) + SLOT] = out[r.rid][s].reshape(-1)
+        assert max_err_step(sub, got, U) <= 1e-12 * r.steps
+    # and the options made a difference
+    _, plain = _serve(db, reqs[:1], 12, b.dt)
+    assert not np.array_equal(plain[reqs[0].rid], out[reqs[0].rid])
 
 
 def test_host_array_sources(cat):
