@@ -205,10 +205,9 @@ def subgrid16_plain(torch, hydro, inputs, reps=5):
     return out
 
 
-def plain_vs_batched(torch, hydro, inputs, reps=3):
-    """Config 2 (64^3, 512 subgrids): one subgrid per launch vs one batched launch."""
-    b = inputs.config2()
-    db = hydro.DeviceBatch.from_inputs(b)
+def per_subgrid_vs_batched(torch, hydro, b, db, label, reps):
+    """One subgrid per launch (unfused three-kernel form and fused form)
+    against one batched launch, on the same batch."""
     prm = hydro.params(dt=b.dt)
     n = db.n_sub
     U_out = db.U.clone()
@@ -243,12 +242,22 @@ def plain_vs_batched(torch, hydro, inputs, reps=3):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
         out[name] = {"ms": dt * 1e3, "cell_updates_per_s": b.cell_updates / dt}
-        log(f"config2 {name}: {dt * 1e3:.2f} ms")
-    out["plain_batched_stages"] = plain_batched_stages(torch, hydro, db, prm)
+        log(f"{label} {name}: {dt * 1e3:.2f} ms")
     out["speedup_batched_vs_per_subgrid_unfused"] = (
         out["per_subgrid_unfused"]["ms"] / out["batched_fused"]["ms"])
     out["speedup_batched_vs_per_subgrid_fused"] = (
         out["per_subgrid_fused"]["ms"] / out["batched_fused"]["ms"])
+    del U_out, Q, F
+    return out
+
+
+def plain_vs_batched(torch, hydro, inputs, reps=3):
+    """Config 2 (64^3, 512 subgrids): one subgrid per launch vs one batched
+    launch, and the batched unfused stages."""
+    b = inputs.config2()
+    db = hydro.DeviceBatch.from_inputs(b)
+    out = per_subgrid_vs_batched(torch, hydro, b, db, "config2", reps)
+    out["plain_batched_stages"] = plain_batched_stages(torch, hydro, db, hydro.params(dt=b.dt))
     return out
 
 
@@ -487,6 +496,10 @@ def main():
     }
     if variants is not None:
         result["variants"] = variants
+    if not args.no_plain:
+        # the same comparison on the 128^3 batch (4096 subgrids), one timed pass
+        result["per_subgrid_vs_batched_config3"] = per_subgrid_vs_batched(torch, hydro, b, db,
+                                                                          "config3", 1)
     del U_out
     torch.cuda.empty_cache()
     if not args.no_serving:
