@@ -208,8 +208,11 @@ int hydro_ref_ppm1d(const double *u, double *qp_out, double *qm_out)
  */
 static double steepen_weight(double gamma, const double *rho, const double *p)
 {
-    double d2m = rho[2] - 2.0 * rho[1] + rho[0];
-    double d2p = rho[4] - 2.0 * rho[3] + rho[2];
+    /* each second difference adds its outer pair first: read backwards,
+     * the line gives the same two differences, bit for bit, so the weight
+     * keeps the scheme's mirror symmetry exactly */
+    double d2m = (rho[0] + rho[2]) - 2.0 * rho[1];
+    double d2p = (rho[2] + rho[4]) - 2.0 * rho[3];
     double drho = rho[3] - rho[1];
     if (!(d2p * d2m < 0.0)) return 0.0;
     if (!(fabs(drho) - CW_EPS1 * fmin(fabs(rho[3]), fabs(rho[1])) > 0.0)) return 0.0;

@@ -116,6 +116,27 @@ def test_reversal_swaps_faces_with_both_options():
         assert (rp, rm) == (qm, qp)
 
 
+
+def test_partial_steepening_is_bitwise_mirror_symmetric():
+    """Contacts whose weight lies strictly inside (0, 1), so that it enters
+    the interface values unclamped: the line read backwards (velocities
+    negated) gives the two interface values swapped, bit for bit.  That
+    needs both second differences to be formed with the same grouping."""
+    rng = np.random.default_rng(73)
+    partial = 0
+    for _ in range(4000):
+        lo, hi = rng.uniform(0.5, 1.5), rng.uniform(2.0, 4.0)
+        r = np.sort(np.concatenate([[lo, hi], rng.uniform(lo, hi, 3)]))
+        d2m = r[2] - 2.0 * r[1] + r[0]
+        d2p = r[4] - 2.0 * r[3] + r[2]
+        et = -(d2p - d2m) / (6.0 * (r[3] - r[1]))
+        if d2m * d2p < 0.0 and 0.05 < et < 0.1:
+            partial += 1
+        qp, qm = line(r, p=ONES, un=ZERO, flags=ST)
+        rp, rm = line(r[::-1].copy(), p=ONES, un=ZERO, flags=ST)
+        assert (rp, rm) == (qm, qp)
+    assert partial > 150
+
 # ---- whole subgrids ------------------------------------------------------------------
 
 NB = 14
