@@ -228,7 +228,8 @@ static double steepen_weight(double gamma, const double *rho, const double *p)
  * velocities un[0..4] along the line direction: nonzero only in a
  * compression (un_{j-1} > un_{j+1}) with a relative pressure jump
  * |p_{j+1} - p_{j-1}| / min(p_{j+1}, p_{j-1}) above eps; then
- * max(0, min(1, omega2 ((p_{j+1} - p_{j-1}) / (p_{j+2} - p_{j-2}) - omega1))).
+ * max(0, min(1, omega2 ((p_{j+1} - p_{j-1}) / (p_{j+2} - p_{j-2}) - omega1))),
+ * the ratio taken as +inf where p_{j+2} = p_{j-2}.
  * (The method also takes the larger weight of the upstream neighbour; that
  * needs pressures three cells away, beyond the ghost layers of the cells
  * reconstructed here, so the cell's own weight is used.)
@@ -238,7 +239,10 @@ static double flatten_weight(const double *p, const double *un)
     double dp1 = p[3] - p[1];
     if (!(un[1] - un[3] > 0.0)) return 0.0;
     if (!(fabs(dp1) / fmin(p[3], p[1]) > CW_EPS_SHOCK)) return 0.0;
-    double ratio = dp1 / (p[4] - p[0]);
+    double dp2 = p[4] - p[0];
+    /* equal outer pressures: the ratio is read as +inf, whichever way the
+     * line runs (a quotient by +0 would be +inf one way and -inf the other) */
+    double ratio = dp2 != 0.0 ? dp1 / dp2 : INFINITY;
     return fmax(0.0, fmin(1.0, CW_OMEGA2 * (ratio - CW_OMEGA1)));
 }
 

@@ -103,6 +103,20 @@ def test_flattening_gates():
     assert line(u, rho=ONES, p=p, un=un, density=False, flags=FL) == (3.1875, 2.8125)
 
 
+
+def test_equal_outer_pressures_flatten_fully_in_either_direction():
+    """p_{j+2} = p_{j-2} with a shock-sized p_{j+1} - p_{j-1} in a
+    compression: the ratio (p_{j+1} - p_{j-1}) / (p_{j+2} - p_{j-2}) has a
+    zero denominator, and is read as +inf whichever way the line runs, so the
+    weight is 1 and both interface values are the cell value.  (A quotient
+    by +0 would give +inf one way and -inf the other.)"""
+    u = np.array([1.0, 2.0, 3.0, 4.0, 5.0])
+    p = np.array([1.0, 1.0, 2.0, 9.0, 1.0])
+    un = np.array([0.0, 1.0, 0.0, -1.0, 0.0])
+    assert line(u, rho=ONES, p=p, un=un, density=False, flags=FL) == (3.0, 3.0)
+    assert line(u[::-1].copy(), rho=ONES, p=p[::-1].copy(), un=-un[::-1], density=False,
+                flags=FL) == (3.0, 3.0)
+
 def test_reversal_swaps_faces_with_both_options():
     rng = np.random.default_rng(70)
     for _ in range(300):
