@@ -303,11 +303,18 @@ struct CwW {
 
 // Pressure and velocity along (dx, dy, dz) of the window cell at offset o,
 // with the point-state formulas (dual-energy switch included).  With VEL the
-// momentum slots hold velocities.
+// momentum slots hold velocities.  The detectors that take these are
+// discontinuous in them, and a cell's weights are formed again by every
+// wave whose lines pass through it -- at a subgrid's edge by both
+// neighbours, which must agree for the face flux to be conservative -- so
+// the arithmetic is fixed: no contraction and the rounded quotient, in the
+// order of the definition (the dual-energy branch takes tau_pow, as the
+// point states do).
 template <bool VEL>
 __device__ __forceinline__ void cw_cell(const double *win, int o, int dx, int dy, int dz,
                                         double gamma, double gm1, double de, double &p,
                                         double &un) {
+#pragma clang fp contract(off)
     const double rho = win[o];
     const double m1 = win[o + NPLANE], m2 = win[o + 2 * NPLANE], m3 = win[o + 3 * NPLANE];
     double vx, vy, vz, ek;
@@ -317,7 +324,7 @@ __device__ __forceinline__ void cw_cell(const double *win, int o, int dx, int dy
         vz = m3;
         ek = 0.5 * (((rho * vx) * vx + (rho * vy) * vy) + (rho * vz) * vz);
     } else {
-        const double r = recip(rho);
+        const double r = 1.0 / rho;
         vx = m1 * r;
         vy = m2 * r;
         vz = m3 * r;
@@ -333,7 +340,7 @@ __device__ __forceinline__ void cw_cell(const double *win, int o, int dx, int dy
 // The weights of the line l along (dx, dy, dz).  mode: bit 0 steepening, bit 1
 // flattening.  Flattening: in a compression along the line with a relative
 // pressure jump above eps, clamp(omega2 ((p_1 - p_-1) / (p_2 - p_-2) -
-// omega1), 0, 1).  Steepening: where the density's second differences on the
+// omega1), 0, 1), the ratio +inf where p_2 = p_-2.  Steepening: where the density's second differences on the
 // two sides have opposite signs, its jump exceeds eps1 of the smaller density
 // and gamma K0 |jump| / min rho >= |p_1 - p_-1| / min p, clamp(eta1 (eta~ -
 // eta2), 0, 1) with eta~ = -(D_1 - D_-1) / (6 (rho_1 - rho_-1)).  Both are
@@ -342,6 +349,7 @@ template <bool VEL>
 __device__ __forceinline__ CwW cw_weights(const double *win, const Line5 &l, int dx, int dy,
                                           int dz, double gamma, double gm1, double de, int mode,
                                           bool need_eta) {
+#pragma clang fp contract(off)
     double p[5], un[5];
 #pragma unroll
     for (int m = 0; m < 5; m++)
@@ -352,7 +360,9 @@ __device__ __forceinline__ CwW cw_weights(const double *win, const Line5 &l, int
     if (mode & 2) {
         const double dp1 = p[3] - p[1];
         const bool shock = (un[1] - un[3] > 0.0) && (fabs(dp1) / fmin(p[3], p[1]) > CW_EPS_SHOCK);
-        const double ratio = dp1 / (p[4] - p[0]);
+        const double dp2 = p[4] - p[0];
+        // equal outer pressures: +inf in either direction of the line
+        const double ratio = dp2 != 0.0 ? dp1 / dp2 : INFINITY;
         const double f = fmax(0.0, fmin(1.0, CW_OMEGA2 * (ratio - CW_OMEGA1)));
         w.flat = shock ? f : 0.0;
     }
@@ -360,8 +370,9 @@ __device__ __forceinline__ CwW cw_weights(const double *win, const Line5 &l, int
         double r[5];
 #pragma unroll
         for (int m = 0; m < 5; m++) r[m] = win[l.o[m]];
-        const double d2m = r[2] - 2.0 * r[1] + r[0];
-        const double d2p = r[4] - 2.0 * r[3] + r[2];
+        // outer pair first: a line and its reverse give the same bits
+        const double d2m = (r[0] + r[2]) - 2.0 * r[1];
+        const double d2p = (r[2] + r[4]) - 2.0 * r[3];
         const double drho = r[3] - r[1];
         const bool contact =
             (d2p * d2m < 0.0) &&

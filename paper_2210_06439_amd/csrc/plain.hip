@@ -113,8 +113,9 @@ __device__ inline void cell_p_un(const StepArgs &a, const double *Us, int c, int
 // then eta = clamp(eta1 (eta~ - eta2), 0, 1) with
 // eta~ = -(D_{j+1} - D_{j-1}) / (6 (rho_{j+1} - rho_{j-1})).
 __device__ inline double steepen_weight(double gamma, const double *rho, const double *p) {
-    const double d2m = rho[2] - 2.0 * rho[1] + rho[0];
-    const double d2p = rho[4] - 2.0 * rho[3] + rho[2];
+    // outer pair first: the reversed line gives the same bits
+    const double d2m = (rho[0] + rho[2]) - 2.0 * rho[1];
+    const double d2p = (rho[2] + rho[4]) - 2.0 * rho[3];
     const double drho = rho[3] - rho[1];
     if (!(d2p * d2m < 0.0)) return 0.0;
     if (!(fabs(drho) - CW_EPS1 * fmin(fabs(rho[3]), fabs(rho[1])) > 0.0)) return 0.0;
@@ -127,14 +128,17 @@ __device__ inline double steepen_weight(double gamma, const double *rho, const d
 
 // Flattening weight of the middle cell: in a compression along the line with
 // a relative pressure jump above eps,
-// clamp(omega2 ((p_{j+1} - p_{j-1}) / (p_{j+2} - p_{j-2}) - omega1), 0, 1).
+// clamp(omega2 ((p_{j+1} - p_{j-1}) / (p_{j+2} - p_{j-2}) - omega1), 0, 1),
+// the ratio +inf where p_{j+2} = p_{j-2}.
 // (The neighbour's weight, which needs pressures three cells away, beyond
 // the ghost layers of the reconstructed cells, is not taken.)
 __device__ inline double flatten_weight(const double *p, const double *un) {
     const double dp1 = p[3] - p[1];
     if (!(un[1] - un[3] > 0.0)) return 0.0;
     if (!(fabs(dp1) / fmin(p[3], p[1]) > CW_EPS_SHOCK)) return 0.0;
-    const double ratio = dp1 / (p[4] - p[0]);
+    const double dp2 = p[4] - p[0];
+    // equal outer pressures: +inf in either direction of the line
+    const double ratio = dp2 != 0.0 ? dp1 / dp2 : INFINITY;
     return fmax(0.0, fmin(1.0, CW_OMEGA2 * (ratio - CW_OMEGA1)));
 }
 
