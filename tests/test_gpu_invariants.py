@@ -1,7 +1,8 @@
 """The oracle's invariants, run directly on the GPU: linear data reconstructed
-exactly, mirror symmetry and axis-permutation symmetry of the step, in the
-plain form (which evaluates in the oracle's order: bitwise) and in the fused
-form (which sums in another order: to rounding)."""
+exactly, mirror symmetry (also with the Colella-Woodward options) and
+axis-permutation symmetry of the step, in the plain form (which evaluates in
+the oracle's order: bitwise) and in the fused form (which sums in another
+order: to rounding)."""
 import numpy as np
 import pytest
 
@@ -40,7 +41,7 @@ def test_linear_data_reconstructed_exactly_plain():
 
 
 @pytest.mark.parametrize("axis", [0, 1, 2])
-@pytest.mark.parametrize("flags", [0, hydro.VELOCITY])
+@pytest.mark.parametrize("flags", [0, hydro.VELOCITY, hydro.STEEPEN | hydro.FLATTEN])
 def test_mirror_symmetry(axis, flags):
     b = inputs.config1(seed=21)
     blk = np.array(b.block(0))
