@@ -1136,8 +1136,10 @@ __global__ __launch_bounds__(NT, 2) void k_fused(FusedArgs a, const double *__re
     double *run = keep + KEEP_D;       // ring lanes' normal velocity
     double *red = run + RUN_D;
 
-    const int tid = threadIdx.x, wave = tid >> 6;
-    const int role = wave & 3;           // wave-uniform
+    // the wave index as a scalar: branches on the role and on the field group
+    // are then uniform branches, with no exec-mask bookkeeping
+    const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int role = wave & 3;
     const bool hyd = wave < 4;
 
     const double gamma = a.gamma, gm1 = a.gamma - 1.0, de = a.de_switch;
