@@ -1136,10 +1136,11 @@ __global__ __launch_bounds__(NT, 2) void k_fused(FusedArgs a, const double *__re
     double *run = keep + KEEP_D;       // ring lanes' normal velocity
     double *red = run + RUN_D;
 
-    // the wave index as a scalar: branches on the role and on the field group
-    // are then uniform branches, with no exec-mask bookkeeping
-    const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int role = wave & 3;
+    // the role as a scalar: branches on it are then uniform branches, with no
+    // exec-mask bookkeeping.  (The field-group test stays a vector compare: as
+    // a scalar it made the allocator spill 108 bytes per lane instead of none.)
+    const int tid = threadIdx.x, wave = tid >> 6;
+    const int role = __builtin_amdgcn_readfirstlane(wave) & 3;
     const bool hyd = wave < 4;
 
     const double gamma = a.gamma, gm1 = a.gamma - 1.0, de = a.de_switch;
