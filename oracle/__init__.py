@@ -20,27 +20,40 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hydro_ref.c")
-_LIB = os.path.join(_HERE, "libhydro_ref.so")
 SUBGRID_SIZES = (8, 16)     # interior cells per dimension; 8 is the default
 
 CFLAGS = ["-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
           "-fno-fast-math", "-Wall", "-Wextra"]
+# The sanitizer build (HYDRO_REF_SANITIZE=1 in the environment): address and
+# undefined-behaviour checks, every finding fatal.  A process that loads it
+# must have the address-sanitizer runtime preloaded (LD_PRELOAD).
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+             "-fno-omit-frame-pointer", "-g"]
 
 
-def lib_path(n: int = 8) -> str:
-    return _LIB if n == 8 else os.path.join(_HERE, f"libhydro_ref_n{n}.so")
+def sanitized() -> bool:
+    return os.environ.get("HYDRO_REF_SANITIZE", "") == "1"
 
 
-def build(force: bool = False, n: int | None = None) -> str:
+def lib_path(n: int = 8, san: bool | None = None) -> str:
+    san = sanitized() if san is None else san
+    base = "libhydro_ref" + ("" if n == 8 else f"_n{n}") + ("_san" if san else "")
+    return os.path.join(_HERE, base + ".so")
+
+
+def build(force: bool = False, n: int | None = None, san: bool | None = None) -> str:
     """Compile the oracle with gcc into ``oracle/libhydro_ref.so`` (subgrid
-    size 8) and ``libhydro_ref_n16.so`` (size 16); returns the size-n path."""
+    size 8) and ``libhydro_ref_n16.so`` (size 16), or their ``_san``
+    sanitizer builds; returns the size-n path."""
+    san = sanitized() if san is None else san
     for m in (SUBGRID_SIZES if n is None else (n,)):
-        path = lib_path(m)
+        path = lib_path(m, san)
         if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
             tmp = path + ".tmp"
-            subprocess.run(["gcc", *CFLAGS, f"-DREF_N={m}", "-o", tmp, _SRC, "-lm"], check=True)
+            subprocess.run(["gcc", *CFLAGS, *(SAN_FLAGS if san else []), f"-DREF_N={m}", "-o",
+                            tmp, _SRC, "-lm"], check=True)
             os.replace(tmp, path)
-    return lib_path(8 if n is None else n)
+    return lib_path(8 if n is None else n, san)
 
 
 class Params(ctypes.Structure):
@@ -257,6 +270,43 @@ def step(U_in, offset, h, n_species, fstride, dt, gamma=5.0 / 3.0, de_switch=1e-
                               _dp(U_out), _dp(amax),
                               status.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
     assert rc == 0, rc
+    return U_out, amax, status
+
+
+def step_threaded(U_in, offset, h, n_species, fstride, dt, threads=None, **kw):
+    """oracle.step over disjoint slices of the batch in threads (the C calls
+    release the interpreter lock, and the oracle keeps no global state); the
+    result is the single-threaded one, subgrid by subgrid."""
+    from concurrent.futures import ThreadPoolExecutor
+    offset = np.ascontiguousarray(offset, dtype=np.int64)
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    n_species = np.ascontiguousarray(n_species, dtype=np.int32)
+    n = len(offset)
+    threads = threads or min(16, os.cpu_count() or 1)
+    U_in = _f64(U_in)
+    U_out = U_in.copy()
+    amax = np.zeros(n)
+    status = np.zeros(n, dtype=np.int32)
+    bounds = np.linspace(0, n, min(threads, max(n, 1)) + 1).astype(int)
+
+    def run(lo, hi):
+        if hi <= lo:
+            return
+        ba = _BatchArgs(offset[lo:hi], h[lo:hi], n_species[lo:hi], fstride)
+        prm = params(kw.get("gamma", 5.0 / 3.0), kw.get("de_switch", 1e-3), dt, kw.get("flags", 0))
+        st = np.zeros(hi - lo, dtype=np.int32)
+        am = np.zeros(hi - lo)
+        # outputs go straight into U_out: the slices' interiors are disjoint
+        rc = lib(kw.get("n", 8)).hydro_ref_step(
+            ctypes.byref(prm), ctypes.byref(ba.struct), _dp(U_in), _dp(U_out), _dp(am),
+            st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        assert rc == 0, rc
+        amax[lo:hi] = am
+        status[lo:hi] = st
+
+    lib(kw.get("n", 8))
+    with ThreadPoolExecutor(len(bounds) - 1) as ex:
+        list(ex.map(lambda i: run(bounds[i], bounds[i + 1]), range(len(bounds) - 1)))
     return U_out, amax, status
 
 

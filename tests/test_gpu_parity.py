@@ -1,17 +1,22 @@
 """GPU parity: the HIP library against the CPU oracle on the same seeded
 inputs, through the C ABI.
 
-Bar: 1e-12 mixed-relative per cell for the fused step (it sums the Simpson
-terms in another order); the unfused kernels evaluate every expression in
-the oracle's order, so Q, F and U_out are expected bit for bit wherever the
-dual-energy switch (the only `pow`) does not fire.
+Bar: 1e-12 relative per cell for the fused step (it sums the Simpson terms
+in another order): plain relative error for density, energy and the entropy
+tracer, relative to a per-subgrid scale floor for the momenta and species,
+which can be zero (tests/metrics.py); the mixed measure with a floor on every
+field is printed beside it.  The unfused kernels evaluate every expression
+in the oracle's order, so Q, F and U_out are expected bit for bit wherever
+the dual-energy switch (the only `pow`) does not fire.  The full-size
+batches are compared subgrid by subgrid over the whole batch, with the
+oracle run in threads.
 """
 import numpy as np
 import pytest
 
 import oracle
 from gpu_util import device_batch, gpu_plain, gpu_step, rel
-from metrics import field_scales, max_err_step, mixed_rel
+from metrics import max_err_both, max_err_step
 from paper_2210_06439_amd import hydro, inputs
 
 pytestmark = pytest.mark.gpu
@@ -23,6 +28,12 @@ def ref_step(b, dt=None, idx=None, flags=0):
     if idx is not None:
         b = b.subset(idx)
     return oracle.step(b.U, b.offset, b.h, b.n_species, b.fstride, dt, flags=flags)
+
+
+def ref_step_all(b, dt=None, flags=0):
+    """The oracle over a whole (large) batch, in threads."""
+    dt = b.dt if dt is None else dt
+    return oracle.step_threaded(b.U, b.offset, b.h, b.n_species, b.fstride, dt, flags=flags)
 
 
 def ref_plain(b):
@@ -59,8 +70,8 @@ def test_fused_step_matches_oracle(cfg):
         b = inputs.config1(seed=33, n_species=0)
     Ug, ag, sg = gpu_step(b)
     Ur, ar, sr = ref_step(b)
-    err = max_err_step(b, Ug, Ur)
-    print(f"{cfg}: max mixed-rel err {err:.3e}")
+    err, mixed = max_err_both(b, Ug, Ur)
+    print(f"{cfg}: max per-cell rel err {err:.3e} (mixed {mixed:.3e})")
     assert err <= TOL
     assert rel(ag, ar) <= 1e-13
     assert np.array_equal(sg, sr)
@@ -77,9 +88,9 @@ def test_fused_config2_full_mesh():
     oracle on every subgrid; total mass/momentum/energy conserved."""
     b = inputs.config2()
     Ug, ag, sg = gpu_step(b)
-    Ur, ar, sr = ref_step(b)
-    err = max_err_step(b, Ug, Ur)
-    print(f"config2: max mixed-rel err {err:.3e}")
+    Ur, ar, sr = ref_step_all(b)
+    err, mixed = max_err_both(b, Ug, Ur)
+    print(f"config2: max per-cell rel err {err:.3e} (mixed {mixed:.3e})")
     assert err <= TOL and rel(ag, ar) <= 1e-13
     assert np.all(sg == 0)
     mom = sum(np.sum(np.sqrt(b.interior(s)[0] * b.interior(s)[4])) for s in range(b.n_sub))
@@ -117,81 +128,68 @@ def test_plain_per_subgrid_launches_config2_sample():
     assert np.array_equal(amax.cpu().numpy()[idx], ar)
 
 
-def test_config3_full_size_sampled():
-    """128^3 binary star (4096 subgrids) in one launch; 24 sampled subgrids,
-    including ones in the floor region where the dual-energy switch fires,
-    recomputed by the oracle one by one."""
+def test_config3_full_size():
+    """128^3 binary star (4096 subgrids) in one launch, every subgrid against
+    the oracle (the floor region, where the dual-energy switch fires,
+    included)."""
     b = inputs.config3()
     Ug, ag, sg = gpu_step(b)
-    rng = np.random.default_rng(7)
-    rho_max = np.array([b.interior(s)[0].max() for s in range(b.n_sub)])
-    floor = np.flatnonzero(rho_max < 1e-6)
-    dense = np.flatnonzero(rho_max > 0.1)
-    idx = np.unique(np.concatenate([rng.choice(b.n_sub, 12, replace=False),
-                                    rng.choice(floor, 6, replace=False),
-                                    rng.choice(dense, 6, replace=False), [0, b.n_sub - 1]]))
-    sub = b.subset(idx)
-    Ur, ar, sr = ref_step(sub, dt=b.dt)
-    worst = 0.0
-    for n, s in enumerate(idx):
-        S = field_scales(np.array(b.block(s)))
-        e = mixed_rel(b.interior(s, Ug), sub.interior(n, Ur), S)
-        worst = max(worst, float(e.max()))
-    print(f"config3 sampled: max mixed-rel err {worst:.3e}")
-    assert worst <= TOL
-    assert rel(ag[idx], ar) <= 1e-13
-    assert np.array_equal(sg[idx], sr)
-    assert np.all(sg == 0)
+    Ur, ar, sr = ref_step_all(b)
+    err, mixed = max_err_both(b, Ug, Ur)
+    print(f"config3: max per-cell rel err {err:.3e} (mixed {mixed:.3e})")
+    assert err <= TOL
+    assert rel(ag, ar) <= 1e-13
+    assert np.array_equal(sg, sr) and np.all(sg == 0)
 
 
 @pytest.mark.parametrize("flags", [hydro.KT_SYMMETRIC, hydro.VELOCITY,
                                    hydro.VELOCITY | hydro.KT_SYMMETRIC])
-def test_config3_full_size_sampled_with_options(flags):
+def test_config3_full_size_with_options(flags):
     """The benchmark's variant runs: the whole 128^3 batch in one launch with
-    each fused-path option, 16 sampled subgrids (floor and dense ones
-    included) against the oracle with the same option."""
+    each fused-path option, every subgrid against the oracle with the same
+    option."""
     b = inputs.config3()
     Ug, ag, sg = gpu_step(b, flags=flags)
-    rng = np.random.default_rng(8)
-    rho_max = np.array([b.interior(s)[0].max() for s in range(b.n_sub)])
-    idx = np.unique(np.concatenate([rng.choice(b.n_sub, 8, replace=False),
-                                    rng.choice(np.flatnonzero(rho_max < 1e-6), 4, replace=False),
-                                    rng.choice(np.flatnonzero(rho_max > 0.1), 4, replace=False)]))
-    sub = b.subset(idx)
-    Ur, ar, sr = ref_step(sub, dt=b.dt, flags=flags)
-    for n, s in enumerate(idx):
-        S = field_scales(np.array(b.block(s)))
-        assert float(mixed_rel(b.interior(s, Ug), sub.interior(n, Ur), S).max()) <= TOL, s
-    assert rel(ag[idx], ar) <= 1e-13
-    assert np.array_equal(sg[idx], sr) and np.all(sg == 0)
+    Ur, ar, sr = ref_step_all(b, flags=flags)
+    err, mixed = max_err_both(b, Ug, Ur)
+    print(f"config3 flags {flags}: max per-cell rel err {err:.3e} (mixed {mixed:.3e})")
+    assert err <= TOL
+    assert rel(ag, ar) <= 1e-13
+    assert np.array_equal(sg, sr) and np.all(sg == 0)
 
 
 def test_config4_mixed_species_launch():
     b = inputs.config4(launch=3)
     assert set(np.unique(b.n_species)) <= {0, 5}
     Ug, ag, sg = gpu_step(b)
-    idx = np.unique(np.linspace(0, b.n_sub - 1, min(b.n_sub, 16)).astype(int))
-    sub = b.subset(idx)
-    Ur, ar, sr = ref_step(sub, dt=b.dt)
-    for n, s in enumerate(idx):
-        S = field_scales(np.array(b.block(s)))
-        assert float(mixed_rel(b.interior(s, Ug), sub.interior(n, Ur), S).max()) <= TOL
-    assert rel(ag[idx], ar) <= 1e-13
+    Ur, ar, sr = ref_step_all(b)
+    err, mixed = max_err_both(b, Ug, Ur)
+    print(f"config4 launch 3 ({b.n_sub} subgrids): max per-cell rel err {err:.3e} (mixed {mixed:.3e})")
+    assert err <= TOL
+    assert rel(ag, ar) <= 1e-13
+    assert np.array_equal(sg, sr)
 
 
 @pytest.mark.parametrize("variant", [None, 2])
-def test_config4_maximum_batch_sampled(variant):
+def test_config4_maximum_batch(variant):
     """The largest uneven batch (8192 subgrids, levels 0-4, 0 or 5 species),
-    in the tuned launch shape and in one workgroup per subgrid: sampled
-    subgrids against the oracle, every status word clear."""
+    in the tuned launch shape and in one workgroup per subgrid: every
+    subgrid against the oracle, every status word clear."""
     b = inputs.config4(launch=9, n_override=8192)
     Ug, ag, sg = gpu_step(b, variant=variant)
     assert np.all(sg == 0) and np.all(ag > 0)
-    idx = np.unique(np.concatenate([[0, b.n_sub - 1],
-                                    np.random.default_rng(7).choice(b.n_sub, 14, replace=False)]))
-    sub = b.subset(idx)
-    Ur, ar, sr = ref_step(sub, dt=b.dt)
-    for n, s in enumerate(idx):
-        S = field_scales(np.array(b.block(s)))
-        assert float(mixed_rel(b.interior(s, Ug), sub.interior(n, Ur), S).max()) <= TOL
-    assert rel(ag[idx], ar) <= 1e-13
+    Ur, ar, sr = _config4_max_ref(b)
+    err, mixed = max_err_both(b, Ug, Ur)
+    print(f"config4 8192 variant {variant}: max per-cell rel err {err:.3e} (mixed {mixed:.3e})")
+    assert err <= TOL
+    assert rel(ag, ar) <= 1e-13
+    assert np.array_equal(sg, sr)
+
+
+_REF_CACHE = {}
+
+
+def _config4_max_ref(b):
+    if "c4max" not in _REF_CACHE:
+        _REF_CACHE["c4max"] = ref_step_all(b)
+    return _REF_CACHE["c4max"]

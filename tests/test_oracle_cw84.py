@@ -209,7 +209,7 @@ def test_blast_with_flattening_is_rounding_decided():
     step stays well conditioned -- so the blast with flattening is compared
     with the oracle through conservation and the solution, not cell by cell."""
     from mesh_util import refill
-    from metrics import max_err_step
+    from metrics import max_err_step_mixed as max_err_step
     b = inputs.sedov(32)
     fill = refill(b, (4, 4, 4), (True, True, True))
     errs = {}
@@ -309,7 +309,7 @@ def test_sod_with_the_options():
 
 def _ulp_sensitivity(b, flags):
     """How far the step moves when every momentum changes by one ulp."""
-    from metrics import max_err_step
+    from metrics import max_err_step_mixed as max_err_step
     U1, _, _ = oracle.step(b.U, b.offset, b.h, b.n_species, b.fstride, b.dt, flags=flags)
     Up = b.U.copy()
     for s in range(b.n_sub):
