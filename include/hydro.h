@@ -29,7 +29,9 @@
  *  - Pointers named U, Q, F, amax, status and every array inside hydro_batch
  *    are DEVICE pointers owned by the caller; `params` and `batch` themselves
  *    are host pointers read during the call.  Nothing is retained after the
- *    call returns, except by hydro_plan_create (see there).
+ *    call returns, except by hydro_plan_create and hydro_rk3_create (see
+ *    there) and the scratch of the split launch shapes (see
+ *    hydro_workspace_bytes).
  *  - Every call enqueues its kernels on `stream` (a hipStream_t; NULL means
  *    the default stream) and returns without synchronising.
  *  - Return value: HYDRO_OK, or a negative HYDRO_E* code; hydro_strerror()
@@ -214,15 +216,40 @@ int hydro_subgrid_n(void);
 /* Text for a return code (static storage; HIP detail for HYDRO_ELAUNCH). */
 const char *hydro_strerror(int code);
 
-/* Device memory the library holds between calls: always 0.  No entry point
- * allocates device memory; every buffer (including the unfused form's Q and
- * F, and the work buffers of the time integration) belongs to the caller. */
+/* Device memory the library holds between calls on the current device, in
+ * bytes.  The fused step's split and dynamic launch shapes (below) keep
+ * per-subgrid partial results and work counters in scratch: 64 + 16 n_sub
+ * bytes, zero between launches.  The eager entry points (hydro_step,
+ * hydro_step_variant, hydro_step_io, hydro_step_gather, hydro_rate,
+ * hydro_rk_stage, hydro_autotune) use one such buffer per (device, stream),
+ * allocated (hipMalloc, synchronously zero-filled) the first time a launch on
+ * that stream needs it and grown when a larger batch needs more, so that
+ * first call must not be made while the stream is being captured; launches
+ * on one stream run in order and share it.  Plans and RK3 graphs allocate
+ * their own at creation and free it when destroyed.  Every other buffer
+ * (the unfused form's Q and F, the time integration's work buffers) belongs
+ * to the caller.  0 on a host without a GPU. */
 int64_t hydro_workspace_bytes(void);
 
 /* ---------------------------------------------------------------------------
  * Launch variants and the autotuner.  The fused step has several launch
- * shapes (workgroups per CU, subgrid scheduling order); all of them compute
- * bitwise-identical results.
+ * shapes; all of them compute bitwise-identical results:
+ *   0 persistent-1x          one workgroup per CU, subgrids in a static stride
+ *   1 persistent-2x          two per CU (the second wave evens out the tail)
+ *   2 one-per-subgrid        one workgroup per subgrid
+ *   3 persistent-1x-rev      as 0, subgrids in reverse order
+ *   4 persistent-1x-dynamic  as 0, each workgroup fetching its next subgrid
+ *                            from a counter (scratch)
+ *   5, 6, 7 split-2/4/8      each subgrid's sweep along z cut into 2, 4 or 8
+ *                            parts of 4, 2 or 1 interior planes, one
+ *                            workgroup each; a part also computes the z face
+ *                            below and above its planes, in the same
+ *                            arithmetic as a whole sweep, and the last part
+ *                            to finish combines the subgrid's amax and
+ *                            status words (scratch).  More work in all, but
+ *                            a batch of fewer subgrids than CUs runs on more
+ *                            of the chip (one subgrid: 141 us whole, 36 us in
+ *                            8 parts, on an MI355X).
  */
 
 /* Number of launch variants of the fused step, and a short name for each. */
@@ -246,16 +273,21 @@ int hydro_autotune(const hydro_params *params, const hydro_batch *batch,
                    const double *U_in, double *U_out, double *amax,
                    int32_t *status, int reps, float *times_ms, void *stream);
 
-/* The variant hydro_step will use for a batch of n_sub subgrids (the tuned one
- * for that power-of-two bucket, else the default, variant 1).  max_species is reserved:
- * the choice does not depend on it. */
+/* The variant hydro_step will use for a batch of n_sub subgrids: the tuned one
+ * for that power-of-two bucket, else the default -- split-8, -4 or -2 when
+ * n_sub times the parts still fits one work item per CU (at most 32, 64 or
+ * 128 subgrids on 256 CUs), persistent-2x otherwise.  max_species is
+ * reserved: the choice does not depend on it. */
 int hydro_selected_variant(int n_sub, int max_species);
 
 /* ---------------------------------------------------------------------------
  * Captured plans: a fused step recorded once into a hipGraph and replayed.
  * The plan keeps the device pointers and the batch metadata pointers given at
  * creation (not the contents they point to: metadata and field data may be
- * rewritten between replays).  dt can be changed per replay.
+ * rewritten between replays).  dt can be changed per replay.  The launch
+ * shape is the one hydro_selected_variant gives at creation; a split or
+ * dynamic shape gets scratch of its own (allocated here, freed by
+ * hydro_plan_destroy), so replays of one plan must not overlap each other.
  */
 typedef struct hydro_plan hydro_plan;
 
@@ -386,7 +418,8 @@ int hydro_rk_stage(const hydro_params *params, const hydro_batch *batch, const d
  * [3] = {t, dt, n} as for hydro_cfl_dt (set t and n before the first step).  Steps past t_end have
  * dt = 0 and leave U unchanged.  The plan keeps every pointer (including
  * batch and map arrays) until destroyed; their contents may change between
- * replays.
+ * replays.  A split or dynamic launch shape gets scratch of its own
+ * (allocated before the capture, freed by hydro_rk3_destroy).
  */
 typedef struct hydro_rk3 hydro_rk3;
 

@@ -5,9 +5,11 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <unordered_map>
+#include <utility>
 
 #include "hydro_internal.hpp"
 
@@ -107,6 +109,73 @@ void tune_save_locked() {
     std::rename(tmp.c_str(), fn);
 }
 
+// ---- scratch of the split and dynamic launch shapes -----------------------
+//
+// The library keeps one scratch buffer per (device, stream) for the eager
+// calls, grown on demand and zero-filled when allocated (the kernel leaves it
+// zero after every launch).  Plans and RK3 graphs own their own.  The first
+// call that needs scratch on a stream allocates it, so that call must not be
+// made while the stream is being captured.
+
+struct Scratch {
+    uint32_t *ptr = nullptr;
+    int64_t bytes = 0;
+};
+
+std::mutex g_ws_mu;
+std::map<std::pair<int, void *>, Scratch> g_ws;
+
+int alloc_scratch(int64_t bytes, uint32_t **out) {
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, (size_t)bytes);
+    if (e == hipSuccess) e = hipMemset(p, 0, (size_t)bytes);
+    if (e != hipSuccess) {
+        if (p) hipFree(p);
+        return fail_hip(e);
+    }
+    *out = static_cast<uint32_t *>(p);
+    return HYDRO_OK;
+}
+
+// Scratch for `n_sub` subgrids on the current device and `stream`.
+int stream_scratch(void *stream, int n_sub, uint32_t **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e);
+    const int64_t need = fused_scratch_bytes(n_sub);
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Scratch &w = g_ws[std::make_pair(dev, stream)];
+    if (w.bytes < need) {
+        if (w.ptr) {
+            // the old buffer may still be in use by launches on the stream
+            e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+            if (e != hipSuccess) return fail_hip(e);
+            hipFree(w.ptr);
+            w.ptr = nullptr;
+            w.bytes = 0;
+        }
+        int64_t bytes = need < 4096 ? 4096 : need;
+        int rc = alloc_scratch(bytes, &w.ptr);
+        if (rc) return rc;
+        w.bytes = bytes;
+    }
+    *out = w.ptr;
+    return HYDRO_OK;
+}
+
+// Launch the fused step in `variant`, attaching the stream's scratch when
+// that launch shape needs it.
+int launch_step(StepArgs a, const double *U_in, double *U_out, double *amax, int32_t *status,
+                int variant, void *stream) {
+    if (fused_variant_needs_scratch(variant) && !a.scratch) {
+        int rc = stream_scratch(stream, a.n_sub, &a.scratch);
+        if (rc) return rc;
+    }
+    hipError_t e = launch_fused_step(a, U_in, U_out, amax, status, variant,
+                                     static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? HYDRO_OK : fail_hip(e);
+}
+
 }  // namespace
 
 struct hydro_plan {
@@ -122,18 +191,28 @@ struct hydro_plan {
     hipGraphNode_t node;
     hipGraphExec_t exec;
     hipKernelNodeParams np;
+    uint32_t *scratch;   // owned (split and dynamic launch shapes)
 };
 
 struct hydro_rk3 {
     hipGraph_t graph;
     hipGraphExec_t exec;
+    uint32_t *scratch;   // owned (split and dynamic launch shapes)
 };
 
 extern "C" {
 
 int64_t hydro_q_elems(int n_species) { return (int64_t)26 * (6 + n_species) * QCELL; }
 int64_t hydro_f_elems(int n_species) { return (int64_t)3 * (6 + n_species) * NFACE; }
-int64_t hydro_workspace_bytes(void) { return 0; }
+int64_t hydro_workspace_bytes(void) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    int64_t total = 0;
+    for (auto &kv : g_ws)
+        if (kv.first.first == dev) total += kv.second.bytes;
+    return total;
+}
 int hydro_subgrid_n(void) { return NSUB; }
 
 const char *hydro_strerror(int code) {
@@ -198,19 +277,18 @@ int hydro_step_variant(const hydro_params *params, const hydro_batch *batch, con
     if (!U_in || !U_out || !amax || U_in == U_out || !aligned8(U_in) || !aligned8(U_out))
         return HYDRO_EINVAL;
     if ((rc = check_device())) return rc;
-    hipError_t e = launch_fused_step(make_args(params, batch), U_in, U_out, amax, status, variant,
-                                     static_cast<hipStream_t>(stream));
-    return e == hipSuccess ? HYDRO_OK : fail_hip(e);
+    return launch_step(make_args(params, batch), U_in, U_out, amax, status, variant, stream);
 }
 
 int hydro_selected_variant(int n_sub, int max_species) {
     (void)max_species;
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    tune_load_locked();
-    auto it = g_tuned.find(bucket_of(n_sub));
-    // untuned: two workgroups per CU (the second wave of workgroups evens out
-    // the tail of a persistent launch)
-    return it == g_tuned.end() ? 1 : it->second;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        auto it = g_tuned.find(bucket_of(n_sub));
+        if (it != g_tuned.end()) return it->second;
+    }
+    return fused_default_variant(n_sub);
 }
 
 int hydro_step(const hydro_params *params, const hydro_batch *batch, const double *U_in,
@@ -231,10 +309,8 @@ int hydro_step_io(const hydro_params *params, const hydro_batch *batch,
     if ((rc = check_device())) return rc;
     StepArgs a = make_args(params, batch);
     a.out_offset = out_offset;
-    hipError_t e = launch_fused_step(a, U_in, U_out, amax, status,
-                                     hydro_selected_variant(batch->n_sub, 5),
-                                     static_cast<hipStream_t>(stream));
-    return e == hipSuccess ? HYDRO_OK : fail_hip(e);
+    return launch_step(a, U_in, U_out, amax, status, hydro_selected_variant(batch->n_sub, 5),
+                       stream);
 }
 
 int hydro_step_gather(const hydro_params *params, const hydro_batch *batch,
@@ -250,10 +326,8 @@ int hydro_step_gather(const hydro_params *params, const hydro_batch *batch,
     StepArgs a = make_args(params, batch);
     a.gsrc = map->src;
     a.gmode = map->mode;
-    hipError_t e = launch_fused_step(a, U_in, U_out, amax, status,
-                                     hydro_selected_variant(batch->n_sub, 5),
-                                     static_cast<hipStream_t>(stream));
-    return e == hipSuccess ? HYDRO_OK : fail_hip(e);
+    return launch_step(a, U_in, U_out, amax, status, hydro_selected_variant(batch->n_sub, 5),
+                       stream);
 }
 
 int hydro_autotune(const hydro_params *params, const hydro_batch *batch, const double *U_in,
@@ -320,6 +394,15 @@ int hydro_plan_create(const hydro_params *params, const hydro_batch *batch, cons
     p->status = status;
     int variant = hydro_selected_variant(batch->n_sub, 5);
     p->order = fused_variant_order(variant);
+    apply_variant(p->args, variant);
+    if (fused_variant_needs_scratch(variant)) {
+        rc = alloc_scratch(fused_scratch_bytes(batch->n_sub), &p->scratch);
+        if (rc) {
+            delete p;
+            return rc;
+        }
+        p->args.scratch = p->scratch;
+    }
     p->fargs = fused_args(p->args);
     p->kargs[0] = &p->fargs;
     p->kargs[1] = &p->U_in;
@@ -332,6 +415,7 @@ int hydro_plan_create(const hydro_params *params, const hydro_batch *batch, cons
     if (e == hipSuccess) e = hipGraphAddKernelNode(&p->node, p->graph, nullptr, 0, &p->np);
     if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
+        if (p->scratch) hipFree(p->scratch);
         delete p;
         return fail_hip(e);
     }
@@ -357,6 +441,7 @@ int hydro_plan_destroy(hydro_plan *plan) {
     if (!plan) return HYDRO_EINVAL;
     hipGraphExecDestroy(plan->exec);
     hipGraphDestroy(plan->graph);
+    if (plan->scratch) hipFree(plan->scratch);
     delete plan;
     return HYDRO_OK;
 }
@@ -385,10 +470,7 @@ int hydro_rate(const hydro_params *params, const hydro_batch *batch, const doubl
     if ((rc = check_device())) return rc;
     StepArgs a = make_args(params, batch);
     a.rate = 1;
-    hipError_t e = launch_fused_step(a, U_in, R, amax, status,
-                                     hydro_selected_variant(batch->n_sub, 5),
-                                     static_cast<hipStream_t>(stream));
-    return e == hipSuccess ? HYDRO_OK : fail_hip(e);
+    return launch_step(a, U_in, R, amax, status, hydro_selected_variant(batch->n_sub, 5), stream);
 }
 
 int hydro_cfl_dt(const hydro_batch *batch, const double *amax, double cfl, double t_end,
@@ -417,10 +499,8 @@ int hydro_rk_stage(const hydro_params *params, const hydro_batch *batch, const d
     sa.U0 = U0;
     sa.c0 = a;
     sa.c1 = b;
-    hipError_t e = launch_fused_step(sa, U_in, U_out, amax, status,
-                                     hydro_selected_variant(batch->n_sub, 5),
-                                     static_cast<hipStream_t>(stream));
-    return e == hipSuccess ? HYDRO_OK : fail_hip(e);
+    return launch_step(sa, U_in, U_out, amax, status, hydro_selected_variant(batch->n_sub, 5),
+                       stream);
 }
 
 int hydro_tau_resync(const hydro_params *params, const hydro_batch *batch, double *U,
@@ -499,13 +579,24 @@ int hydro_rk3_create(const hydro_params *params, const hydro_batch *batch,
     ra.gsrc = map->src;
     ra.gmode = map->mode;
     const int variant = hydro_selected_variant(batch->n_sub, 5);
+    hydro_rk3 *p = new (std::nothrow) hydro_rk3();
+    if (!p) return HYDRO_EINVAL;
+    if (fused_variant_needs_scratch(variant)) {
+        // allocated before the capture (no allocation may be captured); the
+        // stages run one after another, so they share it
+        rc = alloc_scratch(fused_scratch_bytes(batch->n_sub), &p->scratch);
+        if (rc) {
+            delete p;
+            return rc;
+        }
+        ra.scratch = p->scratch;
+    }
     hipStream_t cs;
     hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-    if (e != hipSuccess) return fail_hip(e);
-    hydro_rk3 *p = new (std::nothrow) hydro_rk3();
-    if (!p) {
-        hipStreamDestroy(cs);
-        return HYDRO_EINVAL;
+    if (e != hipSuccess) {
+        if (p->scratch) hipFree(p->scratch);
+        delete p;
+        return fail_hip(e);
     }
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
@@ -518,6 +609,7 @@ int hydro_rk3_create(const hydro_params *params, const hydro_batch *batch,
     hipStreamDestroy(cs);
     if (e != hipSuccess) {
         if (p->graph) hipGraphDestroy(p->graph);
+        if (p->scratch) hipFree(p->scratch);
         delete p;
         return fail_hip(e);
     }
@@ -538,6 +630,7 @@ int hydro_rk3_destroy(hydro_rk3 *plan) {
     if (!plan) return HYDRO_EINVAL;
     hipGraphExecDestroy(plan->exec);
     hipGraphDestroy(plan->graph);
+    if (plan->scratch) hipFree(plan->scratch);
     delete plan;
     return HYDRO_OK;
 }

@@ -98,6 +98,25 @@ __device__ __host__ constexpr int cons_producer(int ax, int r, int j) {
                    : 1 + j;
 }
 
+// The t-th line (t = 0..8) that crosses the z faces, in the order in which the
+// z-face owner of an interior plane step sums them (rounds 0-4, two lines a
+// round, one in the last).  The face layers sum their points in this order
+// too, so a z face comes out bit for bit the same whether its sides were
+// produced in interior steps or in face layers.
+__device__ __host__ constexpr int zline(int t) {
+    return line_of(cons_producer(2, t / 2, t % 2), t / 2);
+}
+
+__host__ constexpr bool zlines_ok() {
+    for (int t = 0; t < 9; t++) {
+        if (zline(t) < 0 || ldz(zline(t)) != 1) return false;
+        for (int u = 0; u < t; u++)
+            if (zline(u) == zline(t)) return false;
+    }
+    return true;
+}
+static_assert(zlines_ok(), "the nine z-crossing lines, each once");
+
 // Simpson weight of a surface point from its two tangential offsets.
 __device__ __forceinline__ double simpson_w(int t1, int t2) {
     const double w1a = t1 == 0 ? 4.0 / 6.0 : 1.0 / 6.0;
@@ -403,7 +422,8 @@ __device__ __forceinline__ void ppm_line(const double *win, const Line5 &l, int 
 
 // Hydro fields along one line: reconstructed values and the point states at
 // both ends, written to the exchange slots as they are formed (component
-// stride 64) when `store`; with `both` false only the + point is formed.
+// stride 64) when `store`; with `both` false only the + point is formed, and
+// with `minus_only` only the - point (stored at pm).
 // With VEL the window holds the velocities s / rho in the momentum slots:
 // their PPM values are the point velocities, and the point momenta are those
 // times the point density.
@@ -412,11 +432,12 @@ struct PlusState {
     double vx, vy, p, cs;
 };
 
-template <bool store, bool both, bool VEL, bool CW>
+template <bool store_, bool both_, bool VEL, bool CW, bool minus_only = false>
 __device__ __forceinline__ PlusState produce_hydro(const double *win, const Line5 &l,
                                                    double *pp, double *pm, double gamma,
                                                    double gm1, double de, int &bits,
                                                    const CwW &cw) {
+    constexpr bool plus = !minus_only, store = store_ && plus, both = both_ || minus_only;
     PlusState ps;
     double qp, qm;
     ppm_line<CW>(win, l, 0, cw, qp, qm);
@@ -424,7 +445,7 @@ __device__ __forceinline__ PlusState produce_hydro(const double *win, const Line
     if (store) pp[0] = qp;
     if (both) pm[0] = qm;
     const double rhop = qp, rhom = qm;
-    const double rp = recip(qp), rm = both ? recip(qm) : 1.0;
+    const double rp = plus ? recip(qp) : 1.0, rm = both ? recip(qm) : 1.0;
     ppm_line<CW>(win, l, 1, cw, qp, qm);
     const double wxp = qp, wxm = qm;
     if (VEL) {
@@ -469,18 +490,22 @@ __device__ __forceinline__ PlusState produce_hydro(const double *win, const Line
     ps.q[5] = qp;
     if (store) pp[5 * 64] = qp;
     if (both) pm[5 * 64] = qm;
-    double eip = fma(-0.5, ekp, Ep);
-    if (eip < de * Ep) eip = tau_pow(qp, gamma);      // dual energy: tau^gamma
-    const double prp = gm1 * eip;
-    const double csp = sqrt((gamma * prp) * rp);
-    if (store) {
-        pp[P_VX * 64] = vxp;
-        pp[(P_VX + 1) * 64] = vyp;
-        pp[(P_VX + 2) * 64] = vzp;
-        pp[P_P * 64] = prp;
-        pp[P_CS * 64] = csp;
+    double prp = 0.0, csp = 0.0;
+    if (plus) {
+        double eip = fma(-0.5, ekp, Ep);
+        if (eip < de * Ep) eip = tau_pow(qp, gamma);      // dual energy: tau^gamma
+        prp = gm1 * eip;
+        csp = sqrt((gamma * prp) * rp);
+        if (store) {
+            pp[P_VX * 64] = vxp;
+            pp[(P_VX + 1) * 64] = vyp;
+            pp[(P_VX + 2) * 64] = vzp;
+            pp[P_P * 64] = prp;
+            pp[P_CS * 64] = csp;
+        }
+        bits |= (__ballot(rhop <= 0.0) ? HYDRO_STATUS_RHO : 0) |
+                (__ballot(prp <= 0.0) ? HYDRO_STATUS_P : 0);
     }
-    bits |= (__ballot(rhop <= 0.0) ? HYDRO_STATUS_RHO : 0) | (__ballot(prp <= 0.0) ? HYDRO_STATUS_P : 0);
     if (both) {
         double eim = fma(-0.5, ekm, Em);
         if (eim < de * Em) eim = tau_pow(qm, gamma);
@@ -674,7 +699,8 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                                              double lam, bool rate, const Stage &stg, bool sym,
                                              int cwmode, double gamma, double gm1, double de,
                                              double &amax_l, int &bits, const FusedArgs &a, int s,
-                                             const double *Ug, int64_t *toff, int *tmode) {
+                                             const double *Ug, int64_t *toff, int *tmode, int kb,
+                                             int ke) {
     const int nf = 6 + nspec;
     double chk = 0.0;
     const int f0 = HYD ? 0 : 6, f1 = HYD ? 6 : nf;     // this wave's fields
@@ -754,39 +780,41 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
         }
         lds_barrier();
     }
-    // window: planes 0..4, then prefetch plane 5
+    // window: planes kb-2..kb+2, then prefetch plane kb+3
     {
         double v[SLOTS][5];
 #pragma unroll
         for (int pl = 0; pl < SLOTS; pl++)
 #pragma unroll
-            for (int q = 0; q < 5; q++) v[pl][q] = *src(q, pl);
+            for (int q = 0; q < 5; q++) v[pl][q] = *src(q, kb - 2 + pl);
         if (VEL) {
 #pragma unroll
             for (int pl = 0; pl < SLOTS; pl++)
 #pragma unroll
                 for (int q = 0; q < 2; q++) {
-                    const double rho = *src_rho(q, pl);
+                    const double rho = *src_rho(q, kb - 2 + pl);
                     if (mom[q]) v[pl][q] = v[pl][q] / rho;
                 }
         }
 #pragma unroll
-        for (int pl = 0; pl < SLOTS; pl++)
+        for (int pl = 0; pl < SLOTS; pl++) {
+            double *dst = win + ((kb - 2 + pl) % SLOTS) * SLOT_D;
 #pragma unroll
-            for (int q = 0; q < 5; q++) win[pl * SLOT_D + l_off[q]] = v[pl][q];
+            for (int q = 0; q < 5; q++) dst[l_off[q]] = v[pl][q];
+        }
     }
     double pf[5], pr[2];
 #pragma unroll
-    for (int q = 0; q < 5; q++) pf[q] = *src(q, 5);
+    for (int q = 0; q < 5; q++) pf[q] = *src(q, kb + 3);
     if (VEL) {
 #pragma unroll
-        for (int q = 0; q < 2; q++) pr[q] = *src_rho(q, 5);
+        for (int q = 0; q < 2; q++) pr[q] = *src_rho(q, kb + 3);
     }
     lds_barrier();
 
     double acc[2][NH];       // [0]: face + (or the ring / layer face), [1]: face -
     double Fb[NF_MAX];
-    for (int k = 2; k <= 11; k++) {
+    for (int k = kb; k <= ke; k++) {
         const double *Us = Us0;
         double *Os = Os0;
         const int fst = opaque_s(fst0);
@@ -794,36 +822,45 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
         acc_zero(acc[0], HYD);
         acc_zero(acc[1], HYD);
 
-        // ---- rounds of line production and consumption.  Face layers k = 2
-        // and 11: 3 rounds, every role produces one of the 9 points of the
-        // boundary z-face of the interior cells of the plane and role 2
-        // consumes them.  Interior planes: 5 rounds; roles 0-2 produce their
+        // ---- rounds of line production and consumption.  Face layers (the
+        // planes kb and ke just below and above the part's interior planes):
+        // 3 rounds, every role produces one of the 9 points of the z face the
+        // plane shares with the part (its + side at kb, its - side at ke) and
+        // role 2 consumes them.  Interior planes: 5 rounds; roles 0-2 produce their
         // lines for the interior cells and consume the two lines of the round
         // that cross their faces, role 3 works on the ring cells.  Each kind
         // of wave runs its own loop (same barrier count), so the
         // accumulators never pass through a control-flow merge.
-        const bool layer = (k == 2 || k == 11);
+        const bool layer = (k == kb || k == ke);
         if (layer) {
+            const bool bottom = k == kb;
 #pragma unroll 1
             for (int r = 0; r < 3; r++) {
                 LANE_GEOMETRY();
                 const int t = role + 4 * r;
                 double *pp = xch + role * PT * 64 + lane;
                 if (t < 9) {
-                    const int ldxv = t % 3 - 1, ldyv = t / 3 - 1, ldzv = k == 2 ? 1 : -1;
-                    const Line5 l = line5(ci, cj, k, ldxv, ldyv, ldzv);
+                    // the t-th z line through the cell: its + end lies on the
+                    // cell's top face, its - end on the bottom face
+                    const int L = zline(t);
+                    const Line5 l = line5(ci, cj, k, ldx(L), ldy(L), ldz(L));
                     CwW cw = {0.0, 0.0};
                     if (CW && (HYD || nspec > 0))
-                        cw = cw_weights<VEL>(win, l, ldxv, ldyv, ldzv, gamma, gm1, de, cwmode, HYD);
+                        cw = cw_weights<VEL>(win, l, ldx(L), ldy(L), ldz(L), gamma, gm1, de, cwmode,
+                                             HYD);
                     if (HYD) {
-                        produce_hydro<true, false, VEL, CW>(win, l, pp, pp, gamma, gm1, de, bits,
-                                                            cw);
+                        if (bottom)
+                            produce_hydro<true, false, VEL, CW>(win, l, pp, pp, gamma, gm1, de,
+                                                                bits, cw);
+                        else
+                            produce_hydro<false, false, VEL, CW, true>(win, l, pp, pp, gamma, gm1,
+                                                                       de, bits, cw);
                     } else if (nspec > 0) {
 #pragma unroll
                         for (int f = 6; f < NF_MAX; f++) {
                             double qp, qm;
                             ppm_line<CW>(win, l, f, cw, qp, qm);
-                            pp[f * 64] = qp;
+                            pp[f * 64] = bottom ? qp : qm;
                         }
                     }
                 }
@@ -833,7 +870,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                     for (int w = 0; w < 4; w++) {
                         const int t2 = w + 4 * r;
                         if (t2 < 9) {
-                            const double wt = simpson_w(t2 % 3 - 1, t2 / 3 - 1);
+                            const double wt = simpson_w(ldx(zline(t2)), ldy(zline(t2)));
                             const double *pt = xch + w * PT * 64 + lane;
                             if (HYD) acc_h_lds(acc[0], pt, 2, wt);
                             else acc_s_lds(acc[0], pt, 2, wt);
@@ -954,7 +991,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
         // of plane k+4 start, behind this step's stores.  On interior planes
         // the barriers of the flux phases below order these stores before the
         // next step's reads; after the first face layer a barrier does.
-        if (k + 3 <= 13) {
+        if (k + 3 <= ke + 2) {
             double *dst = win + ((k + 3) % SLOTS) * SLOT_D;
             if (VEL) {
 #pragma unroll
@@ -963,7 +1000,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
             }
 #pragma unroll
             for (int q = 0; q < 5; q++) dst[l_off[q]] = pf[q];
-            if (k + 4 <= 13) {
+            if (k + 4 <= ke + 2) {
 #pragma unroll
                 for (int q = 0; q < 5; q++) pf[q] = *src(q, k + 4);
                 if (VEL) {
@@ -976,14 +1013,14 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
 
         if (layer) {
             LANE_GEOMETRY();
-            if (k == 2) {
+            if (k == kb) {
                 if (role == 2) {
                     if (HYD) store_h(zl + lane, 64, acc[0]);
                     else store_s(zl + lane, 64, acc[0], nspec);
                 }
             } else {
-                // face (10|11): left partial from step 10, right = acc[0]; the species
-                // wave gets the right-side speeds through LDS
+                // face (ke-1|ke): left partial from step ke-1, right = acc[0]; the
+                // species wave gets the right-side speeds through LDS
                 if (role == 2 && HYD) {
                     xch[ZB_OFF + 2 * 64 + lane] = acc[0][H_LP];
                     xch[ZB_OFF + 3 * 64 + lane] = acc[0][H_LM];
@@ -1000,8 +1037,8 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                                                       xch[ZB_OFF + 3 * 64 + lane], sym);
                         combine_s(acc[0], zl + lane, 64, false, sp, nspec, Fz);
                     }
-                    update_cell<VEL>(win, keep, lane, 10, ci, cj, f0, f1, Fz, lam, rate, stg,
-                                     Us, Os, fst, chk);
+                    update_cell<VEL>(win, keep, lane, ke - 1, ci, cj, f0, f1, Fz, lam, rate,
+                                     stg, Us, Os, fst, chk);
                 }
             }
             continue;
@@ -1081,7 +1118,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                                               sym);
                 combine_s(acc[1], zl + lane, 64, false, sp, nspec, Fz);
             }
-            if (k >= 4)
+            if (k >= kb + 2)
                 update_cell<VEL>(win, keep, lane, k - 1, ci, cj, f0, f1, Fz, lam, rate, stg, Us,
                                  Os, fst, chk);
 #pragma unroll
@@ -1120,6 +1157,17 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
 
 // ---- the kernel ---------------------------------------------------------------
 
+// Scratch of the split and dynamic launch shapes (32-bit words): [0] next work
+// item, [1] workgroups done, [16, 16 + 2 n) per-subgrid running max of the
+// parts' face speeds (as 64-bit patterns of non-negative doubles), then n
+// status words and n arrival counts.  Every word is back at zero when the
+// launch ends (the last workgroup or part to finish clears what it used).
+__device__ __forceinline__ unsigned long long *sc_amax(uint32_t *sc) {
+    return reinterpret_cast<unsigned long long *>(sc + 16);
+}
+__device__ __forceinline__ uint32_t *sc_bits(uint32_t *sc, int n) { return sc + 16 + 2 * n; }
+__device__ __forceinline__ uint32_t *sc_count(uint32_t *sc, int n) { return sc + 16 + 3 * n; }
+
 template <bool VEL, bool CW, bool GATHER>
 __global__ __launch_bounds__(NT, 2) void k_fused(FusedArgs a, const double *__restrict__ U,
                                                  double *Uo,
@@ -1127,6 +1175,8 @@ __global__ __launch_bounds__(NT, 2) void k_fused(FusedArgs a, const double *__re
                                                  int32_t *__restrict__ status, int order) {
     __shared__ double lds[LDS_D];
     __shared__ int red_bits[8];
+    __shared__ int next_item[2];     // by parity of the iteration (no barrier between
+                                     // one iteration's read and the next one's write)
     __shared__ int64_t g_toff[GATHER ? 27 : 1];    // ghost-map table of the current subgrid
     __shared__ int g_tmode[GATHER ? 27 : 1];
     double *win = lds;
@@ -1147,77 +1197,130 @@ __global__ __launch_bounds__(NT, 2) void k_fused(FusedArgs a, const double *__re
     const bool rate = a.rate != 0;
     const bool sym = a.sym != 0;
     const int cwmode = (a.steepen ? 1 : 0) | (a.flatten ? 2 : 0);
+    // work items: the parts of the subgrids' z sweeps (P parts of 8 / P
+    // interior planes each, part q of subgrid s is item s P + q), fetched in
+    // a static stride or, in the dynamic form, from a counter in scratch
+    const int lp = a.log_parts, P = 1 << lp, span = NSUB >> lp;
+    const int n_items = a.n_sub << lp;
+    uint32_t *sc = a.scratch;
 
-    for (int it = blockIdx.x; it < a.n_sub; it += gridDim.x) {
-        const int s = order ? (a.n_sub - 1 - it) : it;
+    int parity = 0;
+    for (int it = blockIdx.x; it < n_items; parity ^= 1) {
+        const int s0 = it >> lp, q = it & (P - 1);
+        const int s = order ? (a.n_sub - 1 - s0) : s0;
+        const int kb = NG - 1 + q * span, ke = kb + span + 1;
         const int nspec = a.n_species[s];
         const int64_t off = a.offset[s];
         const int64_t ooff = a.out_offset ? a.out_offset[s] : off;
-        if (nspec < 0 || nspec > 5 || off < 0 || (off & 1) || ooff < 0 || (ooff & 1)) {
-            if (tid == 0) {
-                amax[s] = 0.0;
-                if (status) status[s] = (rate || a.U0 ? status[s] : 0) | HYDRO_STATUS_BADMETA;
-            }
-            continue;
-        }
-        const double dtv = a.clock ? a.clock[1] : a.dt;
-        const double lam = rate ? 1.0 / a.h[s] : dtv / a.h[s];
-        Stage stg;
-        stg.U0 = a.U0 ? a.U0 + off : nullptr;
-        stg.c0 = a.c0;
-        stg.c1 = a.c1;
-        stg.identity = dtv == 0.0;
-        const double *Us0 = U + off;
-        double *Os0 = Uo + ooff;
-        const int fst0 = a.fstride;
+        const bool bad = nspec < 0 || nspec > 5 || off < 0 || (off & 1) || ooff < 0 || (ooff & 1);
         double amax_l = 0.0;
         int bits = 0;
+        if (!bad) {
+            const double dtv = a.clock ? a.clock[1] : a.dt;
+            const double lam = rate ? 1.0 / a.h[s] : dtv / a.h[s];
+            Stage stg;
+            stg.U0 = a.U0 ? a.U0 + off : nullptr;
+            stg.c0 = a.c0;
+            stg.c1 = a.c1;
+            stg.identity = dtv == 0.0;
+            const double *Us0 = U + off;
+            double *Os0 = Uo + ooff;
+            const int fst0 = a.fstride;
+            if (hyd)
+                subgrid_body<true, VEL, CW, GATHER>(win, xch, zl, keep, run, tid, role, nspec, Us0,
+                                                    Os0, fst0, lam, rate, stg, sym, cwmode, gamma,
+                                                    gm1, de, amax_l, bits, a, s, U, g_toff,
+                                                    g_tmode, kb, ke);
+            else
+                subgrid_body<false, VEL, CW, GATHER>(win, xch, zl, keep, run, tid, role, nspec,
+                                                     Us0, Os0, fst0, lam, rate, stg, sym, cwmode,
+                                                     gamma, gm1, de, amax_l, bits, a, s, U, g_toff,
+                                                     g_tmode, kb, ke);
 
-        if (hyd)
-            subgrid_body<true, VEL, CW, GATHER>(win, xch, zl, keep, run, tid, role, nspec, Us0, Os0,
-                                                fst0, lam, rate, stg, sym, cwmode, gamma, gm1, de,
-                                                amax_l, bits, a, s, U, g_toff, g_tmode);
-        else
-            subgrid_body<false, VEL, CW, GATHER>(win, xch, zl, keep, run, tid, role, nspec, Us0,
-                                                 Os0, fst0, lam, rate, stg, sym, cwmode, gamma, gm1,
-                                                 de, amax_l, bits, a, s, U, g_toff, g_tmode);
-
-        // ---- per-subgrid speed and status
-        for (int o = 32; o > 0; o >>= 1) {
-            amax_l = fmax(amax_l, __shfl_xor(amax_l, o));
-            bits |= __shfl_xor(bits, o);
+            // ---- the part's speed and status
+            for (int o = 32; o > 0; o >>= 1) {
+                amax_l = fmax(amax_l, __shfl_xor(amax_l, o));
+                bits |= __shfl_xor(bits, o);
+            }
+            if ((tid & 63) == 0) {
+                red[wave] = amax_l;
+                red_bits[wave] = bits;
+            }
         }
-        if ((tid & 63) == 0) {
-            red[wave] = amax_l;
-            red_bits[wave] = bits;
-        }
+        if (a.dyn && tid == 0)
+            next_item[parity] = (int)gridDim.x + (int)atomicAdd(&sc[0], 1u);
         lds_barrier();
         if (tid == 0) {
             double m = 0.0;
-            int b = 0;
-            for (int w = 0; w < 8; w++) {
-                m = fmax(m, red[w]);
-                b |= red_bits[w];
+            int b = HYDRO_STATUS_BADMETA;
+            if (!bad) {
+                b = 0;
+                for (int w = 0; w < 8; w++) {
+                    m = fmax(m, red[w]);
+                    b |= red_bits[w];
+                }
             }
-            if (!isfinite(m)) b |= HYDRO_STATUS_NONFINITE;
-            amax[s] = m;
-            if (status) status[s] = (rate || a.U0) ? (status[s] | b) : b;
+            bool last = true;
+            if (P > 1) {
+                // the last part of the subgrid to arrive writes its result
+                atomicMax(&sc_amax(sc)[s], (unsigned long long)__double_as_longlong(m));
+                atomicOr(&sc_bits(sc, a.n_sub)[s], (uint32_t)b);
+                __threadfence();
+                last = atomicAdd(&sc_count(sc, a.n_sub)[s], 1u) == (uint32_t)(P - 1);
+                if (last) {
+                    __threadfence();
+                    m = __longlong_as_double(
+                        (long long)atomicExch(&sc_amax(sc)[s], 0ull));
+                    b = (int)atomicExch(&sc_bits(sc, a.n_sub)[s], 0u);
+                    atomicExch(&sc_count(sc, a.n_sub)[s], 0u);
+                }
+            }
+            if (last) {
+                if (!isfinite(m)) b |= HYDRO_STATUS_NONFINITE;
+                amax[s] = m;
+                if (status) status[s] = (rate || a.U0) ? (status[s] | b) : b;
+            }
+        }
+        it = a.dyn ? next_item[parity] : it + (int)gridDim.x;
+    }
+    if (a.dyn) {
+        // the last workgroup out clears the counters for the next launch
+        if (tid == 0) {
+            __threadfence();
+            if (atomicAdd(&sc[1], 1u) == gridDim.x - 1) {
+                atomicExch(&sc[0], 0u);
+                atomicExch(&sc[1], 0u);
+            }
         }
     }
 }
 
 struct Variant {
     const char *name;
-    int grid_per_cu;   // persistent workgroups per CU; 0 = one workgroup per subgrid
+    int grid_per_cu;   // persistent workgroups per CU; 0 = one workgroup per work item
     int order;         // 0: subgrid order, 1: reverse order
+    int log_parts;     // each subgrid's z sweep in 2^log_parts parts (work items)
+    int dyn;           // work items fetched from a counter instead of a static stride
 };
 
+// The launch shapes the autotuner chooses from.  A part of a subgrid sweeps
+// 8 / P interior planes plus the face layer below and above them, so P parts
+// cost more in all than one sweep, but spread a batch of fewer subgrids than
+// CUs over more of the chip.
 constexpr Variant kVariants[] = {
-    {"persistent-1x", 1, 0},
-    {"persistent-2x", 2, 0},
-    {"one-per-subgrid", 0, 0},
-    {"persistent-1x-rev", 1, 1},
+    {"persistent-1x", 1, 0, 0, 0},
+    {"persistent-2x", 2, 0, 0, 0},
+    {"one-per-subgrid", 0, 0, 0, 0},
+    {"persistent-1x-rev", 1, 1, 0, 0},
+    {"persistent-1x-dynamic", 1, 0, 0, 1},
+    {"split-2", 0, 0, 1, 0},
+    {"split-4", 0, 0, 2, 0},
+    {"split-8", 0, 0, 3, 0},
 };
+constexpr int kVariantSplit2 = 5;
+static_assert(kVariants[kVariantSplit2].log_parts == 1 &&
+                  kVariants[kVariantSplit2 + 2].log_parts == 3,
+              "split variants in order");
 
 int device_cus() {
     static int cus = 0;
@@ -1248,8 +1351,9 @@ FusedKernel fused_kernel(const StepArgs &a) {
 
 dim3 grid_of(const StepArgs &a, int v) {
     const Variant &V = kVariants[v];
-    int g = V.grid_per_cu ? V.grid_per_cu * device_cus() : a.n_sub;
-    if (g > a.n_sub) g = a.n_sub;
+    const int items = a.n_sub << V.log_parts;
+    int g = V.grid_per_cu ? V.grid_per_cu * device_cus() : items;
+    if (g > items) g = items;
     return dim3(g < 1 ? 1 : g);
 }
 
@@ -1262,10 +1366,32 @@ const char *fused_variant_name(int v) {
 int fused_variant_order(int v) {
     return (v >= 0 && v < fused_variant_count()) ? kVariants[v].order : 0;
 }
+bool fused_variant_needs_scratch(int v) {
+    return v >= 0 && v < fused_variant_count() && (kVariants[v].log_parts > 0 || kVariants[v].dyn);
+}
+int64_t fused_scratch_bytes(int n_sub) { return 64 + 16 * (int64_t)(n_sub > 0 ? n_sub : 0); }
 
-hipError_t launch_fused_step(const StepArgs &a, const double *U_in, double *U_out,
+int fused_default_variant(int n_sub) {
+    // fewer subgrids than CUs: as many parts per subgrid as keep one work
+    // item per CU; otherwise two persistent workgroups per CU (the second
+    // wave of workgroups evens out the tail)
+    const int cus = device_cus();
+    for (int lp = 3; lp >= 1; lp--)
+        if ((int64_t)n_sub << lp <= cus) return kVariantSplit2 + lp - 1;
+    return 1;
+}
+
+void apply_variant(StepArgs &a, int v) {
+    a.log_parts = kVariants[v].log_parts;
+    a.dyn = kVariants[v].dyn;
+}
+
+hipError_t launch_fused_step(const StepArgs &a0, const double *U_in, double *U_out,
                              double *amax, int32_t *status, int variant, hipStream_t st) {
-    if (a.n_sub == 0) return hipSuccess;
+    if (a0.n_sub == 0) return hipSuccess;
+    StepArgs a = a0;
+    apply_variant(a, variant);
+    if ((a.log_parts || a.dyn) && !a.scratch) return hipErrorInvalidValue;
     hipLaunchKernelGGL(fused_kernel(a), grid_of(a, variant), dim3(NT), 0, st, fused_args(a), U_in,
                        U_out, amax, status, kVariants[variant].order);
     return hipGetLastError();

@@ -63,6 +63,12 @@ struct StepArgs {
     // hydro_ghost_map): when set, the fused step reads ghost cells from the
     // neighbours' interiors instead of the block's own ghost layers
     const int32_t *gsrc, *gmode;
+    // launch shape of the fused step: each subgrid's z sweep in 2^log_parts
+    // parts (workgroups), items fetched from a counter when dyn; both need
+    // scratch (fused_scratch_bytes), all zero between launches
+    int32_t log_parts;
+    int32_t dyn;
+    uint32_t *scratch;
 };
 
 // The fused kernel's copy of the same parameters, with the option flags as
@@ -87,6 +93,9 @@ struct FusedArgs {
     double c0, c1;
     const int64_t *out_offset;
     const int32_t *gsrc, *gmode;
+    int32_t log_parts;
+    uint32_t dyn : 1;
+    uint32_t *scratch;
 };
 
 inline FusedArgs fused_args(const StepArgs &a) {
@@ -111,6 +120,9 @@ inline FusedArgs fused_args(const StepArgs &a) {
     f.out_offset = a.out_offset;
     f.gsrc = a.gsrc;
     f.gmode = a.gmode;
+    f.log_parts = a.log_parts;
+    f.dyn = a.dyn ? 1 : 0;
+    f.scratch = a.scratch;
     return f;
 }
 
@@ -136,6 +148,9 @@ inline StepArgs make_args(const hydro_params *p, const hydro_batch *b) {
     a.out_offset = nullptr;
     a.gsrc = nullptr;
     a.gmode = nullptr;
+    a.log_parts = 0;
+    a.dyn = 0;
+    a.scratch = nullptr;
     return a;
 }
 
@@ -151,6 +166,14 @@ hipError_t launch_plain_divergence(const StepArgs &a, const double *F, const int
 // Fused step: variant index selects the launch shape.
 int fused_variant_count();
 const char *fused_variant_name(int v);
+// whether variant v needs scratch, and how many bytes it needs for n_sub
+// subgrids (zero-filled before first use; the kernel leaves it zero)
+bool fused_variant_needs_scratch(int v);
+int64_t fused_scratch_bytes(int n_sub);
+// the launch shape for n_sub subgrids when no tuned choice exists
+int fused_default_variant(int n_sub);
+// the variant's launch-shape fields of a (log_parts, dyn)
+void apply_variant(StepArgs &a, int v);
 hipError_t launch_fused_step(const StepArgs &a, const double *U_in, double *U_out,
                              double *amax, int32_t *status, int variant, hipStream_t st);
 // Device-resident time integration (evolve.hip).
