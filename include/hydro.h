@@ -65,7 +65,8 @@ enum {
     HYDRO_OK = 0,
     HYDRO_EINVAL = -1,   /* null pointer, fstride < 2744, n_sub < 0, misalignment */
     HYDRO_ELAUNCH = -2,  /* a HIP runtime call or kernel launch failed             */
-    HYDRO_ENODEV = -3    /* no gfx950 device is current                            */
+    HYDRO_ENODEV = -3,   /* no gfx950 device is current                            */
+    HYDRO_ESCRATCH = -4  /* batch larger than hydro_step_noalloc's fixed scratch     */
 };
 
 enum { HYDRO_STATUS_RHO = 1, HYDRO_STATUS_P = 2, HYDRO_STATUS_NONFINITE = 4,
@@ -191,6 +192,24 @@ int hydro_divergence(const hydro_params *params, const hydro_batch *batch,
 int hydro_step(const hydro_params *params, const hydro_batch *batch,
                const double *U_in, double *U_out, double *amax,
                int32_t *status, void *stream);
+
+/*
+ * hydro_step_noalloc -- hydro_step for callers that cannot allocate device
+ * memory (code under hipGraph stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, launch shape and results (bit for
+ * bit) as hydro_step, but it never allocates: the scratch of the split and
+ * dynamic launch shapes is a fixed array in the library's device code, one
+ * per GPU, sized for HYDRO_NOALLOC_MAX_SUB subgrids (about 1 MiB) and held
+ * until the process ends.  A batch of more subgrids returns HYDRO_ESCRATCH.
+ * Every call on one GPU shares that GPU's array: the call clears the part it
+ * uses with a kernel on `stream` first, and calls whose launches overlap on
+ * one GPU (on different streams, or in different plans replayed at once)
+ * race on it -- serialise them.
+ */
+#define HYDRO_NOALLOC_MAX_SUB 65536
+int hydro_step_noalloc(const hydro_params *params, const hydro_batch *batch,
+                       const double *U_in, double *U_out, double *amax,
+                       int32_t *status, void *stream);
 
 /*
  * hydro_step_io -- hydro_step with a separate output offset per subgrid:

@@ -163,6 +163,44 @@ int stream_scratch(void *stream, int n_sub, uint32_t **out) {
     return HYDRO_OK;
 }
 
+// ---- scratch of hydro_step_noalloc ------------------------------------------
+//
+// A file-scope device array, one copy per GPU, held until the process ends:
+// the split and dynamic launch shapes' scratch for up to
+// HYDRO_NOALLOC_MAX_SUB subgrids.  Host code never passes `scratch` itself
+// to a kernel (on the host it only names the symbol): its device address is
+// looked up once per device and kept in g_noalloc.
+
+constexpr int64_t kNoallocBytes = 64 + 16 * (int64_t)HYDRO_NOALLOC_MAX_SUB;
+static __device__ __align__(256) uint32_t scratch[kNoallocBytes / 4];
+
+std::mutex g_noalloc_mu;
+std::unordered_map<int, uint32_t *> g_noalloc;
+
+// Device address of this device's `scratch` (looked up on its first use).
+int noalloc_scratch(uint32_t **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e);
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    auto it = g_noalloc.find(dev);
+    if (it == g_noalloc.end()) {
+        uint32_t *ptr = nullptr;
+        e = hipGetSymbolAddress(reinterpret_cast<void **>(&ptr), HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return fail_hip(e != hipSuccess ? e : hipErrorInvalidSymbol);
+        it = g_noalloc.emplace(dev, ptr).first;
+    }
+    *out = it->second;
+    return HYDRO_OK;
+}
+
+// Zero n words (a kernel, not a memset node, so that a caller may capture it).
+__global__ void k_clear_words(uint32_t *p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
 // Launch the fused step in `variant`, attaching the stream's scratch when
 // that launch shape needs it.
 int launch_step(StepArgs a, const double *U_in, double *U_out, double *amax, int32_t *status,
@@ -220,6 +258,8 @@ const char *hydro_strerror(int code) {
     case HYDRO_OK: return "ok";
     case HYDRO_EINVAL: return "invalid argument";
     case HYDRO_ENODEV: return "the current device is not a gfx950 GPU";
+    case HYDRO_ESCRATCH:
+        return "batch larger than hydro_step_noalloc's scratch (HYDRO_NOALLOC_MAX_SUB subgrids)";
     case HYDRO_ELAUNCH:
         std::snprintf(g_err, sizeof g_err, "HIP error: %s", hipGetErrorString(g_last_hip));
         return g_err;
@@ -296,6 +336,32 @@ int hydro_step(const hydro_params *params, const hydro_batch *batch, const doubl
     if (!batch) return HYDRO_EINVAL;
     return hydro_step_variant(params, batch, U_in, U_out, amax, status,
                               hydro_selected_variant(batch->n_sub, 5), stream);
+}
+
+int hydro_step_noalloc(const hydro_params *params, const hydro_batch *batch,
+                       const double *U_in, double *U_out, double *amax, int32_t *status,
+                       void *stream) {
+    int rc = check_fused(params, batch);
+    if (rc) return rc;
+    if (batch->n_sub > HYDRO_NOALLOC_MAX_SUB) return HYDRO_ESCRATCH;
+    if (batch->n_sub == 0) return HYDRO_OK;
+    if (!U_in || !U_out || !amax || U_in == U_out || !aligned8(U_in) || !aligned8(U_out))
+        return HYDRO_EINVAL;
+    if ((rc = check_device())) return rc;
+    const int variant = hydro_selected_variant(batch->n_sub, 5);
+    StepArgs a = make_args(params, batch);
+    if (fused_variant_needs_scratch(variant)) {
+        if ((rc = noalloc_scratch(&a.scratch))) return rc;
+        // the words this launch uses start at zero, whatever an earlier call
+        // left behind
+        const int64_t words = fused_scratch_bytes(batch->n_sub) / 4;
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        hipLaunchKernelGGL(k_clear_words, dim3((unsigned)((words + 255) / 256 < 1024 ? (words + 255) / 256 : 1024)),
+                           dim3(256), 0, st, a.scratch, words);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail_hip(e);
+    }
+    return launch_step(a, U_in, U_out, amax, status, variant, stream);
 }
 
 int hydro_step_io(const hydro_params *params, const hydro_batch *batch,

@@ -23,7 +23,7 @@ EXPORTS = [
     "hydro_fill_ghosts", "hydro_rate", "hydro_cfl_dt", "hydro_rk_update",
     "hydro_rk3_create", "hydro_rk3_launch", "hydro_rk3_destroy", "hydro_tau_resync",
     "hydro_rk_stage", "hydro_step_io", "hydro_workspace_bytes", "hydro_subgrid_n",
-    "hydro_step_gather",
+    "hydro_step_gather", "hydro_step_noalloc",
 ]
 
 STATUS_RHO, STATUS_P, STATUS_NONFINITE, STATUS_BADMETA = 1, 2, 4, 8
@@ -76,6 +76,7 @@ def lib(n: int = 8):
         L.hydro_flux.argtypes = [P, B, vp, vp, vp, vp, vp, vp, vp]
         L.hydro_divergence.argtypes = [P, B, vp, vp, vp, vp, vp]
         L.hydro_step.argtypes = [P, B, vp, vp, vp, vp, vp]
+        L.hydro_step_noalloc.argtypes = [P, B, vp, vp, vp, vp, vp]
         L.hydro_step_variant.argtypes = [P, B, vp, vp, vp, vp, ctypes.c_int, vp]
         L.hydro_autotune.argtypes = [P, B, vp, vp, vp, vp, ctypes.c_int,
                                      ctypes.POINTER(ctypes.c_float), vp]
@@ -222,6 +223,17 @@ def step(prm: Params, batch: Batch, U_in, U_out, amax, status=None, variant=None
         check(lib().hydro_step_variant(ctypes.byref(prm), ctypes.byref(batch), _ptr(U_in),
                                        _ptr(U_out), _ptr(amax), _ptr(status), int(variant),
                                        _stream(stream)))
+
+
+def step_noalloc(prm: Params, batch: Batch, U_in, U_out, amax, status=None, stream=None):
+    """hydro_step without any device allocation (fixed scratch in the library;
+    at most NOALLOC_MAX_SUB subgrids)."""
+    check(lib().hydro_step_noalloc(ctypes.byref(prm), ctypes.byref(batch), _ptr(U_in),
+                                   _ptr(U_out), _ptr(amax), _ptr(status), _stream(stream)))
+
+
+NOALLOC_MAX_SUB = 65536
+ESCRATCH = -4
 
 
 def step_io(prm: Params, batch: Batch, out_offset, U_in, U_out, amax, status=None, stream=None):
