@@ -261,24 +261,46 @@ def plain_vs_batched(torch, hydro, inputs, reps=3):
     return out
 
 
-def serving_run(torch, hydro, serving, b, db, peak_subgrids_per_s, n_requests, budget_gb):
+def serving_run(torch, hydro, serving, b, db, peak_subgrids_per_s, n_requests, budget_gb,
+                lanes=2):
     """Continuous-batching serving of Poisson request streams drawn from the
-    128^3 batch at offered loads 0.3/0.6/0.9 of the measured batched peak."""
+    128^3 batch.  The loop's capacity is measured first: the same kind of
+    stream with every request visible at once (the queue never empties),
+    with one lane and with `lanes` lanes.  The offered loads 0.3/0.6/0.9 are
+    fractions of that capacity (with `lanes` lanes), so a load below 1 is
+    one the loop can sustain; each is also given against the kernel's batched
+    peak."""
     n_slots = serving.slots_for_budget(int(budget_gb * 1e9))
-    be = serving.GpuBackend(n_slots, catalogue=db)
+    be = serving.GpuBackend(n_slots, catalogue=db, max_lanes=lanes)
     be.warmup(b.dt)
     work = serving.mean_work(4000, b.n_sub)
     out = {"budget_GB": budget_gb, "slots": n_slots, "requests_per_load": n_requests,
-           "peak_subgrid_steps_per_s": peak_subgrids_per_s, "mean_subgrid_steps_per_request": work,
-           "streams": 2, "loads": {}}
+           "kernel_peak_subgrid_steps_per_s": peak_subgrids_per_s,
+           "mean_subgrid_steps_per_request": work, "lanes": lanes, "loads": {}}
+    cap = {}
+    for nl in sorted({1, lanes}):
+        reqs = serving.poisson_requests(n_requests, 1.0, b.n_sub, b.h, b.n_species, seed=1006)
+        for r in reqs:
+            r.arrival = 0.0                  # all queued at the start
+        summ = serving.summarize(serving.HydroServer(be, b.dt, lanes=nl).run(reqs, realtime=False))
+        cap[nl] = summ["subgrid_steps_per_s"]
+        log(f"serving capacity, {nl} lane(s): {cap[nl]:.3e} subgrid-steps/s "
+            f"({cap[nl] / peak_subgrids_per_s:.3f} of the kernel's batched peak)")
+    capacity = cap[lanes]
+    out["capacity_subgrid_steps_per_s"] = {str(k): v for k, v in cap.items()}
+    out["capacity_over_kernel_peak"] = capacity / peak_subgrids_per_s
     for load in (0.3, 0.6, 0.9):
-        rate = load * peak_subgrids_per_s / work
+        rate = load * capacity / work
         reqs = serving.poisson_requests(n_requests, rate, b.n_sub, b.h, b.n_species)
-        recs = serving.HydroServer(be, b.dt).run(reqs, realtime=True)
+        recs = serving.HydroServer(be, b.dt, lanes=lanes).run(reqs, realtime=True)
         summ = serving.summarize(recs)
         summ["offered_requests_per_s"] = rate
+        summ["offered_subgrid_steps_per_s"] = rate * work
+        summ["offered_over_kernel_peak"] = rate * work / peak_subgrids_per_s
+        summ["delivered_over_offered"] = summ["subgrid_steps_per_s"] / (rate * work)
         out["loads"][str(load)] = summ
-        log(f"serving load {load}: {summ['cell_updates_per_s']:.3e} cell-updates/s, "
+        log(f"serving load {load} of capacity: {summ['cell_updates_per_s']:.3e} cell-updates/s "
+            f"({summ['delivered_over_offered']:.3f} of offered), "
             f"p50 {summ['latency_ms']['p50']:.2f} ms, p99 {summ['latency_ms']['p99']:.2f} ms, "
             f"{summ['ticks']} ticks")
     del be
@@ -319,6 +341,149 @@ def rk3_timing(torch, hydro, db, n_per_dim, periodic, steps):
             "stage_cell_updates_per_s": 3 * cells / (ms * 1e-3),
             "time_steps_per_s": 1e3 / ms, "simulated_time": t_sim,
             "nonzero_status": st, "ghost_fill_ms": fill_ms}
+
+
+def _launch_set(torch, hydro, cat_db, picks):
+    """Batch descriptors of a set of launches that each take the subgrids
+    picks[l] of a resident catalogue: all launches' metadata in one device
+    buffer, outputs (U_out at the catalogue's offsets, amax and status) in
+    buffers of their own."""
+    cat_off = cat_db.offset.cpu().numpy()
+    cat_h = cat_db.h.cpu().numpy()
+    cat_ns = cat_db.n_species_host
+    idx = np.concatenate(picks)
+    off = torch.as_tensor(cat_off[idx]).cuda()
+    h = torch.as_tensor(cat_h[idx]).cuda()
+    ns = torch.as_tensor(cat_ns[idx].astype(np.int32)).cuda()
+    amax = torch.zeros(len(idx), dtype=torch.float64, device="cuda")
+    status = torch.zeros(len(idx), dtype=torch.int32, device="cuda")
+    launches, start = [], 0
+    for p in picks:
+        n = len(p)
+        b = hydro.Batch(n, cat_db.fstride, off.data_ptr() + 8 * start, h.data_ptr() + 8 * start,
+                        ns.data_ptr() + 4 * start)
+        launches.append((b, amax[start:start + n], status[start:start + n], cat_ns[p]))
+        start += n
+    return {"launches": launches, "keep": (off, h, ns), "amax": amax, "status": status}
+
+
+def _time_launches(torch, hydro, prm, cat_db, U_out, ls, variant=None):
+    """Every launch of the set once (warm-up), then once more timed: HIP
+    events around each launch and around the whole set."""
+    def go(timed):
+        evs = []
+        for b, am, st, _ in ls["launches"]:
+            if timed:
+                e = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                e[0].record(torch.cuda.current_stream())
+            hydro.step(prm, b, cat_db.U, U_out, am, st, variant=variant)
+            if timed:
+                e[1].record(torch.cuda.current_stream())
+                evs.append(e)
+        return evs
+    go(False)
+    torch.cuda.synchronize()
+    a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(torch.cuda.current_stream())
+    evs = go(True)
+    z.record(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    per = np.array([x.elapsed_time(y) for x, y in evs])
+    return a.elapsed_time(z), per
+
+
+def config4_run(torch, hydro, inputs, costmodel, n_launches):
+    """Config 4: uneven AMR batches.  A catalogue of 8192 subgrids of the
+    binary-star field at levels 0-4 (0 or 5 species each) stays resident;
+    each launch takes n = clip(round(lognormal(ln 256, 1.5)), 1, 8192) of
+    them (seeded, without repetition).  The launches run back to back with
+    the default launch shape for their size, again after autotuning every
+    size bucket that occurs, and with the one-sweep shape (persistent-2x)
+    for all of them."""
+    cat = inputs.config4(launch=9, n_override=8192)
+    db = hydro.DeviceBatch.from_inputs(cat)
+    rng = np.random.default_rng([1004, 200])
+    sizes = np.clip(np.round(np.exp(rng.normal(np.log(256), 1.5, n_launches))), 1,
+                    cat.n_sub).astype(int)
+    picks = [np.sort(rng.choice(cat.n_sub, n, replace=False)) for n in sizes]
+    ls = _launch_set(torch, hydro, db, picks)
+    prm = hydro.params(dt=cat.dt)
+    U_out = db.U.clone()
+    flops = sum(costmodel.cost(nsp)[0] for *_, nsp in ls["launches"])
+    cells = int(sizes.sum()) * 512
+    out = {"workload": f"{n_launches} launches of lognormal(ln 256, 1.5) sizes in [1, 8192] "
+                       "drawn from 8192 resident binary-star subgrids at levels 0-4, 0 or 5 "
+                       "species mixed",
+           "launches": n_launches, "subgrid_steps": int(sizes.sum()),
+           "size_p50": float(np.median(sizes)), "size_max": int(sizes.max()),
+           "flops": flops}
+
+    def record(name, total_ms, per):
+        kern = float(per.sum())
+        out[name] = {"ms_total": total_ms, "cell_updates_per_s": cells / (total_ms * 1e-3),
+                     "kernel_ms_sum": kern,
+                     "fp64_tflops": flops / (kern * 1e-3) / 1e12,
+                     "alu_frac": flops / (kern * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                     "launch_ms": {"p50": float(np.percentile(per, 50)),
+                                   "p99": float(np.percentile(per, 99)),
+                                   "max": float(per.max())}}
+        log(f"config4 {name}: {total_ms:.2f} ms for {n_launches} launches, "
+            f"{out[name]['cell_updates_per_s']:.3e} cell-updates/s, launch p50 "
+            f"{out[name]['launch_ms']['p50']:.3f} p99 {out[name]['launch_ms']['p99']:.3f} ms")
+
+    record("one_sweep", *_time_launches(torch, hydro, prm, db, U_out, ls, variant=1))
+    record("default_shapes", *_time_launches(torch, hydro, prm, db, U_out, ls))
+    # autotune one launch of every power-of-two size bucket that occurs
+    tuned = {}
+    for (b, am, st, _), n in zip(ls["launches"], sizes):
+        key = int(np.ceil(np.log2(max(n, 1))))
+        if key not in tuned:
+            best, _ = hydro.autotune(prm, b, db.U, U_out, am, st, reps=3)
+            tuned[key] = hydro.variant_name(best)
+    out["tuned_shapes"] = {str(2 ** k): v for k, v in sorted(tuned.items())}
+    record("tuned", *_time_launches(torch, hydro, prm, db, U_out, ls))
+    st = ls["status"].cpu().numpy()
+    out["nonzero_status"] = int(np.count_nonzero(st))
+    del U_out, ls, db
+    torch.cuda.empty_cache()
+    return out
+
+
+def single_subgrid_latency(torch, hydro, inputs, reps=200):
+    """Config 1: one subgrid per launch, eager and replayed from a plan; HIP
+    events around each launch."""
+    b = inputs.config1()
+    db = hydro.DeviceBatch.from_inputs(b)
+    prm = hydro.params(dt=b.dt)
+    U_out = db.U.clone()
+    amax = torch.zeros(1, dtype=torch.float64, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out = {"workload": "one 8^3 subgrid (+3 ghosts), 11 fields",
+           "shape": hydro.variant_name(hydro.selected_variant(1))}
+    for name, fn in (("eager", lambda: hydro.step(prm, db.struct, db.U, U_out, amax, status)),
+                     ("one_sweep", lambda: hydro.step(prm, db.struct, db.U, U_out, amax, status,
+                                                      variant=1))):
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+        evs = []
+        for _ in range(reps):
+            e = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            e[0].record(torch.cuda.current_stream())
+            fn()
+            e[1].record(torch.cuda.current_stream())
+            evs.append(e)
+        torch.cuda.synchronize()
+        per = np.array([x.elapsed_time(y) for x, y in evs])
+        out[name] = {"p50_ms": float(np.percentile(per, 50)), "p99_ms": float(np.percentile(per, 99))}
+    plan = hydro.Plan(prm, db.struct, db.U, U_out, amax, status)
+    _, per = timed_plan(plan, reps, 5, torch)
+    plan.close()
+    out["graph"] = {"p50_ms": float(np.percentile(per, 50)), "p99_ms": float(np.percentile(per, 99))}
+    log(f"config1 one subgrid ({out['shape']}): eager p50 {out['eager']['p50_ms'] * 1e3:.1f} us, "
+        f"graph p50 {out['graph']['p50_ms'] * 1e3:.1f} us, one sweep p50 "
+        f"{out['one_sweep']['p50_ms'] * 1e3:.1f} us")
+    return out
 
 
 def _oracle_slice(args):
@@ -388,6 +553,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-rk3", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-config4", action="store_true")
+    ap.add_argument("--config4-launches", type=int, default=200)
     ap.add_argument("--rk3-steps", type=int, default=10)
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-budget-gb", type=float, default=64.0)
@@ -502,6 +669,9 @@ def main():
                                                                           "config3", 1)
     del U_out
     torch.cuda.empty_cache()
+    if not args.no_config4:
+        result["config4"] = config4_run(torch, hydro, inputs, costmodel, args.config4_launches)
+        result["config1_latency"] = single_subgrid_latency(torch, hydro, inputs)
     if not args.no_serving:
         result["serving"] = serving_run(torch, hydro, serving, b, db, b.n_sub / (kern_ms * 1e-3),
                                         args.serving_requests, args.serving_budget_gb)

@@ -293,10 +293,12 @@ int hydro_autotune(const hydro_params *params, const hydro_batch *batch,
                    int32_t *status, int reps, float *times_ms, void *stream);
 
 /* The variant hydro_step will use for a batch of n_sub subgrids: the tuned one
- * for that power-of-two bucket, else the default -- split-8, -4 or -2 when
- * n_sub times the parts still fits one work item per CU (at most 32, 64 or
- * 128 subgrids on 256 CUs), persistent-2x otherwise.  max_species is
- * reserved: the choice does not depend on it. */
+ * for that power-of-two bucket, else the default -- the split into P = 1, 2,
+ * 4 or 8 parts with the fewest rounds of work items over the CUs, each round
+ * weighted by a part's measured time (P = 8 up to 32 subgrids on 256 CUs,
+ * P = 4 up to 64, P = 2 up to 128 and for tails such as 300 or 600
+ * subgrids), with P = 1 launched as persistent-2x.  max_species is reserved:
+ * the choice does not depend on it. */
 int hydro_selected_variant(int n_sub, int max_species);
 
 /* ---------------------------------------------------------------------------

@@ -1372,13 +1372,24 @@ bool fused_variant_needs_scratch(int v) {
 int64_t fused_scratch_bytes(int n_sub) { return 64 + 16 * (int64_t)(n_sub > 0 ? n_sub : 0); }
 
 int fused_default_variant(int n_sub) {
-    // fewer subgrids than CUs: as many parts per subgrid as keep one work
-    // item per CU; otherwise two persistent workgroups per CU (the second
-    // wave of workgroups evens out the tail)
-    const int cus = device_cus();
-    for (int lp = 3; lp >= 1; lp--)
-        if ((int64_t)n_sub << lp <= cus) return kVariantSplit2 + lp - 1;
-    return 1;
+    // The launch of fewest rounds of work items, each round costing one
+    // part's time: ceil(n_sub P / CUs) t(P), with t(P) the time of one part
+    // relative to a whole sweep as measured on an MI355X (141.5, 82.9, 52.2
+    // and 36.4 us for P = 1, 2, 4, 8).  P = 1 launches as persistent-2x (the
+    // second wave of workgroups evens out the tail).
+    static const double kPartCost[4] = {1.0, 0.586, 0.369, 0.257};
+    const int64_t cus = device_cus();
+    int best = 0;
+    double best_t = 0.0;
+    for (int lp = 0; lp <= 3; lp++) {
+        const int64_t items = (int64_t)n_sub << lp;
+        const double t = (double)((items + cus - 1) / cus) * kPartCost[lp];
+        if (lp == 0 || t < best_t * 0.98) {
+            best = lp;
+            best_t = t;
+        }
+    }
+    return best == 0 ? 1 : kVariantSplit2 + best - 1;
 }
 
 void apply_variant(StepArgs &a, int v) {

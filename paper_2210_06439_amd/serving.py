@@ -19,9 +19,17 @@ returned when the tick that finishes a session has completed on the device.
 Ticks.  A session's stage k reads copy k % 2 and writes copy (k + 1) % 2.
 A tick is one launch of the fused step with per-subgrid input and output
 offsets into one pool buffer, so sessions at even and odd stages advance
-together; new sessions are copied in on a second stream that the tick waits
+together; new sessions are copied in on a copy stream that the tick waits
 for.  The host builds and launches tick t+1 while tick t runs, and retires
-tick t (completions, freed slots) before it launches tick t+2.
+the oldest tick (completions, freed slots) before it launches a third.
+
+Lanes.  With lanes > 1 the sessions are dealt to several lanes at
+admission (each to the lane with the fewest resident subgrids); every lane
+runs its own sequence of ticks on its own stream, so the ticks of different
+lanes overlap on the device: the tail of one tick (its last, partly filled
+round of workgroups) runs beside the start of another lane's tick, and one
+lane's launch gaps are filled by the other.  A session stays in its lane,
+so its stages still run one after another.
 
 The arithmetic is the library's fused step; a session's result does not
 depend on what else is in its ticks (the kernel computes each subgrid on its
@@ -72,6 +80,7 @@ class Record:
     n: int
     steps: int
     arrival: float
+    lane: int = 0
     admitted: float = float("nan")
     completed: float = float("nan")
     status: int = 0
@@ -119,10 +128,14 @@ def slots_for_budget(budget_bytes: int, nf_max: int = NF_MAX, fstride: int = FST
 class HydroServer:
     """Continuous-batching loop over a backend (see module docstring)."""
 
-    def __init__(self, backend, dt: float):
+    def __init__(self, backend, dt: float, lanes: int = 1):
         self.be = backend
         self.dt = float(dt)
         self.pool = SlotPool(backend.n_slots)
+        self.lanes = int(lanes)
+        if self.lanes < 1 or self.lanes > getattr(backend, "max_lanes", 1):
+            raise ValueError(f"{self.lanes} lanes: the backend supports "
+                             f"{getattr(backend, 'max_lanes', 1)}")
 
     def run(self, requests, realtime: bool = True,
             on_complete: Optional[Callable] = None) -> list:
@@ -136,15 +149,19 @@ class HydroServer:
         recs = {r.rid: Record(r.rid, r.n, r.steps, r.arrival) for r in reqs}
         pending = collections.deque(reqs)
         waiting = collections.deque()
-        active: list[_Session] = []
-        inflight = collections.deque()      # (tick handle, sessions finishing at it, all sessions in it)
+        L = self.lanes
+        active: list[list[_Session]] = [[] for _ in range(L)]
+        resident = [0] * L                  # subgrids admitted to each lane and not yet done
+        inflight = collections.deque()      # (tick handle, sessions finishing, all sessions, lane)
+        lane_inflight = [0] * L
+        next_lane = 0
         tick_no = 0
         t0 = self.be.start()
 
         def now():
             return self.be.now(t0)
 
-        while pending or waiting or active or inflight:
+        while pending or waiting or any(active) or inflight:
             t = now() if realtime else float("inf")
             while pending and pending[0].arrival <= t:
                 waiting.append(pending.popleft())
@@ -164,36 +181,56 @@ class HydroServer:
                 rec = recs[r.rid]
                 rec.admitted = now()
                 s = _Session(r, rec, slots)
+                lane = min(range(L), key=lambda q: (resident[q], q))
+                rec.lane = lane
+                resident[lane] += r.n
                 admitted.append(s)
-                active.append(s)
+                active[lane].append(s)
             if admitted:
                 self.be.load(admitted)
-            # retire the oldest tick first when two are in flight
-            if len(inflight) >= 2 or (inflight and not active):
-                self._retire(inflight.popleft(), t0, on_complete)
+            # the next lane (in turn) with sessions and fewer than two ticks in flight
+            lane = None
+            for q in range(L):
+                c = (next_lane + q) % L
+                if active[c] and lane_inflight[c] < 2:
+                    lane = c
+                    break
+            # retire the oldest tick when no lane can launch, or when every
+            # lane that could is busy
+            if inflight and (lane is None or len(inflight) >= 2 * L):
+                item = inflight.popleft()
+                lane_inflight[item[3]] -= 1
+                for s in item[1]:
+                    resident[item[3]] -= s.req.n
+                self._retire(item, t0, on_complete)
                 continue
-            if not active:
+            if lane is None:
                 if pending and realtime:
                     self.be.idle_until(t0, pending[0].arrival)
                 continue
             groups = ([], [])
-            for s in active:
+            for s in active[lane]:
                 groups[s.launched % 2].append(s)
-            handle = self.be.launch_tick(groups, self.dt, tick_no)
+            if L == 1:
+                handle = self.be.launch_tick(groups, self.dt, tick_no)
+            else:
+                handle = self.be.launch_tick(groups, self.dt, tick_no, lane=lane)
             finishing = []
-            for s in active:
+            for s in active[lane]:
                 s.launched += 1
                 s.rec.ticks.append(tick_no)
                 if s.launched == s.req.steps:
                     finishing.append(s)
-            inflight.append((handle, finishing, list(active)))
-            active = [s for s in active if s.launched < s.req.steps]
+            inflight.append((handle, finishing, list(active[lane]), lane))
+            lane_inflight[lane] += 1
+            active[lane] = [s for s in active[lane] if s.launched < s.req.steps]
+            next_lane = (lane + 1) % L
             tick_no += 1
         self.be.finish()
         return [recs[r.rid] for r in requests]
 
     def _retire(self, item, t0, on_complete):
-        handle, finishing, members = item
+        handle, finishing, members, _ = item
         t_end, status = self.be.wait_tick(handle, t0)
         for s in members:
             st = status.get(id(s), 0)
@@ -266,7 +303,8 @@ class GpuBackend:
     """
 
     def __init__(self, n_slots: int, catalogue=None, gamma=5.0 / 3.0, de_switch=1e-3,
-                 nf_max: int = NF_MAX, fstride: int = FSTRIDE, flags: int = 0):
+                 nf_max: int = NF_MAX, fstride: int = FSTRIDE, flags: int = 0,
+                 max_lanes: int = 2):
         import torch
 
         from . import hydro
@@ -284,7 +322,9 @@ class GpuBackend:
             if catalogue.fstride != fstride or np.any(off != np.arange(len(off)) * self.slot_elems):
                 raise ValueError("catalogue subgrids must each fill one slot-sized region")
         self.gamma, self.de_switch, self.flags = gamma, de_switch, int(flags)
-        self.compute = torch.cuda.Stream()
+        self.max_lanes = int(max_lanes)
+        self.lane_streams = [torch.cuda.Stream() for _ in range(self.max_lanes)]
+        self.compute = self.lane_streams[0]
         self.copy = torch.cuda.Stream()
         self._load_ev = None
         self.tick_log = []      # per retired tick: (subgrids, GPU start s, GPU end s)
@@ -293,10 +333,10 @@ class GpuBackend:
         self._idx_h = torch.empty(3 * self.n_slots, dtype=torch.int64, pin_memory=True)
         self._idx_d = torch.empty(3 * self.n_slots, dtype=torch.int64, device=dev)
         self._idx_ev = None
-        # ring of metadata buffers: three ticks (two in flight, one being filled)
+        # ring of metadata buffers: two ticks in flight per lane, one being filled
         n = 2 * self.n_slots
         self.ring = []
-        for _ in range(3):
+        for _ in range(2 * self.max_lanes + 1):
             self.ring.append({
                 "off_h": torch.empty(self.n_slots, dtype=torch.int64, pin_memory=True),
                 "oo_h": torch.empty(self.n_slots, dtype=torch.int64, pin_memory=True),
@@ -326,8 +366,9 @@ class GpuBackend:
         sess = [SimpleNamespace(req=req, slots=np.arange(n, dtype=np.int64))]
         self.start()
         self.load(sess)
-        self.wait_tick(self.launch_tick((sess, []), 0.0, 0), 0.0)
-        self.wait_tick(self.launch_tick(([], sess), 0.0, 1), 0.0)
+        for lane in range(self.max_lanes):     # every lane's stream (and its scratch)
+            self.wait_tick(self.launch_tick((sess, []), 0.0, 2 * lane, lane=lane), 0.0)
+            self.wait_tick(self.launch_tick(([], sess), 0.0, 2 * lane + 1, lane=lane), 0.0)
         self.read(sess[0].slots, 0)
         self.torch.cuda.synchronize()
 
@@ -400,9 +441,9 @@ class GpuBackend:
         return v.cpu().numpy().reshape(len(slots), self.nf_max, self.fstride)
 
     # -- ticks ---------------------------------------------------------------
-    def launch_tick(self, groups, dt, tick_no):
+    def launch_tick(self, groups, dt, tick_no, lane: int = 0):
         torch, hydro = self.torch, self.hydro
-        b = self.ring[tick_no % 3]
+        b = self.ring[tick_no % len(self.ring)]
         sess = list(groups[0]) + list(groups[1])
         par = [0] * len(groups[0]) + [1] * len(groups[1])
         sizes = [s.req.n for s in sess]
@@ -418,11 +459,12 @@ class GpuBackend:
             np.concatenate([s.req.h for s in sess], out=b["h_h"].numpy()[:p])
             np.concatenate([s.req.n_species for s in sess], out=b["ns_h"].numpy()[:p],
                            casting="unsafe")
-        st = self.compute
+        st = self.lane_streams[lane]
         with torch.cuda.stream(st):
             if self._load_ev is not None:
+                # the latest load (every session of this tick was loaded by it
+                # or by an earlier one, which the copy stream ran first)
                 st.wait_event(self._load_ev)
-                self._load_ev = None
             e0 = torch.cuda.Event(enable_timing=True)
             e0.record(st)
             if p:
@@ -448,7 +490,7 @@ class GpuBackend:
         ids, starts, sizes = rows
         status = {}
         if ids:
-            sh = self.ring[tick_no % 3]["status_h"].numpy()[:p]
+            sh = self.ring[tick_no % len(self.ring)]["status_h"].numpy()[:p]
             red = np.bitwise_or.reduceat(sh, starts) if p else np.zeros(len(ids), np.int32)
             status = {sid: int(v) for sid, v, k in zip(ids, red, sizes) if k and v}
         return t_end, status

@@ -31,21 +31,26 @@ def _requests(b):
     return out
 
 
-def _serve(db, reqs, n_slots, dt, flags=0):
+def _serve(db, reqs, n_slots, dt, flags=0, lanes=1):
     be = serving.GpuBackend(n_slots, catalogue=db, flags=flags)
     finals = {}
 
     def grab(req, slots, copy):
         finals[req.rid] = be.read(slots, copy)
 
-    recs = serving.HydroServer(be, dt).run(reqs, realtime=False, on_complete=grab)
+    recs = serving.HydroServer(be, dt, lanes=lanes).run(reqs, realtime=False, on_complete=grab)
     return recs, finals
 
 
-def test_alone_equals_in_the_mix_and_matches_oracle(cat):
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_alone_equals_in_the_mix_and_matches_oracle(cat, lanes):
+    """In the mix -- with one lane, or with two whose ticks overlap on the
+    device -- each request's result is the bits of the request served alone."""
     b, db = cat
     reqs = _requests(b)
-    recs, mixed = _serve(db, reqs, 12, b.dt)      # 12 slots: admission has to wait
+    recs, mixed = _serve(db, reqs, 12, b.dt, lanes=lanes)   # 12 slots: admission has to wait
+    if lanes == 2:
+        assert {r.lane for r in recs} == {0, 1}
     assert all(not r.rejected and r.status == 0 for r in recs)
     starts = sorted(r.ticks[0] for r in recs)
     assert starts[-1] > 0                          # some requests joined later ticks
@@ -103,7 +108,7 @@ def test_realtime_poisson_stream(cat):
                                     n_species=b.n_species, seed=73, median_n=4,
                                     max_n=12)
     be = serving.GpuBackend(16, catalogue=db)
-    recs = serving.HydroServer(be, b.dt).run(reqs, realtime=True)
+    recs = serving.HydroServer(be, b.dt, lanes=2).run(reqs, realtime=True)
     assert all(not r.rejected for r in recs)
     for r in recs:
         assert r.completed > r.arrival and len(r.ticks) == r.steps

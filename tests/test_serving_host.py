@@ -21,6 +21,7 @@ class OracleBackend:
         self.cat = catalogue
         self.copies = [np.zeros(n_slots * SLOT), np.zeros(n_slots * SLOT)]
         self.ticks = []          # per tick: (group0 rids, group1 rids)
+        self.lanes = []          # per tick: its lane
         self.loads = []          # per load call: rids
 
     def start(self):
@@ -41,8 +42,11 @@ class OracleBackend:
                 for c in range(2):
                     self.copies[c][slot * SLOT:(slot + 1) * SLOT] = blk
 
-    def launch_tick(self, groups, dt, tick_no):
+    max_lanes = 2
+
+    def launch_tick(self, groups, dt, tick_no, lane=0):
         self.ticks.append(tuple([s.req.rid for s in g] for g in groups))
+        self.lanes.append(lane)
         status = {}
         for g in range(2):
             for s in groups[g]:
@@ -122,6 +126,35 @@ def test_sessions_at_different_stages_share_ticks(catalogue):
         for s in range(r.n):
             blk = U[int(sub.offset[s]):int(sub.offset[s]) + SLOT]
             assert np.array_equal(got[s], blk), (r.rid, s)
+
+
+def test_two_lanes_keep_sessions_in_order_and_results_alone(catalogue):
+    """Sessions dealt to two lanes: each runs its stages in one lane, in
+    consecutive ticks of that lane, both lanes carry work, and every result
+    is the request stepped alone."""
+    be = OracleBackend(12, catalogue)
+    srv = serving.HydroServer(be, dt=catalogue.dt, lanes=2)
+    reqs = [_req(i, [(3 * i + k) % 12 for k in range(1 + i % 3)], 1 + i % 4, 0.3 * i, catalogue)
+            for i in range(10)]
+    finals = {}
+
+    def grab(req, slots, copy):
+        finals[req.rid] = be.read(slots, copy)
+
+    recs = srv.run(reqs, realtime=True, on_complete=grab)
+    assert all(not r.rejected for r in recs)
+    assert set(be.lanes) == {0, 1}
+    for r in recs:
+        assert all(be.lanes[t] == r.lane for t in r.ticks)
+        lane_ticks = [t for t, q in enumerate(be.lanes) if q == r.lane]
+        first = lane_ticks.index(r.ticks[0])
+        assert r.ticks == lane_ticks[first:first + r.steps]
+    for r in reqs:
+        sub, U = _alone(catalogue, r.source, r.steps, catalogue.dt)
+        for s in range(r.n):
+            assert np.array_equal(finals[r.rid][s], U[int(sub.offset[s]):int(sub.offset[s]) + SLOT])
+    with pytest.raises(ValueError):
+        serving.HydroServer(be, dt=catalogue.dt, lanes=3)
 
 
 def test_oversize_and_empty_requests_are_rejected(catalogue):
