@@ -560,6 +560,8 @@ def main():
     ap.add_argument("--serving-budget-gb", type=float, default=64.0)
     ap.add_argument("--traffic-probe", action="store_true",
                     help="one fused step and a calibration copy, for counter runs")
+    ap.add_argument("--only-config4", action="store_true",
+                    help="the config-4 launches alone (for a kernel trace of them)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the hydro stage is measured on a single "
@@ -567,6 +569,14 @@ def main():
         sys.exit(2)
     if args.traffic_probe:
         traffic_probe()
+        return
+    if args.only_config4:
+        import torch
+
+        from paper_2210_06439_amd import costmodel, hydro, inputs
+        torch.cuda.set_device(0)
+        print(json.dumps({"config4": config4_run(torch, hydro, inputs, costmodel,
+                                                 args.config4_launches)}), flush=True)
         return
 
     from paper_2210_06439_amd import inputs
