@@ -517,7 +517,7 @@ def cpu_baseline(b, seconds, procs):
            "kind": "oracle",
            "sample": f"{done} subgrid steps over the 4096 subgrids of the 128^3 binary-star "
                      f"batch (random order, seed 0), single thread, {elapsed:.1f} s",
-           "cpu": _cpu_model()}
+           "cpu": _cpu_model(), "host": _host_cpus()}
     if procs > 1:
         slices = [(b, order[p::procs], seconds) for p in range(procs)]
         with multiprocessing.get_context("fork").Pool(procs) as pool:
@@ -526,7 +526,9 @@ def cpu_baseline(b, seconds, procs):
             wall = time.perf_counter() - t0
         n = sum(d for d, _ in res)
         out["all_cores"] = {"value": n * 512 / wall, "unit": "cell-updates/s", "cores": procs,
-                            "sample": f"{n} subgrid steps in {procs} processes, {wall:.1f} s"}
+                            "sample": f"{n} subgrid steps in {procs} processes, {wall:.1f} s",
+                            "note": "one process per core of the CPU share a one-GPU job gets "
+                                    "(16 on the MI355X box), whatever the host shows in all"}
     return out
 
 
@@ -539,6 +541,27 @@ def _cpu_model():
     except OSError:
         pass
     return "unknown"
+
+
+def _host_cpus():
+    """What the timing host shows of its CPUs: logical CPUs of the machine,
+    the ones this process may run on, and lscpu's sockets and cores."""
+    out = {"logical_cpus": os.cpu_count(), "model": _cpu_model()}
+    try:
+        out["usable_cpus"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    try:
+        import subprocess
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in txt.splitlines():
+            k, _, v = ln.partition(":")
+            if k.strip() in ("Socket(s)", "Core(s) per socket", "Thread(s) per core",
+                             "Model name", "CPU max MHz"):
+                out[k.strip()] = v.strip()
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    return out
 
 
 def main():

@@ -56,6 +56,72 @@ def build(force: bool = False, n: int | None = None, san: bool | None = None) ->
     return lib_path(8 if n is None else n, san)
 
 
+_COUNT_SRC = os.path.join(_HERE, "count_build.cpp")
+_COUNT_LIB = os.path.join(_HERE, "libhydro_ref_count.so")
+_count_lib = None
+
+
+def build_count(force: bool = False) -> str:
+    """Compile the operation-counting build of the oracle (count_build.cpp
+    includes hydro_ref.c unchanged; subgrid size 8)."""
+    if (force or not os.path.exists(_COUNT_LIB)
+            or os.path.getmtime(_COUNT_LIB) < max(os.path.getmtime(_SRC),
+                                                  os.path.getmtime(_COUNT_SRC))):
+        tmp = _COUNT_LIB + ".tmp"
+        subprocess.run(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+                        "-fno-fast-math", "-Wall", "-DREF_N=8", "-o", tmp, _COUNT_SRC, "-lm"],
+                       check=True)
+        os.replace(tmp, _COUNT_LIB)
+    return _COUNT_LIB
+
+
+def count_lib():
+    global _count_lib
+    if _count_lib is None:
+        L = ctypes.CDLL(build_count())
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int32)
+        P, B = ctypes.POINTER(Params), ctypes.POINTER(Batch)
+        L.hydro_ref_step.argtypes = [P, B, dp, dp, dp, ip]
+        L.hydro_ref_step.restype = ctypes.c_int
+        L.hydro_ref_ppm1d.argtypes = [dp, dp, dp]
+        L.hydro_ref_ppm1d.restype = ctypes.c_int
+        L.hydro_ref_state_flux.argtypes = [P, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, dp, ip]
+        L.hydro_ref_state_flux.restype = ctypes.c_int
+        L.hydro_ref_face.argtypes = [P, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, ip]
+        L.hydro_ref_face.restype = ctypes.c_int
+        L.hydro_ref_flops.argtypes = []
+        L.hydro_ref_flops.restype = ctypes.c_ulonglong
+        L.hydro_ref_flops_reset.argtypes = []
+        _count_lib = L
+    return _count_lib
+
+
+def counted(fn_name, *args):
+    """Call an entry point of the counting build; returns (return code,
+    operations counted during the call)."""
+    L = count_lib()
+    L.hydro_ref_flops_reset()
+    rc = getattr(L, fn_name)(*args)
+    return rc, int(L.hydro_ref_flops())
+
+
+def step_flops(U_in, offset, h, n_species, fstride, dt, gamma=5.0 / 3.0, de_switch=1e-3,
+               flags=0):
+    """One stage in the counting build: (U_out, amax, status, operations)."""
+    U_in = _f64(U_in)
+    ba = _BatchArgs(offset, h, n_species, fstride)
+    U_out = U_in.copy()
+    n = len(ba.offset)
+    amax = np.zeros(n)
+    status = np.zeros(n, dtype=np.int32)
+    prm = params(gamma, de_switch, dt, flags)
+    rc, ops = counted("hydro_ref_step", ctypes.byref(prm), ctypes.byref(ba.struct), _dp(U_in),
+                      _dp(U_out), _dp(amax), status.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    assert rc == 0, rc
+    return U_out, amax, status, ops
+
+
 class Params(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("de_switch", ctypes.c_double),
                 ("dt", ctypes.c_double), ("flags", ctypes.c_uint32)]
