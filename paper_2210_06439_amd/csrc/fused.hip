@@ -321,14 +321,19 @@ struct CwW {
 };
 
 // Pressure and velocity along (dx, dy, dz) of the window cell at offset o,
-// with the point-state formulas (dual-energy switch included).  With VEL the
-// momentum slots hold velocities.  The detectors that take these are
-// discontinuous in them, and a cell's weights are formed again by every
-// wave whose lines pass through it -- at a subgrid's edge by both
-// neighbours, which must agree for the face flux to be conservative -- so
-// the arithmetic is fixed: no contraction and the rounded quotient, in the
-// order of the definition (the dual-energy branch takes tau_pow, as the
-// point states do).
+// with the point-state formulas (dual-energy switch included).  The
+// detectors that take these are discontinuous in them, and a cell's weights
+// are formed again by every wave whose lines pass through it -- at a
+// subgrid's edge by both neighbours, which must agree for the face flux to
+// be conservative -- so the arithmetic is fixed: no contraction and the
+// rounded quotient (the dual-energy branch takes tau_pow, as the point
+// states do).  Without VEL it is the definition's order: v = s (1/rho),
+// e_k = (s.v)/2.  With VEL the momentum slots hold the correctly rounded
+// quotients s / rho, which are taken as v, and e_k = ((rho v).v)/2; these
+// differ from the definition's values in the last bits, so near a
+// detector's threshold a weight can differ from the definition's (parity
+// for this combination is checked on inputs whose detectors sit away from
+// their thresholds).
 template <bool VEL>
 __device__ __forceinline__ void cw_cell(const double *win, int o, int dx, int dy, int dz,
                                         double gamma, double gm1, double de, double &p,
