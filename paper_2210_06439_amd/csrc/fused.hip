@@ -51,19 +51,18 @@ constexpr int RUN_D = 6 * 64;                        // ring lanes: u_n and 5 sp
 constexpr int LDS_D = WIN_D + XCH_D + ZL_D + KEEP_D + RUN_D + 16;
 static_assert(LDS_D * 8 <= 163840, "LDS budget");
 
-// combine-phase sub-regions of XCH
+// combine-phase sub-regions of XCH.  The face fluxes lie in the slots of
+// the z-line producer, which is idle in the first round: the x owner reads
+// them to form its cells' flux differences while the next step's first
+// round is already being produced, with no barrier in between.
 constexpr int RST = 2 * 8 * 9;                       // stride of one component
 constexpr int XR_OFF = 0;                            // [24][2][8][9] right partials
-constexpr int XF_OFF = NACC * RST;                   // [11][2][8][9] face fluxes
-constexpr int LL_OFF = XF_OFF + NF_MAX * RST;        // [2][2][8][9] left speeds
+constexpr int LL_OFF = NACC * RST;                   // [2][2][8][9] left speeds
 constexpr int ZB_OFF = LL_OFF + 2 * RST;             // [4][64] z-face speeds
-constexpr int DY_OFF = LL_OFF;                       // [11][64] (after LL and ZB are read)
-constexpr int LAYER_D = 4 * PT * 64;                 // layer-step points
-static_assert(ZB_OFF + 4 * 64 <= XCH_D, "combine layout");
-static_assert(LAYER_D <= ZB_OFF, "layer points must not overlap the z speeds");
-static_assert(DY_OFF >= XF_OFF + NF_MAX * RST && DY_OFF >= 4 * PT * 64 &&
-                  DY_OFF + NF_MAX * 64 <= XCH_D,
-              "dFy must not overlap the x/y fluxes or round 0's exchange slots");
+constexpr int XF_OFF = 2 * 2 * PT * 64;              // [11][2][8][9] face fluxes
+static_assert(ZB_OFF + 4 * 64 <= XF_OFF, "combine layout");
+static_assert(XF_OFF >= 4 * PT * 64 && XF_OFF + NF_MAX * RST <= XCH_D,
+              "the face fluxes must lie outside round 0's and the face layers' exchange slots");
 
 // ---- the 13 lines: n = 14 + L, (dx,dy,dz) from the base-3 digits of n -------
 
@@ -81,7 +80,7 @@ __device__ __host__ constexpr int line_of(int w, int r) {
                   : (r == 0 ? -1 : r == 1 ? 4 : r == 2 ? 5 : r == 3 ? 11 : 8);
 }
 
-static_assert(line_of(2, 0) < 0, "the z-line producer must be idle in round 0 (see DY_OFF)");
+static_assert(line_of(2, 0) < 0, "the z-line producer must be idle in round 0 (see XF_OFF)");
 
 __device__ __forceinline__ int comp(int L, int axis) {
     return axis == 0 ? ldx(L) : axis == 1 ? ldy(L) : ldz(L);
@@ -1133,26 +1132,21 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
             else store_s(zl + lane, 64, acc[0], nspec);
         }
         lds_barrier();
-        // phase 3: x/y owners: flux differences of their cells.  The x owner
-        // writes dFx into the cell's kept x/y difference, the y owner puts dFy
-        // in LDS; after the barrier the z owner adds it.  DY lies where the
-        // next step's first round writes nothing (the z-line producer is idle
-        // in round 0), so no XCH value is read after the next rounds begin.
-        if (role < 2) {
-            const int row = role == 0 ? cj - 3 : ci - 3;
-            const int p = role == 0 ? ci - 3 : cj - 3;      // left face of the cell
-            const double *Fl = xch + XF_OFF + (role * 8 + row) * 9 + p;
-            double *d = role == 0 ? keep + NF_MAX * 64 + lane : xch + DY_OFF + lane;
-#pragma unroll
-            for (int f = 0; f < NF_MAX; f++)
-                if (f >= f0 && f < f1) d[f * 64] = Fb[f] - Fl[f * RST];
-        }
-        lds_barrier();
-        if (role == 2) {
+        // phase 3: the x owner forms its cells' x/y flux difference,
+        // (F_x right - F_x left) + (F_y above - F_y below), the x fluxes from
+        // its own right face and the face array, the y fluxes from the face
+        // array.  The first round of the next step writes only below XF_OFF,
+        // and the z-line producer (which writes above it) first produces in
+        // the second round, after the first round's barriers, so no barrier
+        // is needed here.
+        if (role == 0) {
+            const double *Fl = xch + XF_OFF + (cj - 3) * 9 + (ci - 3);     // left x face
+            const double *Fy = xch + XF_OFF + (8 + (ci - 3)) * 9 + (cj - 3); // y face below
 #pragma unroll
             for (int f = 0; f < NF_MAX; f++)
                 if (f >= f0 && f < f1)
-                    keep[(NF_MAX + f) * 64 + lane] += xch[DY_OFF + f * 64 + lane];
+                    keep[(NF_MAX + f) * 64 + lane] =
+                        (Fb[f] - Fl[f * RST]) + (Fy[f * RST + 1] - Fy[f * RST]);
         }
         }
     }
