@@ -693,6 +693,34 @@ __device__ __forceinline__ void update_cell(const double *win, const double *kee
         }
 }
 
+// update_cell with the summed flux difference of each field given,
+// dsum[f] = (dFx + dFy) + dFz: the z owner forms it before the second flux
+// phase's barrier (it reads the kept values another wave overwrites after
+// that barrier) and writes the cells after it, while the first round of the
+// next step is produced.
+template <bool VEL>
+__device__ __forceinline__ void update_cell_sum(const double *win, int kc, int ci, int cj,
+                                                int f0, int f1, const double *dsum, double lam,
+                                                bool rate, const Stage &stg, const double *Us,
+                                                double *Os, int fst, double &chk) {
+    const int cidx = opaque_v(kc * NPLANE + cj * NB + ci);
+    const int fs = opaque_s(fst);
+#pragma unroll
+    for (int f = 0; f < NF_MAX; f++)
+        if (f >= f0 && f < f1) {
+            const double u = (VEL && f >= 1 && f <= 3)
+                                 ? Us[f * fs + cidx]
+                                 : win[(kc % SLOTS) * SLOT_D + f * NPLANE + cj * NB + ci];
+            double v = (rate ? 0.0 : u) - lam * dsum[f];
+            if (stg.U0) {
+                const double u0 = stg.U0[f * fs + cidx];
+                v = stg.identity ? u0 : fma(stg.c0, u0, stg.c1 * v);
+            }
+            chk = fma(v, 0.0, chk);
+            Os[f * fs + cidx] = v;
+        }
+}
+
 // The work of one subgrid for one field group (HYD: hydro fields and point
 // states; else: species).  Both instantiations execute the same sequence of
 // barriers, so the hydro and species waves of a workgroup stay in step.
@@ -818,6 +846,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
 
     double acc[2][NH];       // [0]: face + (or the ring / layer face), [1]: face -
     double Fb[NF_MAX];
+    double dsum[NF_MAX];     // the z owner's summed flux differences of plane k-1
     for (int k = kb; k <= ke; k++) {
         const double *Us = Us0;
         double *Os = Os0;
@@ -1122,12 +1151,14 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                                               sym);
                 combine_s(acc[1], zl + lane, 64, false, sp, nspec, Fz);
             }
-            if (k >= kb + 2)
-                update_cell<VEL>(win, keep, lane, k - 1, ci, cj, f0, f1, Fz, lam, rate, stg, Us,
-                                 Os, fst, chk);
+            // plane k-1's summed flux differences (its cells are written after
+            // the barrier, where the x owner overwrites the kept x/y part)
 #pragma unroll
             for (int f = 0; f < NF_MAX; f++)
-                if (f >= f0 && f < f1) keep[f * 64 + lane] = Fz[f];
+                if (f >= f0 && f < f1) {
+                    dsum[f] = keep[(NF_MAX + f) * 64 + lane] + (Fz[f] - keep[f * 64 + lane]);
+                    keep[f * 64 + lane] = Fz[f];
+                }
             if (HYD) store_h(zl + lane, 64, acc[0]);
             else store_s(zl + lane, 64, acc[0], nspec);
         }
@@ -1139,6 +1170,9 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
         // and the z-line producer (which writes above it) first produces in
         // the second round, after the first round's barriers, so no barrier
         // is needed here.
+        if (role == 2 && k >= kb + 2)
+            update_cell_sum<VEL>(win, k - 1, ci, cj, f0, f1, dsum, lam, rate, stg, Us, Os, fst,
+                                 chk);
         if (role == 0) {
             const double *Fl = xch + XF_OFF + (cj - 3) * 9 + (ci - 3);     // left x face
             const double *Fy = xch + XF_OFF + (8 + (ci - 3)) * 9 + (cj - 3); // y face below
