@@ -125,15 +125,18 @@ __device__ __forceinline__ double simpson_w(int t1, int t2) {
 
 // ---- PPM in branch-free form ---------------------------------------------
 
-// Monotonised-central slope from the two one-sided differences.  The sign of
-// the centred difference d is applied by multiplication (the values stay
-// ordinary floats, so min/max need no NaN canonicalisation).
-__device__ __forceinline__ double mc_slope(double dm, double dp) {
-    double d = 0.5 * (dm + dp);
-    double sg = copysign(1.0, d);
-    double t = fmin(dm * sg, dp * sg);          // > 0 only if both share d's sign
-    t = fmax(fmin(fabs(d), t + t), 0.0);
-    return t * sg;
+// Twice the monotonised-central slope from the two one-sided differences:
+// sign(d) max(0, min(|dm + dp|, 4 min(sg dm, sg dp))), sg the sign of the
+// centred difference d = (dm + dp) / 2.  Halving is exact unless dm + dp is
+// subnormal, so this is bit for bit 2 x the slope min(|d|, 2|dm|, 2|dp|)
+// (zero unless dm and dp share d's sign), with one multiplication fewer.  The sign is applied by
+// multiplication (the values stay ordinary floats, so min/max need no NaN
+// canonicalisation).
+__device__ __forceinline__ double mc_slope2(double dm, double dp) {
+    const double sum = dm + dp;
+    const double sg = copysign(1.0, sum);
+    const double t = fmin(dm * sg, dp * sg);    // > 0 only if both share d's sign
+    return fmax(fmin(fabs(sum), 4.0 * t), 0.0) * sg;
 }
 
 // PPM on u_{-2..2}: the Colella-Woodward monotonicity step written in its
@@ -141,13 +144,14 @@ __device__ __forceinline__ double mc_slope(double dm, double dp) {
 // |b| <= 2|a| and |a| <= 2|b|), which needs no division and no branches.
 __device__ __forceinline__ void ppm_fast(double um2, double um1, double u0, double up1,
                                          double up2, double &qp, double &qm) {
-    const double sixth = 1.0 / 6.0;
+    // with the slopes doubled, (s0 - s+) / 6 is (S0 - S+) / 12: the same bits
+    const double twelfth = 1.0 / 12.0;
     double d0 = um1 - um2, d1 = u0 - um1, d2 = up1 - u0, d3 = up2 - up1;
-    double sm = mc_slope(d0, d1);
-    double s0 = mc_slope(d1, d2);
-    double sp = mc_slope(d2, d3);
-    double a = fma(s0 - sp, sixth, 0.5 * d2);    // q+ - u0
-    double b = fma(s0 - sm, sixth, 0.5 * d1);    // u0 - q-
+    double sm = mc_slope2(d0, d1);
+    double s0 = mc_slope2(d1, d2);
+    double sp = mc_slope2(d2, d3);
+    double a = fma(s0 - sp, twelfth, 0.5 * d2);  // q+ - u0
+    double b = fma(s0 - sm, twelfth, 0.5 * d1);  // u0 - q-
     double sg = copysign(1.0, a);
     double aa = fabs(a);
     double sb = b * sg;                          // |b| if b has a's sign, else < 0
@@ -164,15 +168,15 @@ __device__ __forceinline__ void ppm_fast(double um2, double um1, double u0, doub
 __device__ __forceinline__ void ppm_fast_w(double um2, double um1, double u0, double up1,
                                            double up2, double eta, double flat, double &qp,
                                            double &qm) {
-    const double sixth = 1.0 / 6.0;
+    const double twelfth = 1.0 / 12.0;
     double d0 = um1 - um2, d1 = u0 - um1, d2 = up1 - u0, d3 = up2 - up1;
-    double sm = mc_slope(d0, d1);
-    double s0 = mc_slope(d1, d2);
-    double sp = mc_slope(d2, d3);
-    double a = fma(s0 - sp, sixth, 0.5 * d2);
-    double b = fma(s0 - sm, sixth, 0.5 * d1);
-    a = fma(eta, fma(-0.5, sp, d2) - a, a);
-    b = fma(eta, fma(-0.5, sm, d1) - b, b);
+    double sm = mc_slope2(d0, d1);                // doubled slopes, as in ppm_fast
+    double s0 = mc_slope2(d1, d2);
+    double sp = mc_slope2(d2, d3);
+    double a = fma(s0 - sp, twelfth, 0.5 * d2);
+    double b = fma(s0 - sm, twelfth, 0.5 * d1);
+    a = fma(eta, fma(-0.25, sp, d2) - a, a);      // -s/2 = -S/4
+    b = fma(eta, fma(-0.25, sm, d1) - b, b);
     const double keep = 1.0 - flat;
     a *= keep;
     b *= keep;
