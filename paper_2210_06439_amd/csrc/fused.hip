@@ -308,13 +308,6 @@ __device__ __forceinline__ Line5 line5(int i, int j, int k, int dx, int dy, int 
     return l;
 }
 
-__device__ __forceinline__ void ppm_at(const double *win, const Line5 &l, int f, double &qp,
-                                       double &qm) {
-    const int fo = f * NPLANE;
-    ppm_fast(win[l.o[0] + fo], win[l.o[1] + fo], win[l.o[2] + fo], win[l.o[3] + fo],
-             win[l.o[4] + fo], qp, qm);
-}
-
 // ---- Colella-Woodward steepening and flattening (the CW instantiation) ------
 
 // Weights of one line: eta (contact steepening, density only) and flat
@@ -412,17 +405,46 @@ __device__ __forceinline__ CwW cw_weights(const double *win, const Line5 &l, int
     return w;
 }
 
-// PPM of field f along l: plain, or with the line's weights (eta for the
-// density only).
+// The five window values of field f along l.
+struct Pts5 {
+    double u[5];
+};
+
+__device__ __forceinline__ Pts5 load5(const double *win, const Line5 &l, int f) {
+    const int fo = f * NPLANE;
+    Pts5 p;
+#pragma unroll
+    for (int m = 0; m < 5; m++) p.u[m] = win[l.o[m] + fo];
+    return p;
+}
+
+// PPM of field f from its five values: plain, or with the line's weights
+// (eta for the density only).
 template <bool CW>
-__device__ __forceinline__ void ppm_line(const double *win, const Line5 &l, int f, const CwW &w,
-                                         double &qp, double &qm) {
-    if (!CW) {
-        ppm_at(win, l, f, qp, qm);
-    } else {
-        const int fo = f * NPLANE;
-        ppm_fast_w(win[l.o[0] + fo], win[l.o[1] + fo], win[l.o[2] + fo], win[l.o[3] + fo],
-                   win[l.o[4] + fo], f == 0 ? w.eta : 0.0, w.flat, qp, qm);
+__device__ __forceinline__ void ppm_pts(const Pts5 &p, int f, const CwW &w, double &qp,
+                                        double &qm) {
+    if (!CW) ppm_fast(p.u[0], p.u[1], p.u[2], p.u[3], p.u[4], qp, qm);
+    else ppm_fast_w(p.u[0], p.u[1], p.u[2], p.u[3], p.u[4], f == 0 ? w.eta : 0.0, w.flat, qp, qm);
+}
+
+// PPM of fields F0..F1-1 along l, handing each field's values to sink(f, q+,
+// q-).  A field's loads are issued before the previous field is
+// reconstructed: the sinks store to LDS, which the compiler cannot tell apart
+// from the window, so loads placed after a store would wait for it and leave
+// the load latency exposed field by field.
+template <bool CW, int F0, int F1, typename Sink>
+__device__ __forceinline__ void ppm_fields(const double *win, const Line5 &l, const CwW &cw,
+                                           Sink &&sink) {
+    Pts5 c = load5(win, l, F0);
+#pragma unroll
+    for (int f = F0; f < F1; f++) {
+        Pts5 n = c;
+        if (f + 1 < F1) n = load5(win, l, f + 1);
+        sched_fence();   // keep the loads ahead of the reconstruction
+        double qp, qm;
+        ppm_pts<CW>(c, f, cw, qp, qm);
+        sink(f, qp, qm);
+        c = n;
     }
 }
 
@@ -440,21 +462,28 @@ struct PlusState {
     double vx, vy, p, cs;
 };
 
-template <bool store_, bool both_, bool VEL, bool CW, bool minus_only = false>
+// The loads of field f + 1 are issued before field f is reconstructed (see
+// ppm_fields); with XF >= 0 the values of field XF are loaded the same way
+// during the last hydro field and returned in xv.
+template <bool store_, bool both_, bool VEL, bool CW, bool minus_only = false, int XF = -1>
 __device__ __forceinline__ PlusState produce_hydro(const double *win, const Line5 &l,
                                                    double *pp, double *pm, double gamma,
                                                    double gm1, double de, int &bits,
-                                                   const CwW &cw) {
+                                                   const CwW &cw, Pts5 *xv = nullptr) {
     constexpr bool plus = !minus_only, store = store_ && plus, both = both_ || minus_only;
     PlusState ps;
     double qp, qm;
-    ppm_line<CW>(win, l, 0, cw, qp, qm);
+    Pts5 c = load5(win, l, 0), n = load5(win, l, 1);
+    sched_fence();
+    ppm_pts<CW>(c, 0, cw, qp, qm);
     ps.q[0] = qp;
     if (store) pp[0] = qp;
     if (both) pm[0] = qm;
     const double rhop = qp, rhom = qm;
     const double rp = plus ? recip(qp) : 1.0, rm = both ? recip(qm) : 1.0;
-    ppm_line<CW>(win, l, 1, cw, qp, qm);
+    c = load5(win, l, 2);
+    sched_fence();
+    ppm_pts<CW>(n, 1, cw, qp, qm);
     const double wxp = qp, wxm = qm;
     if (VEL) {
         qp = rhop * wxp;
@@ -465,7 +494,9 @@ __device__ __forceinline__ PlusState produce_hydro(const double *win, const Line
     if (both) pm[64] = qm;
     const double vxp = VEL ? wxp : qp * rp, vxm = VEL ? wxm : qm * rm;
     double ekp = qp * vxp, ekm = qm * vxm;
-    ppm_line<CW>(win, l, 2, cw, qp, qm);
+    n = load5(win, l, 3);
+    sched_fence();
+    ppm_pts<CW>(c, 2, cw, qp, qm);
     const double wyp = qp, wym = qm;
     if (VEL) {
         qp = rhop * wyp;
@@ -477,7 +508,9 @@ __device__ __forceinline__ PlusState produce_hydro(const double *win, const Line
     const double vyp = VEL ? wyp : qp * rp, vym = VEL ? wym : qm * rm;
     ekp = fma(qp, vyp, ekp);
     ekm = fma(qm, vym, ekm);
-    ppm_line<CW>(win, l, 3, cw, qp, qm);
+    c = load5(win, l, 4);
+    sched_fence();
+    ppm_pts<CW>(n, 3, cw, qp, qm);
     const double wzp = qp, wzm = qm;
     if (VEL) {
         qp = rhop * wzp;
@@ -489,12 +522,16 @@ __device__ __forceinline__ PlusState produce_hydro(const double *win, const Line
     const double vzp = VEL ? wzp : qp * rp, vzm = VEL ? wzm : qm * rm;
     ekp = fma(qp, vzp, ekp);
     ekm = fma(qm, vzm, ekm);
-    ppm_line<CW>(win, l, 4, cw, qp, qm);
+    n = load5(win, l, 5);
+    sched_fence();
+    ppm_pts<CW>(c, 4, cw, qp, qm);
     ps.q[4] = qp;
     if (store) pp[4 * 64] = qp;
     if (both) pm[4 * 64] = qm;
     const double Ep = qp, Em = qm;
-    ppm_line<CW>(win, l, 5, cw, qp, qm);
+    if (XF >= 0) *xv = load5(win, l, XF);
+    sched_fence();
+    ppm_pts<CW>(n, 5, cw, qp, qm);
     ps.q[5] = qp;
     if (store) pp[5 * 64] = qp;
     if (both) pm[5 * 64] = qm;
@@ -893,12 +930,9 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                             produce_hydro<false, false, VEL, CW, true>(win, l, pp, pp, gamma, gm1,
                                                                        de, bits, cw);
                     } else if (nspec > 0) {
-#pragma unroll
-                        for (int f = 6; f < NF_MAX; f++) {
-                            double qp, qm;
-                            ppm_line<CW>(win, l, f, cw, qp, qm);
+                        ppm_fields<CW, 6, NF_MAX>(win, l, cw, [&](int f, double qp, double qm) {
                             pp[f * 64] = bottom ? qp : qm;
-                        }
+                        });
                     }
                 }
                 lds_barrier();
@@ -932,21 +966,23 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                         cw = cw_weights<VEL>(win, l, ldx(L), ldy(L), ldz(L), gamma, gm1, de, cwmode,
                                              HYD);
                     if (HYD) {
-                        produce_hydro<true, true, VEL, CW>(win, l, pp, pm, gamma, gm1, de, bits, cw);
-                        if (nspec > 0) {   // the last species field, to balance the pair
+                        // and the last species field, to balance the pair (its
+                        // values are loaded during the energy field; unused
+                        // without species)
+                        Pts5 xv;
+                        produce_hydro<true, true, VEL, CW, false, NF_MAX - 1>(
+                            win, l, pp, pm, gamma, gm1, de, bits, cw, &xv);
+                        if (nspec > 0) {
                             double qp, qm;
-                            ppm_line<CW>(win, l, NF_MAX - 1, cw, qp, qm);
+                            ppm_pts<CW>(xv, NF_MAX - 1, cw, qp, qm);
                             pp[(NF_MAX - 1) * 64] = qp;
                             pm[(NF_MAX - 1) * 64] = qm;
                         }
                     } else if (nspec > 0) {
-#pragma unroll
-                        for (int f = 6; f < NF_MAX - 1; f++) {
-                            double qp, qm;
-                            ppm_line<CW>(win, l, f, cw, qp, qm);
+                        ppm_fields<CW, 6, NF_MAX - 1>(win, l, cw, [&](int f, double qp, double qm) {
                             pp[f * 64] = qp;
                             pm[f * 64] = qm;
-                        }
+                        });
                     }
                 }
                 lds_barrier();
@@ -990,23 +1026,21 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                 if (CW && (HYD || nspec > 0))
                     cw = cw_weights<VEL>(win, l, dx, dy, t / 3 - 1, gamma, gm1, de, cwmode, HYD);
                 if (HYD) {
-                    const PlusState ps = produce_hydro<false, false, VEL, CW>(
-                        win, l, nullptr, nullptr, gamma, gm1, de, bits, cw);
+                    Pts5 xv;
+                    const PlusState ps = produce_hydro<false, false, VEL, CW, false, NF_MAX - 1>(
+                        win, l, nullptr, nullptr, gamma, gm1, de, bits, cw, &xv);
                     const double un = r_axis == 0 ? ps.vx : ps.vy;
                     acc_h_vals(acc[0], ps.q, un, ps.p, ps.cs, wt);
                     run[lane] = un;
                     if (nspec > 0) {
                         double qp, qm;
-                        ppm_line<CW>(win, l, NF_MAX - 1, cw, qp, qm);
+                        ppm_pts<CW>(xv, NF_MAX - 1, cw, qp, qm);
                         run[(NF_MAX - 1 - 5) * 64 + lane] = qp;
                     }
                 } else if (nspec > 0) {
-#pragma unroll
-                    for (int f = 6; f < NF_MAX - 1; f++) {
-                        double qp, qm;
-                        ppm_line<CW>(win, l, f, cw, qp, qm);
+                    ppm_fields<CW, 6, NF_MAX - 1>(win, l, cw, [&](int f, double qp, double) {
                         run[(f - 5) * 64 + lane] = qp;
-                    }
+                    });
                 }
                 lds_barrier();
                 if (!HYD) {
