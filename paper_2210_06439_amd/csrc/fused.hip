@@ -82,7 +82,7 @@ __device__ __host__ constexpr int line_of(int w, int r) {
 
 static_assert(line_of(2, 0) < 0, "the z-line producer must be idle in round 0 (see XF_OFF)");
 
-__device__ __forceinline__ int comp(int L, int axis) {
+__device__ __host__ constexpr int comp(int L, int axis) {
     return axis == 0 ? ldx(L) : axis == 1 ? ldy(L) : ldz(L);
 }
 
@@ -121,6 +121,38 @@ __device__ __forceinline__ double simpson_w(int t1, int t2) {
     const double w1a = t1 == 0 ? 4.0 / 6.0 : 1.0 / 6.0;
     const double w1b = t2 == 0 ? 4.0 / 6.0 : 1.0 / 6.0;
     return w1a * w1b;
+}
+
+// The same weights by code: 0 for none, else 1 + the number of zero offsets
+// (the products are formed as in simpson_w, so the bits agree).
+__device__ __forceinline__ double simpson_wc(int c) {
+    constexpr double e = 1.0 / 6.0, m = 4.0 / 6.0;
+    constexpr double w1 = e * e, w2 = m * e, w3 = m * m;
+    return c == 0 ? 0.0 : c == 1 ? w1 : c == 2 ? w2 : w3;
+}
+
+// What the owner of the axis-ax faces takes from the j-th line it consumes in
+// round r, in 5 bits: the exchange slot of the point on its cells' + side
+// (the producer's + or - slot, by the sign of the line's ax component; the
+// other side's point is in the slot next to it, slot ^ 1), and in bits 3-4
+// the Simpson weight code (0 for the repeated line of the last round).
+__device__ __host__ constexpr int cons_desc(int ax, int r, int j) {
+    const int p = cons_producer(ax, r, j);
+    const int Lp = line_of(p, r);
+    const int b1 = ax == 0 ? 1 : 0, b2 = ax == 2 ? 1 : 2;
+    const int slot = p * 2 + (comp(Lp, ax) > 0 ? 0 : 1);
+    const int wc = (r == 4 && j == 1) ? 0 : 1 + (comp(Lp, b1) == 0) + (comp(Lp, b2) == 0);
+    return slot | (wc << 3);
+}
+
+// The ten descriptors of axis ax, packed: the j-th line of round r at bit
+// 5 (2 r + j).  Uniform lookups with shifts keep the consumption straight-line
+// code, so all of a round's loads can be issued before the first sum.
+__device__ __host__ constexpr uint64_t cons_table(int ax) {
+    uint64_t t = 0;
+    for (int r = 0; r < 5; r++)
+        for (int j = 0; j < 2; j++) t |= (uint64_t)cons_desc(ax, r, j) << (5 * (2 * r + j));
+    return t;
 }
 
 // ---- PPM in branch-free form ---------------------------------------------
@@ -605,6 +637,44 @@ __device__ __forceinline__ void acc_h_lds(double (&c)[NH], const double *pt, int
     acc_h_vals(c, V, pt[(P_VX + ax) * 64], pt[P_P * 64], pt[P_CS * 64], w);
 }
 
+// a point's hydro values (and normal velocity, pressure and sound speed),
+// loaded ahead of their sums
+struct HPt {
+    double V[6], un, p, cs;
+};
+
+__device__ __forceinline__ HPt load_h(const double *pt, int ax) {
+    HPt h;
+#pragma unroll
+    for (int f = 0; f < 6; f++) h.V[f] = pt[f * 64];
+    h.un = pt[(P_VX + ax) * 64];
+    h.p = pt[P_P * 64];
+    h.cs = pt[P_CS * 64];
+    return h;
+}
+
+// a point's normal velocity and species values
+struct SPt {
+    double un, v[5];
+};
+
+__device__ __forceinline__ SPt load_s(const double *pt, int ax) {
+    SPt q;
+    q.un = pt[(P_VX + ax) * 64];
+#pragma unroll
+    for (int i = 0; i < 5; i++) q.v[i] = pt[(6 + i) * 64];
+    return q;
+}
+
+__device__ __forceinline__ void acc_s_pt(double (&c)[NH], const SPt &q, double w) {
+    const double wun = w * q.un;
+#pragma unroll
+    for (int i = 0; i < 5; i++) {
+        c[i] = fma(w, q.v[i], c[i]);
+        c[5 + i] = fma(wun, q.v[i], c[5 + i]);
+    }
+}
+
 // (always all 5 species slots: slots past the subgrid's species count hold
 // values that are never stored, so no per-field branch splits the loads)
 __device__ __forceinline__ void acc_s_lds(double (&c)[NH], const double *pt, int ax, double w) {
@@ -952,7 +1022,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
             }
         } else if (role < 3) {
             const int ax = role;
-            const int b1 = ax == 0 ? 1 : 0, b2 = ax == 2 ? 1 : 2;
+            const uint64_t ctab = ax == 0 ? cons_table(0) : ax == 1 ? cons_table(1) : cons_table(2);
 #pragma unroll 1
             for (int r = 0; r < 5; r++) {
                 LANE_GEOMETRY();
@@ -988,22 +1058,30 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                 lds_barrier();
                 // the two lines of the round that cross my faces (one in the
                 // last round: the second repeats the first with weight 0,
-                // which leaves the sums and the speed extrema unchanged)
-#pragma unroll
-                for (int j = 0; j < 2; j++) {
-                    const int p = cons_producer(ax, r, j);
-                    const int Lp = line_of(p, r);
-                    const int dA = comp(Lp, ax);
-                    const double wt = (r == 4 && j == 1) ? 0.0
-                                                         : simpson_w(comp(Lp, b1), comp(Lp, b2));
-                    const double *pa = xch + (p * 2 + (dA > 0 ? 0 : 1)) * PT * 64 + lane;
-                    const double *pb = xch + (p * 2 + (dA > 0 ? 1 : 0)) * PT * 64 + lane;
+                // which leaves the sums and the speed extrema unchanged).
+                // All four points are loaded before the first sum.
+                {
+                    const int d0 = (int)(ctab >> (10 * r)) & 31;
+                    const int d1 = (int)(ctab >> (10 * r + 5)) & 31;
+                    const double w0 = simpson_wc(d0 >> 3), w1 = simpson_wc(d1 >> 3);
+                    const double *a0 = xch + (d0 & 7) * PT * 64 + lane;
+                    const double *b0 = xch + ((d0 & 7) ^ 1) * PT * 64 + lane;
+                    const double *a1 = xch + (d1 & 7) * PT * 64 + lane;
+                    const double *b1 = xch + ((d1 & 7) ^ 1) * PT * 64 + lane;
                     if (HYD) {
-                        acc_h_lds(acc[0], pa, ax, wt);
-                        acc_h_lds(acc[1], pb, ax, wt);
+                        const HPt pa0 = load_h(a0, ax), pb0 = load_h(b0, ax);
+                        const HPt pa1 = load_h(a1, ax), pb1 = load_h(b1, ax);
+                        acc_h_vals(acc[0], pa0.V, pa0.un, pa0.p, pa0.cs, w0);
+                        acc_h_vals(acc[1], pb0.V, pb0.un, pb0.p, pb0.cs, w0);
+                        acc_h_vals(acc[0], pa1.V, pa1.un, pa1.p, pa1.cs, w1);
+                        acc_h_vals(acc[1], pb1.V, pb1.un, pb1.p, pb1.cs, w1);
                     } else {
-                        acc_s_lds(acc[0], pa, ax, wt);
-                        acc_s_lds(acc[1], pb, ax, wt);
+                        const SPt pa0 = load_s(a0, ax), pb0 = load_s(b0, ax);
+                        const SPt pa1 = load_s(a1, ax), pb1 = load_s(b1, ax);
+                        acc_s_pt(acc[0], pa0, w0);
+                        acc_s_pt(acc[1], pb0, w0);
+                        acc_s_pt(acc[0], pa1, w1);
+                        acc_s_pt(acc[1], pb1, w1);
                     }
                 }
                 lds_barrier();
