@@ -116,6 +116,14 @@ __host__ constexpr bool zlines_ok() {
 }
 static_assert(zlines_ok(), "the nine z-crossing lines, each once");
 
+// Simpson weight codes of the nine z lines (see simpson_wc), two bits each.
+__device__ __host__ constexpr uint32_t zline_wcodes() {
+    uint32_t t = 0;
+    for (int u = 0; u < 9; u++)
+        t |= (uint32_t)(1 + (ldx(zline(u)) == 0) + (ldy(zline(u)) == 0)) << (2 * u);
+    return t;
+}
+
 // Simpson weight of a surface point from its two tangential offsets.
 __device__ __forceinline__ double simpson_w(int t1, int t2) {
     const double w1a = t1 == 0 ? 4.0 / 6.0 : 1.0 / 6.0;
@@ -629,14 +637,6 @@ __device__ __forceinline__ void acc_h_vals(double (&c)[NH], const double *V, dou
     c[H_LM] = fmin(c[H_LM], un - cs);
 }
 
-// point in LDS at pt (component stride 64), normal axis ax
-__device__ __forceinline__ void acc_h_lds(double (&c)[NH], const double *pt, int ax, double w) {
-    double V[6];
-#pragma unroll
-    for (int f = 0; f < 6; f++) V[f] = pt[f * 64];
-    acc_h_vals(c, V, pt[(P_VX + ax) * 64], pt[P_P * 64], pt[P_CS * 64], w);
-}
-
 // a point's hydro values (and normal velocity, pressure and sound speed),
 // loaded ahead of their sums
 struct HPt {
@@ -653,7 +653,9 @@ __device__ __forceinline__ HPt load_h(const double *pt, int ax) {
     return h;
 }
 
-// a point's normal velocity and species values
+// a point's normal velocity and species values (always all 5 species slots:
+// slots past the subgrid's species count hold values that are never stored,
+// so no per-field branch splits the loads)
 struct SPt {
     double un, v[5];
 };
@@ -672,18 +674,6 @@ __device__ __forceinline__ void acc_s_pt(double (&c)[NH], const SPt &q, double w
     for (int i = 0; i < 5; i++) {
         c[i] = fma(w, q.v[i], c[i]);
         c[5 + i] = fma(wun, q.v[i], c[5 + i]);
-    }
-}
-
-// (always all 5 species slots: slots past the subgrid's species count hold
-// values that are never stored, so no per-field branch splits the loads)
-__device__ __forceinline__ void acc_s_lds(double (&c)[NH], const double *pt, int ax, double w) {
-    const double wun = w * pt[(P_VX + ax) * 64];
-#pragma unroll
-    for (int i = 0; i < 5; i++) {
-        const double v = pt[(6 + i) * 64];
-        c[i] = fma(w, v, c[i]);
-        c[5 + i] = fma(wun, v, c[5 + i]);
     }
 }
 
@@ -1007,14 +997,28 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                 }
                 lds_barrier();
                 if (role == 2) {
+                    // the round's points, all loaded before the first sum (the
+                    // slots of idle producers hold older points, never summed)
+                    constexpr uint32_t zw = zline_wcodes();
+                    if (HYD) {
+                        HPt q[4];
 #pragma unroll
-                    for (int w = 0; w < 4; w++) {
-                        const int t2 = w + 4 * r;
-                        if (t2 < 9) {
-                            const double wt = simpson_w(ldx(zline(t2)), ldy(zline(t2)));
-                            const double *pt = xch + w * PT * 64 + lane;
-                            if (HYD) acc_h_lds(acc[0], pt, 2, wt);
-                            else acc_s_lds(acc[0], pt, 2, wt);
+                        for (int w = 0; w < 4; w++) q[w] = load_h(xch + w * PT * 64 + lane, 2);
+#pragma unroll
+                        for (int w = 0; w < 4; w++) {
+                            const int t2 = w + 4 * r;
+                            if (t2 < 9)
+                                acc_h_vals(acc[0], q[w].V, q[w].un, q[w].p, q[w].cs,
+                                           simpson_wc((zw >> (2 * t2)) & 3));
+                        }
+                    } else {
+                        SPt q[4];
+#pragma unroll
+                        for (int w = 0; w < 4; w++) q[w] = load_s(xch + w * PT * 64 + lane, 2);
+#pragma unroll
+                        for (int w = 0; w < 4; w++) {
+                            const int t2 = w + 4 * r;
+                            if (t2 < 9) acc_s_pt(acc[0], q[w], simpson_wc((zw >> (2 * t2)) & 3));
                         }
                     }
                 }
