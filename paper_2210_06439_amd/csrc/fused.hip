@@ -684,13 +684,16 @@ __device__ __forceinline__ void store_h(double *base, int st, const double (&c)[
     for (int i = 0; i < NH; i++) base[i * st] = c[i];
 }
 
-__device__ __forceinline__ void store_s(double *base, int st, const double (&c)[NH], int ns) {
+// All five species slots, whatever the subgrid's species count: LDS work on
+// species is never split by a branch on that count (each branch would end
+// a run of loads and leave their latency exposed); the slots past the count
+// carry values that no output takes.
+__device__ __forceinline__ void store_s(double *base, int st, const double (&c)[NH]) {
 #pragma unroll
-    for (int i = 0; i < 5; i++)
-        if (i < ns) {
-            base[(NH + i) * st] = c[i];
-            base[(NH + 5 + i) * st] = c[5 + i];
-        }
+    for (int i = 0; i < 5; i++) {
+        base[(NH + i) * st] = c[i];
+        base[(NH + 5 + i) * st] = c[5 + i];
+    }
 }
 
 struct Speeds {
@@ -741,19 +744,19 @@ __device__ __forceinline__ Speeds combine_h(const double (&m)[NH], const double 
     return s;
 }
 
-// Species fluxes of a face, speeds given; the other side's species partial at o.
+// Species fluxes of a face, speeds given; the other side's species partial at o
+// (all five slots, see store_s).
 __device__ __forceinline__ void combine_s(const double (&m)[NH], const double *o, int st,
-                                          bool mine_left, const Speeds &s, int ns, double *Fb) {
+                                          bool mine_left, const Speeds &s, double *Fb) {
     const double cm = mine_left ? s.ap : -s.am;
     const double co = mine_left ? -s.am : s.ap;
     const double sg = mine_left ? 1.0 : -1.0;
 #pragma unroll
-    for (int i = 0; i < 5; i++)
-        if (i < ns) {
-            const double sfm = m[5 + i], sfo = o[(NH + 5 + i) * st];
-            const double dv = sg * (o[(NH + i) * st] - m[i]);
-            Fb[6 + i] = fma(cm, sfm, co * sfo) * s.inv + (s.apam * dv) * s.inv;
-        }
+    for (int i = 0; i < 5; i++) {
+        const double sfm = m[5 + i], sfo = o[(NH + 5 + i) * st];
+        const double dv = sg * (o[(NH + i) * st] - m[i]);
+        Fb[6 + i] = fma(cm, sfm, co * sfo) * s.inv + (s.apam * dv) * s.inv;
+    }
 }
 
 // Update of one interior cell of plane `kc` from its z flux Fz and the kept
@@ -768,6 +771,9 @@ struct Stage {
 
 // chk collects 0 * v over the outputs: it stays 0 unless some v is not finite.
 // With VEL the momenta are read from the input (the window holds velocities).
+// The LDS reads and the arithmetic run over the field group's whole range
+// ([0, 6) or [6, 11), fixed at compile time once f0 is), so they form one
+// run of loads; only global memory is limited to the subgrid's fields.
 template <bool VEL>
 __device__ __forceinline__ void update_cell(const double *win, const double *keep, int lane,
                                             int kc, int ci, int cj, int f0, int f1,
@@ -776,15 +782,22 @@ __device__ __forceinline__ void update_cell(const double *win, const double *kee
                                             int fst, double &chk) {
     const int cidx = opaque_v(kc * NPLANE + cj * NB + ci);
     const int fs = opaque_s(fst);
+    const int f1x = f0 == 0 ? 6 : NF_MAX;
+    double vv[NF_MAX];
 #pragma unroll
     for (int f = 0; f < NF_MAX; f++)
-        if (f >= f0 && f < f1) {
+        if (f >= f0 && f < f1x) {
             const double dfz = Fz[f] - keep[f * 64 + lane];
             const double sxy = keep[(NF_MAX + f) * 64 + lane];
             const double u = (VEL && f >= 1 && f <= 3)
                                  ? Us[f * fs + cidx]
                                  : win[(kc % SLOTS) * SLOT_D + f * NPLANE + cj * NB + ci];
-            double v = (rate ? 0.0 : u) - lam * (sxy + dfz);
+            vv[f] = (rate ? 0.0 : u) - lam * (sxy + dfz);
+        }
+#pragma unroll
+    for (int f = 0; f < NF_MAX; f++)
+        if (f >= f0 && f < f1x && f < f1) {
+            double v = vv[f];
             if (stg.U0) {
                 const double u0 = stg.U0[f * fs + cidx];
                 v = stg.identity ? u0 : fma(stg.c0, u0, stg.c1 * v);
@@ -806,13 +819,20 @@ __device__ __forceinline__ void update_cell_sum(const double *win, int kc, int c
                                                 double *Os, int fst, double &chk) {
     const int cidx = opaque_v(kc * NPLANE + cj * NB + ci);
     const int fs = opaque_s(fst);
+    const int f1x = f0 == 0 ? 6 : NF_MAX;
+    double vv[NF_MAX];
 #pragma unroll
     for (int f = 0; f < NF_MAX; f++)
-        if (f >= f0 && f < f1) {
+        if (f >= f0 && f < f1x) {
             const double u = (VEL && f >= 1 && f <= 3)
                                  ? Us[f * fs + cidx]
                                  : win[(kc % SLOTS) * SLOT_D + f * NPLANE + cj * NB + ci];
-            double v = (rate ? 0.0 : u) - lam * dsum[f];
+            vv[f] = (rate ? 0.0 : u) - lam * dsum[f];
+        }
+#pragma unroll
+    for (int f = 0; f < NF_MAX; f++)
+        if (f >= f0 && f < f1x && f < f1) {
+            double v = vv[f];
             if (stg.U0) {
                 const double u0 = stg.U0[f * fs + cidx];
                 v = stg.identity ? u0 : fma(stg.c0, u0, stg.c1 * v);
@@ -837,6 +857,8 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
     const int nf = 6 + nspec;
     double chk = 0.0;
     const int f0 = HYD ? 0 : 6, f1 = HYD ? 6 : nf;     // this wave's fields
+    constexpr int f1x = HYD ? 6 : NF_MAX;              // ... and its LDS range (see store_s)
+    const bool work = HYD || nspec > 0;                 // a species wave without species idles
     // this thread's share of a plane: up to 5 of the nf*196 values.  Lanes
     // without an element load a valid address and store into the slot's
     // dummy word, so the loads carry no branches and issue back to back.
@@ -1167,9 +1189,9 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
         if (layer) {
             LANE_GEOMETRY();
             if (k == kb) {
-                if (role == 2) {
+                if (role == 2 && work) {
                     if (HYD) store_h(zl + lane, 64, acc[0]);
-                    else store_s(zl + lane, 64, acc[0], nspec);
+                    else store_s(zl + lane, 64, acc[0]);
                 }
             } else {
                 // face (ke-1|ke): left partial from step ke-1, right = acc[0]; the
@@ -1179,7 +1201,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                     xch[ZB_OFF + 3 * 64 + lane] = acc[0][H_LM];
                 }
                 lds_barrier();
-                if (role == 2) {
+                if (role == 2 && work) {
                     double Fz[NF_MAX];
                     if (HYD) {
                         const Speeds sp = combine_h(acc[0], zl + lane, 64, false, 2, sym, Fz);
@@ -1188,7 +1210,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                         const Speeds sp = face_speeds(zl[H_LP * 64 + lane], zl[H_LM * 64 + lane],
                                                       xch[ZB_OFF + 2 * 64 + lane],
                                                       xch[ZB_OFF + 3 * 64 + lane], sym);
-                        combine_s(acc[0], zl + lane, 64, false, sp, nspec, Fz);
+                        combine_s(acc[0], zl + lane, 64, false, sp, Fz);
                     }
                     update_cell<VEL>(win, keep, lane, ke - 1, ci, cj, f0, f1, Fz, lam, rate,
                                      stg, Us, Os, fst, chk);
@@ -1200,7 +1222,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
         // ---- face fluxes of plane k and the update of plane k-1
         {
         LANE_GEOMETRY();
-        if (role == 3) {
+        if (role == 3 && work) {
             // the two lanes of a ring cell hold partial sums: add them
 #pragma unroll
             for (int i = 0; i < NH; i++) {
@@ -1211,16 +1233,16 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
             }
         }
         // phase 1: right-side partials and left-side speeds -> LDS
-        if (role == 0 || role == 1) {
+        if ((role == 0 || role == 1) && work) {
             double *R = xch + XR_OFF + (role == 0 ? (0 * 8 + (cj - 3)) * 9 + (ci - 3)
                                                   : (1 * 8 + (ci - 3)) * 9 + (cj - 3));
             if (HYD) store_h(R, RST, acc[1]);
-            else store_s(R, RST, acc[1], nspec);
+            else store_s(R, RST, acc[1]);
         }
-        if (role == 3 && half == 0 && r_side == 1) {
+        if (role == 3 && half == 0 && r_side == 1 && work) {
             double *R = xch + XR_OFF + (r_axis * 8 + (r_pos - 3)) * 9 + 8;
             if (HYD) store_h(R, RST, acc[0]);
-            else store_s(R, RST, acc[0], nspec);
+            else store_s(R, RST, acc[0]);
         }
         if (HYD) {
             int ll = -1;
@@ -1240,7 +1262,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
         }
         lds_barrier();
         // phase 2: left owners form the x/y face fluxes; z owners the z face
-        if (role < 2 || (role == 3 && half == 0 && r_side == 0)) {
+        if (work && (role < 2 || (role == 3 && half == 0 && r_side == 0))) {
             const int ax = role < 2 ? role : r_axis;
             const int row = role == 0 ? cj - 3 : role == 1 ? ci - 3 : r_pos - 3;
             const int p = role == 0 ? ci - 2 : role == 1 ? cj - 2 : 0;
@@ -1253,13 +1275,13 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
             } else {
                 const Speeds sp = face_speeds(xch[LL_OFF + fi], xch[LL_OFF + RST + fi],
                                               R[H_LP * RST], R[H_LM * RST], sym);
-                combine_s(acc[0], R, RST, true, sp, nspec, Fb);
+                combine_s(acc[0], R, RST, true, sp, Fb);
             }
 #pragma unroll
             for (int f = 0; f < NF_MAX; f++)
-                if (f >= f0 && f < f1) Fo[f * RST] = Fb[f];
+                if (f >= f0 && f < f1x) Fo[f * RST] = Fb[f];
         }
-        if (role == 2) {
+        if (role == 2 && work) {
             // z-face (k-1|k): left partial from the previous step, right = acc[1]
             double Fz[NF_MAX];
             if (HYD) {
@@ -1269,18 +1291,18 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                 const Speeds sp = face_speeds(xch[ZB_OFF + lane], xch[ZB_OFF + 64 + lane],
                                               xch[ZB_OFF + 128 + lane], xch[ZB_OFF + 192 + lane],
                                               sym);
-                combine_s(acc[1], zl + lane, 64, false, sp, nspec, Fz);
+                combine_s(acc[1], zl + lane, 64, false, sp, Fz);
             }
             // plane k-1's summed flux differences (its cells are written after
             // the barrier, where the x owner overwrites the kept x/y part)
 #pragma unroll
             for (int f = 0; f < NF_MAX; f++)
-                if (f >= f0 && f < f1) {
+                if (f >= f0 && f < f1x) {
                     dsum[f] = keep[(NF_MAX + f) * 64 + lane] + (Fz[f] - keep[f * 64 + lane]);
                     keep[f * 64 + lane] = Fz[f];
                 }
             if (HYD) store_h(zl + lane, 64, acc[0]);
-            else store_s(zl + lane, 64, acc[0], nspec);
+            else store_s(zl + lane, 64, acc[0]);
         }
         lds_barrier();
         // phase 3: the x owner forms its cells' x/y flux difference,
@@ -1290,15 +1312,15 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
         // and the z-line producer (which writes above it) first produces in
         // the second round, after the first round's barriers, so no barrier
         // is needed here.
-        if (role == 2 && k >= kb + 2)
+        if (role == 2 && k >= kb + 2 && work)
             update_cell_sum<VEL>(win, k - 1, ci, cj, f0, f1, dsum, lam, rate, stg, Us, Os, fst,
                                  chk);
-        if (role == 0) {
+        if (role == 0 && work) {
             const double *Fl = xch + XF_OFF + (cj - 3) * 9 + (ci - 3);     // left x face
             const double *Fy = xch + XF_OFF + (8 + (ci - 3)) * 9 + (cj - 3); // y face below
 #pragma unroll
             for (int f = 0; f < NF_MAX; f++)
-                if (f >= f0 && f < f1)
+                if (f >= f0 && f < f1x)
                     keep[(NF_MAX + f) * 64 + lane] =
                         (Fb[f] - Fl[f * RST]) + (Fy[f * RST + 1] - Fy[f * RST]);
         }
