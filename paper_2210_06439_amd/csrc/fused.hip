@@ -184,21 +184,24 @@ __device__ __forceinline__ double mc_slope2(double dm, double dp) {
 // |b| <= 2|a| and |a| <= 2|b|), which needs no division and no branches.
 __device__ __forceinline__ void ppm_fast(double um2, double um1, double u0, double up1,
                                          double up2, double &qp, double &qm) {
-    // with the slopes doubled, (s0 - s+) / 6 is (S0 - S+) / 12: the same bits
-    const double twelfth = 1.0 / 12.0;
+    // Twice the offsets: with the slopes doubled, 2 (q+ - u0) = d+ + (S0 - S+)/6
+    // and 2 (u0 - q-) = d- + (S0 - S-)/6, each one rounding of an exact
+    // multiple of the undoubled value, so every quantity below is an exact
+    // power-of-two multiple of the undoubled form's and q+, q- are the same
+    // bits (for differences above the subnormal range, where halving rounds).
+    const double sixth = 1.0 / 6.0;
     double d0 = um1 - um2, d1 = u0 - um1, d2 = up1 - u0, d3 = up2 - up1;
     double sm = mc_slope2(d0, d1);
     double s0 = mc_slope2(d1, d2);
     double sp = mc_slope2(d2, d3);
-    double a = fma(s0 - sp, twelfth, 0.5 * d2);  // q+ - u0
-    double b = fma(s0 - sm, twelfth, 0.5 * d1);  // u0 - q-
-    double sg = copysign(1.0, a);
-    double aa = fabs(a);
-    double sb = b * sg;                          // |b| if b has a's sign, else < 0
-    double bn = fmax(fmin(sb, aa + aa), 0.0);
-    double an = fmax(fmin(aa, sb + sb), 0.0);
-    qp = fma(an, sg, u0);
-    qm = fma(-bn, sg, u0);
+    const double A = fma(s0 - sp, sixth, d2);   // 2 (q+ - u0)
+    const double B = fma(s0 - sm, sixth, d1);   // 2 (u0 - q-)
+    const double h = copysign(0.5, A);          // sign of a, halved
+    const double sb = B * h;                    // |b| if b has a's sign, else < 0
+    const double bn = fmax(fmin(sb, fabs(A)), 0.0);           // min(|b|, 2|a|), or 0
+    const double An = fmax(fmin(fabs(A), 4.0 * sb), 0.0);     // 2 min(|a|, 2|b|), or 0
+    qp = fma(An, h, u0);
+    qm = fma(bn, -(h + h), u0);
 }
 
 // ppm_fast with the Colella-Woodward weights applied to the interface offsets
@@ -266,6 +269,15 @@ __device__ __forceinline__ double tau_pow(double x, double gamma) {
         return x * (x * y);
     }
     return pow(x, gamma);
+}
+
+// The value of lane ^ 1 (the other lane of a pair), by a DPP quad
+// permutation [1, 0, 3, 2] of both halves: no LDS round trip.
+__device__ __forceinline__ double pair_swap(double x) {
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), 0xB1, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
 // Workgroup barrier for LDS traffic only: waits for this wave's LDS accesses,
@@ -1226,7 +1238,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
             // the two lanes of a ring cell hold partial sums: add them
 #pragma unroll
             for (int i = 0; i < NH; i++) {
-                const double o = __shfl_xor(acc[0][i], 1);
+                const double o = pair_swap(acc[0][i]);
                 if (HYD && i == H_LP) acc[0][i] = fmax(acc[0][i], o);
                 else if (HYD && i == H_LM) acc[0][i] = fmin(acc[0][i], o);
                 else acc[0][i] += o;
