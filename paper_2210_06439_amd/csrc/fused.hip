@@ -242,6 +242,25 @@ __device__ __forceinline__ double recip(double x) {
     return fma(r, e, r);
 }
 
+// Square root for the sound speed: Goldschmidt's iteration from the hardware
+// reciprocal-square-root estimate (root g and half-reciprocal h refined
+// together), then two Newton corrections of the root, g += (x - g^2) h.  This
+// is the arithmetic of the device library's sqrt without its rescaling of
+// arguments below 2^-767 (a squared sound speed is never that small); zero
+// and infinity pass through, negative and NaN arguments give NaN.
+__device__ __forceinline__ double sqrt_cs(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-h, g, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    d = fma(-g, g, x);
+    g = fma(d, h, g);
+    return (x == 0.0 || x == INFINITY) ? x : g;
+}
+
 // tau^gamma for the dual-energy branch.  For the paper's gas, gamma = 5/3,
 // tau^(5/3) = tau * (tau * tau^(-1/3)) with y = tau^(-1/3) from Newton's
 // iteration for the inverse cube root, y <- y (4 - x y^3) / 3 (quadratic
@@ -592,7 +611,7 @@ __device__ __forceinline__ PlusState produce_hydro(const double *win, const Line
         double eip = fma(-0.5, ekp, Ep);
         if (eip < de * Ep) eip = tau_pow(qp, gamma);      // dual energy: tau^gamma
         prp = gm1 * eip;
-        csp = sqrt((gamma * prp) * rp);
+        csp = sqrt_cs((gamma * prp) * rp);
         if (store) {
             pp[P_VX * 64] = vxp;
             pp[(P_VX + 1) * 64] = vyp;
@@ -611,7 +630,7 @@ __device__ __forceinline__ PlusState produce_hydro(const double *win, const Line
         pm[(P_VX + 1) * 64] = vym;
         pm[(P_VX + 2) * 64] = vzm;
         pm[P_P * 64] = prm;
-        pm[P_CS * 64] = sqrt((gamma * prm) * rm);
+        pm[P_CS * 64] = sqrt_cs((gamma * prm) * rm);
         bits |= (__ballot(rhom <= 0.0) ? HYDRO_STATUS_RHO : 0) |
                 (__ballot(prm <= 0.0) ? HYDRO_STATUS_P : 0);
     }
