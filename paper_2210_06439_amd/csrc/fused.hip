@@ -116,6 +116,28 @@ __host__ constexpr bool zlines_ok() {
 }
 static_assert(zlines_ok(), "the nine z-crossing lines, each once");
 
+// Line directions in 6 bits: dx + 1, dy + 1, dz + 1, two bits each.
+__device__ __host__ constexpr int dir_code(int L) {
+    return (ldx(L) + 1) | ((ldy(L) + 1) << 2) | ((ldz(L) + 1) << 4);
+}
+
+// The lines of role w (0-2) over the 5 rounds, 7 bits a round (bit 6: a line
+// is produced; bits 0-5 its direction code), and the nine z lines of the face
+// layers in the order zline, 6 bits each: uniform lookups by shifts, where the
+// definitions above compile into chains of scalar branches.
+__device__ __host__ constexpr uint64_t prod_table(int w) {
+    uint64_t t = 0;
+    for (int r = 0; r < 5; r++)
+        if (line_of(w, r) >= 0) t |= (uint64_t)(64 | dir_code(line_of(w, r))) << (7 * r);
+    return t;
+}
+
+__device__ __host__ constexpr uint64_t zline_dirs() {
+    uint64_t t = 0;
+    for (int u = 0; u < 9; u++) t |= (uint64_t)dir_code(zline(u)) << (6 * u);
+    return t;
+}
+
 // Simpson weight codes of the nine z lines (see simpson_wc), two bits each.
 __device__ __host__ constexpr uint32_t zline_wcodes() {
     uint32_t t = 0;
@@ -1029,12 +1051,12 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
                 if (t < 9) {
                     // the t-th z line through the cell: its + end lies on the
                     // cell's top face, its - end on the bottom face
-                    const int L = zline(t);
-                    const Line5 l = line5(ci, cj, k, ldx(L), ldy(L), ldz(L));
+                    const int dc = (int)(zline_dirs() >> (6 * t)) & 63;
+                    const int dx = (dc & 3) - 1, dy = ((dc >> 2) & 3) - 1, dz = (dc >> 4) - 1;
+                    const Line5 l = line5(ci, cj, k, dx, dy, dz);
                     CwW cw = {0.0, 0.0};
                     if (CW && (HYD || nspec > 0))
-                        cw = cw_weights<VEL>(win, l, ldx(L), ldy(L), ldz(L), gamma, gm1, de, cwmode,
-                                             HYD);
+                        cw = cw_weights<VEL>(win, l, dx, dy, dz, gamma, gm1, de, cwmode, HYD);
                     if (HYD) {
                         if (bottom)
                             produce_hydro<true, false, VEL, CW>(win, l, pp, pp, gamma, gm1, de,
@@ -1080,18 +1102,19 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
         } else if (role < 3) {
             const int ax = role;
             const uint64_t ctab = ax == 0 ? cons_table(0) : ax == 1 ? cons_table(1) : cons_table(2);
+            const uint64_t ptab = ax == 0 ? prod_table(0) : ax == 1 ? prod_table(1) : prod_table(2);
 #pragma unroll 1
             for (int r = 0; r < 5; r++) {
                 LANE_GEOMETRY();
-                const int L = line_of(role, r);
+                const int pd = (int)(ptab >> (7 * r)) & 127;
                 double *pp = xch + (role * 2 + 0) * PT * 64 + lane;
                 double *pm = xch + (role * 2 + 1) * PT * 64 + lane;
-                if (L >= 0) {
-                    const Line5 l = line5(ci, cj, k, ldx(L), ldy(L), ldz(L));
+                if (pd & 64) {
+                    const int dx = (pd & 3) - 1, dy = ((pd >> 2) & 3) - 1, dz = ((pd >> 4) & 3) - 1;
+                    const Line5 l = line5(ci, cj, k, dx, dy, dz);
                     CwW cw = {0.0, 0.0};
                     if (CW && (HYD || nspec > 0))
-                        cw = cw_weights<VEL>(win, l, ldx(L), ldy(L), ldz(L), gamma, gm1, de, cwmode,
-                                             HYD);
+                        cw = cw_weights<VEL>(win, l, dx, dy, dz, gamma, gm1, de, cwmode, HYD);
                     if (HYD) {
                         // and the last species field, to balance the pair (its
                         // values are loaded during the energy field; unused
