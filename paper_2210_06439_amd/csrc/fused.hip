@@ -138,6 +138,26 @@ __device__ __host__ constexpr uint64_t zline_dirs() {
     return t;
 }
 
+__host__ constexpr bool tables_ok() {
+    for (int w = 0; w < 3; w++)
+        for (int r = 0; r < 5; r++) {
+            const int pd = (int)(prod_table(w) >> (7 * r)) & 127;
+            const int L = line_of(w, r);
+            if ((L >= 0) != ((pd & 64) != 0)) return false;
+            if (L >= 0 && ((pd & 3) - 1 != ldx(L) || ((pd >> 2) & 3) - 1 != ldy(L) ||
+                           ((pd >> 4) & 3) - 1 != ldz(L)))
+                return false;
+        }
+    for (int u = 0; u < 9; u++) {
+        const int dc = (int)(zline_dirs() >> (6 * u)) & 63;
+        if ((dc & 3) - 1 != ldx(zline(u)) || ((dc >> 2) & 3) - 1 != ldy(zline(u)) ||
+            (dc >> 4) - 1 != ldz(zline(u)))
+            return false;
+    }
+    return true;
+}
+static_assert(tables_ok(), "packed line tables decode to the schedule");
+
 // Simpson weight codes of the nine z lines (see simpson_wc), two bits each.
 __device__ __host__ constexpr uint32_t zline_wcodes() {
     uint32_t t = 0;
@@ -184,6 +204,21 @@ __device__ __host__ constexpr uint64_t cons_table(int ax) {
         for (int j = 0; j < 2; j++) t |= (uint64_t)cons_desc(ax, r, j) << (5 * (2 * r + j));
     return t;
 }
+
+// Each entry of the consumption tables names a slot of a line that crosses
+// the owner's faces and was produced in that round, on the owner's + side.
+__host__ constexpr bool cons_tables_ok() {
+    for (int ax = 0; ax < 3; ax++)
+        for (int r = 0; r < 5; r++)
+            for (int j = 0; j < 2; j++) {
+                const int d = (int)(cons_table(ax) >> (5 * (2 * r + j))) & 31;
+                const int p = (d & 7) >> 1, L = line_of(p, r);
+                if (L < 0 || comp(L, ax) == 0 || (comp(L, ax) > 0) != ((d & 1) == 0)) return false;
+                if ((d >> 3) == 0 && !(r == 4 && j == 1)) return false;
+            }
+    return true;
+}
+static_assert(cons_tables_ok(), "consumption tables");
 
 // ---- PPM in branch-free form ---------------------------------------------
 
