@@ -171,7 +171,7 @@ int stream_scratch(void *stream, int n_sub, uint32_t **out) {
 // to a kernel (on the host it only names the symbol): its device address is
 // looked up once per device and kept in g_noalloc.
 
-constexpr int64_t kNoallocBytes = 64 + 16 * (int64_t)HYDRO_NOALLOC_MAX_SUB;
+constexpr int64_t kNoallocBytes = fused_scratch_bytes_for(HYDRO_NOALLOC_MAX_SUB);
 static __device__ __align__(256) uint32_t scratch[kNoallocBytes / 4];
 
 std::mutex g_noalloc_mu;
@@ -202,10 +202,10 @@ __global__ void k_clear_words(uint32_t *p, int64_t n) {
 }
 
 // Launch the fused step in `variant`, attaching the stream's scratch when
-// that launch shape needs it.
+// the step needs it.
 int launch_step(StepArgs a, const double *U_in, double *U_out, double *amax, int32_t *status,
                 int variant, void *stream) {
-    if (fused_variant_needs_scratch(variant) && !a.scratch) {
+    if (fused_needs_scratch(a, variant) && !a.scratch) {
         int rc = stream_scratch(stream, a.n_sub, &a.scratch);
         if (rc) return rc;
     }
@@ -218,25 +218,57 @@ int launch_step(StepArgs a, const double *U_in, double *U_out, double *amax, int
 
 struct hydro_plan {
     StepArgs args;
-    FusedArgs fargs;     // the kernel node's argument block
     const double *U_in;
     double *U_out;
     double *amax;
     int32_t *status;
-    int order;
-    void *kargs[6];
+    int variant;
     hipGraph_t graph;
-    hipGraphNode_t node;
     hipGraphExec_t exec;
-    hipKernelNodeParams np;
-    uint32_t *scratch;   // owned (split and dynamic launch shapes)
+    uint32_t *scratch;   // owned
 };
 
 struct hydro_rk3 {
     hipGraph_t graph;
     hipGraphExec_t exec;
-    uint32_t *scratch;   // owned (split and dynamic launch shapes)
+    uint32_t *scratch;   // owned
 };
+
+namespace {
+
+// Record the plan's step (the fused kernels of its launch shape) into a graph
+// and make it the plan's: a new executable graph, or an update of the one the
+// plan has (whose launches may still be in flight).
+hipError_t plan_build(hydro_plan *p) {
+    hipStream_t cs;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    hipGraph_t g = nullptr;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t e1 = launch_fused_step(p->args, p->U_in, p->U_out, p->amax, p->status,
+                                          p->variant, cs);
+        e = hipStreamEndCapture(cs, &g);
+        if (e1 != hipSuccess) e = e1;
+    }
+    hipStreamDestroy(cs);
+    if (e == hipSuccess && p->exec) {
+        hipGraphNode_t bad = nullptr;
+        hipGraphExecUpdateResult res;
+        e = hipGraphExecUpdate(p->exec, g, &bad, &res);
+    } else if (e == hipSuccess) {
+        e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+    }
+    if (e != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return e;
+    }
+    if (p->graph) hipGraphDestroy(p->graph);
+    p->graph = g;
+    return hipSuccess;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -350,7 +382,7 @@ int hydro_step_noalloc(const hydro_params *params, const hydro_batch *batch,
     if ((rc = check_device())) return rc;
     const int variant = hydro_selected_variant(batch->n_sub, 5);
     StepArgs a = make_args(params, batch);
-    if (fused_variant_needs_scratch(variant)) {
+    if (fused_needs_scratch(a, variant)) {
         if ((rc = noalloc_scratch(&a.scratch))) return rc;
         // the words this launch uses start at zero, whatever an earlier call
         // left behind
@@ -458,10 +490,9 @@ int hydro_plan_create(const hydro_params *params, const hydro_batch *batch, cons
     p->U_out = U_out;
     p->amax = amax;
     p->status = status;
-    int variant = hydro_selected_variant(batch->n_sub, 5);
-    p->order = fused_variant_order(variant);
-    apply_variant(p->args, variant);
-    if (fused_variant_needs_scratch(variant)) {
+    p->variant = hydro_selected_variant(batch->n_sub, 5);
+    apply_variant(p->args, p->variant);
+    if (fused_needs_scratch(p->args, p->variant)) {
         rc = alloc_scratch(fused_scratch_bytes(batch->n_sub), &p->scratch);
         if (rc) {
             delete p;
@@ -469,17 +500,7 @@ int hydro_plan_create(const hydro_params *params, const hydro_batch *batch, cons
         }
         p->args.scratch = p->scratch;
     }
-    p->fargs = fused_args(p->args);
-    p->kargs[0] = &p->fargs;
-    p->kargs[1] = &p->U_in;
-    p->kargs[2] = &p->U_out;
-    p->kargs[3] = &p->amax;
-    p->kargs[4] = &p->status;
-    p->kargs[5] = &p->order;
-    fused_kernel_node_params(p->args, U_in, U_out, amax, status, variant, &p->np, p->kargs);
-    hipError_t e = hipGraphCreate(&p->graph, 0);
-    if (e == hipSuccess) e = hipGraphAddKernelNode(&p->node, p->graph, nullptr, 0, &p->np);
-    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    hipError_t e = plan_build(p);
     if (e != hipSuccess) {
         if (p->scratch) hipFree(p->scratch);
         delete p;
@@ -492,8 +513,7 @@ int hydro_plan_create(const hydro_params *params, const hydro_batch *batch, cons
 int hydro_plan_set_dt(hydro_plan *plan, double dt) {
     if (!plan) return HYDRO_EINVAL;
     plan->args.dt = dt;
-    plan->fargs.dt = dt;
-    hipError_t e = hipGraphExecKernelNodeSetParams(plan->exec, plan->node, &plan->np);
+    hipError_t e = plan_build(plan);
     return e == hipSuccess ? HYDRO_OK : fail_hip(e);
 }
 
@@ -647,7 +667,7 @@ int hydro_rk3_create(const hydro_params *params, const hydro_batch *batch,
     const int variant = hydro_selected_variant(batch->n_sub, 5);
     hydro_rk3 *p = new (std::nothrow) hydro_rk3();
     if (!p) return HYDRO_EINVAL;
-    if (fused_variant_needs_scratch(variant)) {
+    if (fused_needs_scratch(ra, variant)) {
         // allocated before the capture (no allocation may be captured); the
         // stages run one after another, so they share it
         rc = alloc_scratch(fused_scratch_bytes(batch->n_sub), &p->scratch);

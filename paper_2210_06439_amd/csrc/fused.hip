@@ -592,8 +592,12 @@ struct PlusState {
 
 // The loads of field f + 1 are issued before field f is reconstructed (see
 // ppm_fields); with XF >= 0 the values of field XF are loaded the same way
-// during the last hydro field and returned in xv.
-template <bool store_, bool both_, bool VEL, bool CW, bool minus_only = false, int XF = -1>
+// during the last hydro field and returned in xv.  VXO is the slot of the
+// stored point's x velocity (then y, z, pressure and sound speed follow):
+// P_VX for the 16-double point of the 11-field plan, 6 for the 11-double
+// point of the plane-paired plan.
+template <bool store_, bool both_, bool VEL, bool CW, bool minus_only = false, int XF = -1,
+          int VXO = P_VX>
 __device__ __forceinline__ PlusState produce_hydro(const double *win, const Line5 &l,
                                                    double *pp, double *pm, double gamma,
                                                    double gm1, double de, int &bits,
@@ -670,11 +674,11 @@ __device__ __forceinline__ PlusState produce_hydro(const double *win, const Line
         prp = gm1 * eip;
         csp = sqrt_cs((gamma * prp) * rp);
         if (store) {
-            pp[P_VX * 64] = vxp;
-            pp[(P_VX + 1) * 64] = vyp;
-            pp[(P_VX + 2) * 64] = vzp;
-            pp[P_P * 64] = prp;
-            pp[P_CS * 64] = csp;
+            pp[VXO * 64] = vxp;
+            pp[(VXO + 1) * 64] = vyp;
+            pp[(VXO + 2) * 64] = vzp;
+            pp[(VXO + 3) * 64] = prp;
+            pp[(VXO + 4) * 64] = csp;
         }
         bits |= (__ballot(rhop <= 0.0) ? HYDRO_STATUS_RHO : 0) |
                 (__ballot(prp <= 0.0) ? HYDRO_STATUS_P : 0);
@@ -683,11 +687,11 @@ __device__ __forceinline__ PlusState produce_hydro(const double *win, const Line
         double eim = fma(-0.5, ekm, Em);
         if (eim < de * Em) eim = tau_pow(qm, gamma);
         const double prm = gm1 * eim;
-        pm[P_VX * 64] = vxm;
-        pm[(P_VX + 1) * 64] = vym;
-        pm[(P_VX + 2) * 64] = vzm;
-        pm[P_P * 64] = prm;
-        pm[P_CS * 64] = sqrt_cs((gamma * prm) * rm);
+        pm[VXO * 64] = vxm;
+        pm[(VXO + 1) * 64] = vym;
+        pm[(VXO + 2) * 64] = vzm;
+        pm[(VXO + 3) * 64] = prm;
+        pm[(VXO + 4) * 64] = sqrt_cs((gamma * prm) * rm);
         bits |= (__ballot(rhom <= 0.0) ? HYDRO_STATUS_RHO : 0) |
                 (__ballot(prm <= 0.0) ? HYDRO_STATUS_P : 0);
     }
@@ -710,6 +714,18 @@ __device__ __forceinline__ void acc_zero(double (&c)[NH], bool hydro) {
     }
 }
 
+// a + b and a - b as single roundings, never fused with a product that forms
+// a or b: a point's terms are formed in registers by the wave that produced
+// it and read from LDS by the others, and every wave must round them alike
+__device__ __forceinline__ double add_r(double a, double b) {
+#pragma clang fp contract(off)
+    return a + b;
+}
+__device__ __forceinline__ double sub_r(double a, double b) {
+#pragma clang fp contract(off)
+    return a - b;
+}
+
 __device__ __forceinline__ void acc_h_vals(double (&c)[NH], const double *V, double un,
                                            double p, double cs, double w) {
     const double wun = w * un;
@@ -718,11 +734,11 @@ __device__ __forceinline__ void acc_h_vals(double (&c)[NH], const double *V, dou
     c[6] = fma(wun, V[1], c[6]);
     c[7] = fma(wun, V[2], c[7]);
     c[8] = fma(wun, V[3], c[8]);
-    c[9] = fma(wun, V[4] + p, c[9]);
+    c[9] = fma(wun, add_r(V[4], p), c[9]);
     c[10] = fma(wun, V[5], c[10]);
     c[H_SP] = fma(w, p, c[H_SP]);
-    c[H_LP] = fmax(c[H_LP], un + cs);
-    c[H_LM] = fmin(c[H_LM], un - cs);
+    c[H_LP] = fmax(c[H_LP], add_r(un, cs));
+    c[H_LM] = fmin(c[H_LM], sub_r(un, cs));
 }
 
 // a point's hydro values (and normal velocity, pressure and sound speed),
@@ -731,13 +747,14 @@ struct HPt {
     double V[6], un, p, cs;
 };
 
+template <int VXO = P_VX>
 __device__ __forceinline__ HPt load_h(const double *pt, int ax) {
     HPt h;
 #pragma unroll
     for (int f = 0; f < 6; f++) h.V[f] = pt[f * 64];
-    h.un = pt[(P_VX + ax) * 64];
-    h.p = pt[P_P * 64];
-    h.cs = pt[P_CS * 64];
+    h.un = pt[(VXO + ax) * 64];
+    h.p = pt[(VXO + 3) * 64];
+    h.cs = pt[(VXO + 4) * 64];
     return h;
 }
 
@@ -818,7 +835,10 @@ __device__ __forceinline__ Speeds combine_h(const double (&m)[NH], const double 
     const double m1 = m[1], m2 = m[2], m3 = m[3];
     const double ms = axis == 0 ? m1 : (axis == 1 ? m2 : m3);
     const double os = o[(1 + axis) * st];
-    Fb[0] = fma(cm, ms, co * os) * s.inv + (s.apam * (sg * (o[0] - m[0]))) * s.inv;
+    {
+        const double X = fma(cm, ms, co * os), Y = s.apam * (sg * (o[0] - m[0]));
+        Fb[0] = fma(Y, s.inv, X * s.inv);
+    }
     const double msp = m[H_SP], osp = o[H_SP * st];
 #pragma unroll
     for (int f = 1; f < 6; f++) {
@@ -827,7 +847,8 @@ __device__ __forceinline__ Speeds combine_h(const double (&m)[NH], const double 
             sfm += msp;
             sfo += osp;
         }
-        Fb[f] = fma(cm, sfm, co * sfo) * s.inv + (s.apam * (sg * (o[f * st] - m[f]))) * s.inv;
+        const double X = fma(cm, sfm, co * sfo), Y = s.apam * (sg * (o[f * st] - m[f]));
+        Fb[f] = fma(Y, s.inv, X * s.inv);
     }
     return s;
 }
@@ -1419,26 +1440,472 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
 
 }
 
+// ---- subgrids without species: two planes at a time ---------------------------
+//
+// A subgrid without species leaves the species wave of every role idle.  The
+// paired kernel (an instance of its own, so that its registers do not weigh
+// on the 11-field body) splits the eight waves into two groups of four roles:
+// group 0 (the first wave of each role) runs the plane schedule above on
+// plane k, group 1 (the second wave) on plane k + 1, so every SIMD carries two
+// hydro waves, and a step advances two planes.  Each group's sums keep the
+// order of the 11-field plan and every formula rounds as there, so the
+// results are the same bits.  The LDS plan (in doubles):
+//   a window of 6 planes of the 6 hydro fields (planes k-2 .. k+3), one
+//   exchange area per group with 11-double points (V[0..5], v, p, c) and the
+//   group's flux-phase arrays inside it, the z partial carried to the next
+//   step (group 1 -> group 0) and the one passed within a step (group 0 ->
+//   group 1), and each group's z fluxes and x/y differences, kept for two
+//   steps (by the step's parity).
+// A plane's cells are updated once both of its z fluxes exist: plane k-2 (all
+// of whose terms are the last step's) in the first flux phase, plane k-1 in
+// the second, by group 0's z owner, which has just formed its upper flux.
+// Nothing is carried in registers from one step to the next but the window's
+// prefetched planes.  The face layers are formed by group 0 alone.
+namespace pr {
+constexpr int SL = 6;                       // window planes
+constexpr int SD = 6 * NPLANE + 2;          // one window plane, + a dummy word
+constexpr int WIN = SL * SD;
+constexpr int VX = 6;                       // point: V[0..5], vx, vy, vz, p, c
+constexpr int SLOT = 11 * 64;
+constexpr int XG = 6 * SLOT;                // one group's exchange area
+constexpr int XR = 0;                       // [NH][2][8][9] right partials
+constexpr int LL = NH * RST;                // [2][2][8][9] left speeds
+constexpr int XF = 4 * SLOT;                // [6][2][8][9] face fluxes
+constexpr int X0 = WIN;                     // group g's area at X0 + g XG
+constexpr int ZL = X0 + 2 * XG;             // [NH][64]
+constexpr int ZX = ZL + NH * 64;            // [NH][64]
+constexpr int FZ = ZX + NH * 64;            // [parity][group][6][64] z fluxes
+constexpr int KP = FZ + 4 * 6 * 64;         // [parity][group][6][64] x/y differences
+constexpr int END = KP + 4 * 6 * 64;
+__device__ __forceinline__ int fz(int par, int g, int f) { return FZ + ((par * 2 + g) * 6 + f) * 64; }
+__device__ __forceinline__ int kp(int par, int g, int f) { return KP + ((par * 2 + g) * 6 + f) * 64; }
+static_assert(LL + 2 * RST <= XF && XF + 6 * RST <= XG, "a group's flux arrays");
+static_assert(4 * SLOT <= XF, "round 0 writes below the face fluxes (slots of roles 0 and 1)");
+static_assert(END * 8 + 512 <= 163840, "paired LDS plan");
+static_assert(6 * NPLANE <= 3 * NT, "a plane of 6 fields in three elements per thread");
+
+__device__ __forceinline__ Line5 line5(int i, int j, int k, int dx, int dy, int dz) {
+    Line5 l;
+#pragma unroll
+    for (int m = -2; m <= 2; m++) {
+        const int pl = (k + m * dz) % SL;
+        l.o[m + 2] = pl * SD + (j + m * dy) * NB + (i + m * dx);
+    }
+    return l;
+}
+
+// the cell update from the summed flux difference (as update_cell_sum, with
+// the cell's old values given); plane kc of the window, its x/y difference at
+// d, its upper and lower z fluxes at fu (or in Fu) and fl
+__device__ __forceinline__ void update(const double *u, const double *dsum, int kc, int ci, int cj,
+                                       double lam, bool rate, const Stage &stg, double *Os,
+                                       int fst, double &chk) {
+    const int cidx = opaque_v(kc * NPLANE + cj * NB + ci);
+    const int fs = fst;
+#pragma unroll
+    for (int f = 0; f < 6; f++) {
+        double v = (rate ? 0.0 : u[f]) - lam * dsum[f];
+        if (stg.U0) {
+            const double u0 = stg.U0[f * fs + cidx];
+            v = stg.identity ? u0 : fma(stg.c0, u0, stg.c1 * v);
+        }
+        chk = fma(v, 0.0, chk);
+        Os[f * fs + cidx] = v;
+    }
+}
+// The update of plane kc's cell (ci, cj) of the window: its x/y difference at
+// lds + d, the upper z fluxes Fu and the lower at lds + fl (fields 64 apart),
+// summed in the order of the 11-field plan.
+__device__ __forceinline__ void update_w(const double *lds, int kc, int ci, int cj, int lane,
+                                         int d, const double *Fu, int fl, double lam, bool rate,
+                                         const Stage &stg, double *Os, int fst, double &chk) {
+    const int cidx = opaque_v(kc * NPLANE + cj * NB + ci);
+    double vv[6];
+#pragma unroll
+    for (int f = 0; f < 6; f++) {
+        const double u = lds[(kc % SL) * SD + f * NPLANE + cj * NB + ci];
+        const double dfz = Fu[f] - lds[fl + f * 64 + lane];
+        const double sxy = lds[d + f * 64 + lane];
+        vv[f] = (rate ? 0.0 : u) - lam * (sxy + dfz);
+    }
+#pragma unroll
+    for (int f = 0; f < 6; f++) {
+        double v = vv[f];
+        if (stg.U0) {
+            const double u0 = stg.U0[f * fst + cidx];
+            v = stg.identity ? u0 : fma(stg.c0, u0, stg.c1 * v);
+        }
+        chk = fma(v, 0.0, chk);
+        Os[f * fst + cidx] = v;
+    }
+}
+}  // namespace pr
+
+struct PairOut {
+    double amax;
+    int bits;
+};
+
+// what the ghost map's check reads from the launch's arguments
+struct PairMeta {
+    const int32_t *gsrc, *gmode, *n_species;
+    const int64_t *offset;
+    int32_t n_sub;
+};
+
+template <bool GATHER>
+__device__ __forceinline__ PairOut subgrid_pair(
+    double *lds, int tid, int role, int grp, const double *Us0, double *Os0, int fst0, double lam,
+    bool rate, Stage stg, bool sym, double gamma, double gm1, double de, PairMeta a, int s,
+    const double *Ug, int64_t *toff, int *tmode, int kb_, int ke_) {
+    // uniform values as scalars (the subgrid index comes from a list load),
+    // so that branches and addresses derived from them stay scalar
+    role = __builtin_amdgcn_readfirstlane(role);
+    grp = __builtin_amdgcn_readfirstlane(grp);
+    fst0 = __builtin_amdgcn_readfirstlane(fst0);
+    s = __builtin_amdgcn_readfirstlane(s);
+    const int kb = __builtin_amdgcn_readfirstlane(kb_), ke = __builtin_amdgcn_readfirstlane(ke_);
+    double *win = lds;
+    double *xg = lds + pr::X0 + grp * pr::XG;
+    double *zl = lds + pr::ZL;
+    double *zx = lds + pr::ZX;
+    double amax_l = 0.0;
+    int bits = 0;
+    double chk = 0.0;
+    constexpr int nspec = 0;
+    int g_off[3], l_off[3];
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+        const int e = tid + q * NT;
+        const int f = e / NPLANE, c = e - f * NPLANE;
+        const bool ok = e < 6 * NPLANE;
+        if (!GATHER) {
+            g_off[q] = ok ? f * fst0 + c : 0;
+        } else {
+            const int i = ok ? c % NB : NG, j = ok ? c / NB : NG;
+            const int dx = i < NG ? -1 : (i >= NG + NSUB ? 1 : 0);
+            const int dy = j < NG ? -1 : (j >= NG + NSUB ? 1 : 0);
+            g_off[q] = i | (j << 4) | ((dx + 1) << 8) | ((dy + 1) << 10) | ((ok ? f : 0) << 12);
+        }
+        l_off[q] = ok ? f * NPLANE + c : 6 * NPLANE;
+    }
+    auto src = [&](int q, int pk) -> const double * {
+        if (!GATHER) return Us0 + (g_off[q] + pk * NPLANE);
+        const int g = opaque_v(g_off[q]);
+        return gather_ptr(Ug, toff, tmode, (g >> 12) * fst0, g, pk);
+    };
+
+    lds_barrier();   // the previous subgrid's LDS reads are done
+    if (GATHER) {
+        if (tid < 27) {
+            const int64_t own = Us0 - Ug;
+            int64_t o = own;
+            int m = tid == 13 ? 0 : 7;
+            if (tid != 13) {
+                const int sb = a.gsrc[s * 27 + tid];
+                bool good = sb >= 0 && sb < a.n_sub;
+                if (good) {
+                    const int ns2 = a.n_species[sb];
+                    const int64_t o2 = a.offset[sb];
+                    good = ns2 >= 0 && ns2 <= 5 && ns2 >= nspec && o2 >= 0 && !(o2 & 1);
+                    if (good) {
+                        o = o2;
+                        m = a.gmode[s * 27 + tid];
+                    }
+                }
+                if (!good) bits |= HYDRO_STATUS_BADMETA;
+            }
+            toff[tid] = o;
+            tmode[tid] = m;
+        }
+        lds_barrier();
+    }
+    // window: planes kb-2 .. kb+3; then planes kb+4 (after the lower face
+    // layer) and kb+5 are held in registers
+    {
+        double v[pr::SL][3];
+#pragma unroll
+        for (int pl = 0; pl < pr::SL; pl++)
+#pragma unroll
+            for (int q = 0; q < 3; q++) v[pl][q] = *src(q, kb - 2 + pl);
+#pragma unroll
+        for (int pl = 0; pl < pr::SL; pl++) {
+            double *dst = win + ((kb - 2 + pl) % pr::SL) * pr::SD;
+#pragma unroll
+            for (int q = 0; q < 3; q++) dst[l_off[q]] = v[pl][q];
+        }
+    }
+    double pf[2][3];
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+        pf[0][q] = kb + 4 <= ke + 2 ? *src(q, kb + 4) : 0.0;
+        pf[1][q] = kb + 5 <= ke + 2 ? *src(q, kb + 5) : 0.0;
+    }
+    lds_barrier();
+
+    double acc[2][NH];
+    double Fb[6];
+    const CwW cw0 = {0.0, 0.0};
+    int par = 0;         // parity of the pair step: its z fluxes and x/y differences
+    for (int k = kb; k <= ke;) {
+        const bool layer = (k == kb || k == ke);
+        acc_zero(acc[0], true);
+        acc_zero(acc[1], true);
+        if (layer) {
+            // 3 rounds of group 0, as the 11-field face layers
+            const bool bottom = k == kb;
+#pragma unroll 1
+            for (int r = 0; r < 3; r++) {
+                LANE_GEOMETRY();
+                const int t = role + 4 * r;
+                double *pp = xg + role * pr::SLOT + lane;
+                if (grp == 0 && t < 9) {
+                    const int dc = (int)(zline_dirs() >> (6 * t)) & 63;
+                    const int dx = (dc & 3) - 1, dy = ((dc >> 2) & 3) - 1, dz = (dc >> 4) - 1;
+                    const Line5 l = pr::line5(ci, cj, k, dx, dy, dz);
+                    if (bottom)
+                        produce_hydro<true, false, false, false, false, -1, pr::VX>(
+                            win, l, pp, pp, gamma, gm1, de, bits, cw0);
+                    else
+                        produce_hydro<false, false, false, false, true, -1, pr::VX>(
+                            win, l, pp, pp, gamma, gm1, de, bits, cw0);
+                }
+                lds_barrier();
+                if (role == 2 && grp == 0) {
+                    constexpr uint32_t zw = zline_wcodes();
+                    HPt q[4];
+#pragma unroll
+                    for (int w = 0; w < 4; w++) q[w] = load_h<pr::VX>(xg + w * pr::SLOT + lane, 2);
+#pragma unroll
+                    for (int w = 0; w < 4; w++) {
+                        const int t2 = w + 4 * r;
+                        if (t2 < 9)
+                            acc_h_vals(acc[0], q[w].V, q[w].un, q[w].p, q[w].cs,
+                                       simpson_wc((zw >> (2 * t2)) & 3));
+                    }
+                }
+                lds_barrier();
+            }
+            LANE_GEOMETRY();
+            if (bottom) {
+                // plane kb+4 into the slot of kb-2; kb+5 moves up, kb+6 is loaded
+                if (kb + 4 <= ke + 2) {
+                    double *dst = win + ((kb + 4) % pr::SL) * pr::SD;
+#pragma unroll
+                    for (int q = 0; q < 3; q++) dst[l_off[q]] = pf[0][q];
+                }
+#pragma unroll
+                for (int q = 0; q < 3; q++) {
+                    pf[0][q] = pf[1][q];
+                    pf[1][q] = kb + 6 <= ke + 2 ? *src(q, kb + 6) : 0.0;
+                }
+                if (role == 2 && grp == 0) store_h(zl + lane, 64, acc[0]);
+                lds_barrier();
+                k += 1;
+            } else {
+                // face (ke-1|ke), its left partial from the last pair step's
+                // group 1; planes ke-2 and ke-1 are updated
+                const int pl = par ^ 1;
+                if (role == 2 && grp == 1 && ke - 2 >= kb + 1) {
+                    double Fu[6];
+#pragma unroll
+                    for (int f = 0; f < 6; f++) Fu[f] = lds[pr::fz(pl, 1, f) + lane];
+                    pr::update_w(lds, ke - 2, ci, cj, lane, pr::kp(pl, 0, 0), Fu, pr::fz(pl, 0, 0),
+                                 lam, rate, stg, Os0, fst0, chk);
+                }
+                if (role == 2 && grp == 0) {
+                    double Fz[6];
+                    const Speeds sp = combine_h(acc[0], zl + lane, 64, false, 2, sym, Fz);
+                    amax_l = fmax(amax_l, sp.amax_face);
+                    if (ke - 1 >= kb + 1)
+                        pr::update_w(lds, ke - 1, ci, cj, lane, pr::kp(pl, 1, 0), Fz,
+                                     pr::fz(pl, 1, 0), lam, rate, stg, Os0, fst0, chk);
+                }
+                k += 1;
+            }
+            continue;
+        }
+
+        // ---- a pair step: plane k by group 0, plane k+1 by group 1
+        const int kg = k + grp;
+        const int pl = par ^ 1;      // the last pair step's buffers
+        if (role < 3) {
+            const int ax = role;
+            const uint64_t ctab = ax == 0 ? cons_table(0) : ax == 1 ? cons_table(1) : cons_table(2);
+            const uint64_t ptab = ax == 0 ? prod_table(0) : ax == 1 ? prod_table(1) : prod_table(2);
+#pragma unroll 1
+            for (int r = 0; r < 5; r++) {
+                LANE_GEOMETRY();
+                const int pd = (int)(ptab >> (7 * r)) & 127;
+                if (pd & 64) {
+                    const int dx = (pd & 3) - 1, dy = ((pd >> 2) & 3) - 1, dz = ((pd >> 4) & 3) - 1;
+                    const Line5 l = pr::line5(ci, cj, kg, dx, dy, dz);
+                    produce_hydro<true, true, false, false, false, -1, pr::VX>(
+                        win, l, xg + (role * 2 + 0) * pr::SLOT + lane,
+                        xg + (role * 2 + 1) * pr::SLOT + lane, gamma, gm1, de, bits, cw0);
+                }
+                lds_barrier();
+                {
+                    const int d0 = (int)(ctab >> (10 * r)) & 31;
+                    const int d1 = (int)(ctab >> (10 * r + 5)) & 31;
+                    const double w0 = simpson_wc(d0 >> 3), w1 = simpson_wc(d1 >> 3);
+                    const HPt pa0 = load_h<pr::VX>(xg + (d0 & 7) * pr::SLOT + lane, ax);
+                    const HPt pb0 = load_h<pr::VX>(xg + ((d0 & 7) ^ 1) * pr::SLOT + lane, ax);
+                    const HPt pa1 = load_h<pr::VX>(xg + (d1 & 7) * pr::SLOT + lane, ax);
+                    const HPt pb1 = load_h<pr::VX>(xg + ((d1 & 7) ^ 1) * pr::SLOT + lane, ax);
+                    acc_h_vals(acc[0], pa0.V, pa0.un, pa0.p, pa0.cs, w0);
+                    acc_h_vals(acc[1], pb0.V, pb0.un, pb0.p, pb0.cs, w0);
+                    acc_h_vals(acc[0], pa1.V, pa1.un, pa1.p, pa1.cs, w1);
+                    acc_h_vals(acc[1], pb1.V, pb1.un, pb1.p, pb1.cs, w1);
+                }
+                lds_barrier();
+            }
+        } else {
+#pragma unroll 1
+            for (int r = 0; r < 5; r++) {
+                LANE_GEOMETRY();
+                const int t0 = half ? 5 + r : r;
+                const int t = t0 < 9 ? t0 : 8;
+                const double wt = t0 < 9 ? simpson_w(t % 3 - 1, t / 3 - 1) : 0.0;
+                const int dn = r_side ? -1 : 1;
+                const int dx = r_axis == 0 ? dn : t % 3 - 1;
+                const int dy = r_axis == 0 ? t % 3 - 1 : dn;
+                const Line5 l = pr::line5(ri, rj, kg, dx, dy, t / 3 - 1);
+                const PlusState ps = produce_hydro<false, false, false, false>(
+                    win, l, nullptr, nullptr, gamma, gm1, de, bits, cw0);
+                acc_h_vals(acc[0], ps.q, r_axis == 0 ? ps.vx : ps.vy, ps.p, ps.cs, wt);
+                lds_barrier();
+                lds_barrier();
+            }
+        }
+
+        LANE_GEOMETRY();
+        if (role == 3) {
+#pragma unroll
+            for (int i = 0; i < NH; i++) {
+                const double o = pair_swap(acc[0][i]);
+                if (i == H_LP) acc[0][i] = fmax(acc[0][i], o);
+                else if (i == H_LM) acc[0][i] = fmin(acc[0][i], o);
+                else acc[0][i] += o;
+            }
+        }
+        // phase 1: right partials and left speeds of the group's x/y faces;
+        // group 0's z owner passes its upper partial to group 1; group 1's z
+        // owner updates plane k-2 (all its terms are the last step's)
+        if (role == 0 || role == 1) {
+            double *R = xg + pr::XR + (role == 0 ? (0 * 8 + (cj - 3)) * 9 + (ci - 3)
+                                                 : (1 * 8 + (ci - 3)) * 9 + (cj - 3));
+            store_h(R, RST, acc[1]);
+        }
+        if (role == 3 && half == 0 && r_side == 1) {
+            double *R = xg + pr::XR + (r_axis * 8 + (r_pos - 3)) * 9 + 8;
+            store_h(R, RST, acc[0]);
+        }
+        {
+            int ll = -1;
+            if (role == 0) ll = (0 * 8 + (cj - 3)) * 9 + (ci - 2);
+            if (role == 1) ll = (1 * 8 + (ci - 3)) * 9 + (cj - 2);
+            if (role == 3 && half == 0 && r_side == 0) ll = (r_axis * 8 + (r_pos - 3)) * 9;
+            if (ll >= 0) {
+                xg[pr::LL + ll] = acc[0][H_LP];
+                xg[pr::LL + RST + ll] = acc[0][H_LM];
+            }
+        }
+        if (role == 2 && grp == 0) store_h(zx + lane, 64, acc[0]);
+        if (role == 2 && grp == 1 && k - 2 >= kb + 1) {
+            double Fu[6];
+#pragma unroll
+            for (int f = 0; f < 6; f++) Fu[f] = lds[pr::fz(pl, 1, f) + lane];
+            pr::update_w(lds, k - 2, ci, cj, lane, pr::kp(pl, 0, 0), Fu, pr::fz(pl, 0, 0), lam,
+                         rate, stg, Os0, fst0, chk);
+        }
+        lds_barrier();
+        // phase 2: x/y face fluxes; the z faces (k-1|k) (group 0, which then
+        // updates plane k-1) and (k|k+1) (group 1)
+        if (role < 2 || (role == 3 && half == 0 && r_side == 0)) {
+            const int ax = role < 2 ? role : r_axis;
+            const int row = role == 0 ? cj - 3 : role == 1 ? ci - 3 : r_pos - 3;
+            const int p = role == 0 ? ci - 2 : role == 1 ? cj - 2 : 0;
+            const int fi = (ax * 8 + row) * 9 + p;
+            const Speeds sp = combine_h(acc[0], xg + pr::XR + fi, RST, true, ax, sym, Fb);
+            amax_l = fmax(amax_l, sp.amax_face);
+#pragma unroll
+            for (int f = 0; f < 6; f++) xg[pr::XF + fi + f * RST] = Fb[f];
+        }
+        if (role == 2) {
+            double Fz[6];
+            const Speeds sp = combine_h(acc[1], (grp == 0 ? zl : zx) + lane, 64, false, 2, sym, Fz);
+            amax_l = fmax(amax_l, sp.amax_face);
+#pragma unroll
+            for (int f = 0; f < 6; f++) lds[pr::fz(par, grp, f) + lane] = Fz[f];
+            if (grp == 0 && k - 1 >= kb + 1)
+                pr::update_w(lds, k - 1, ci, cj, lane, pr::kp(pl, 1, 0), Fz, pr::fz(pl, 1, 0), lam,
+                             rate, stg, Os0, fst0, chk);
+        }
+        lds_barrier();
+        // phase 3: each group's x owner forms its plane's x/y difference;
+        // group 1 passes its upper partial to the next step; the two planes
+        // after the window are stored
+        if (role == 2 && grp == 1) store_h(zl + lane, 64, acc[0]);
+        if (role == 0) {
+            const double *Fl = xg + pr::XF + (cj - 3) * 9 + (ci - 3);
+            const double *Fy = xg + pr::XF + (8 + (ci - 3)) * 9 + (cj - 3);
+#pragma unroll
+            for (int f = 0; f < 6; f++)
+                lds[pr::kp(par, grp, f) + lane] =
+                    (Fb[f] - Fl[f * RST]) + (Fy[f * RST + 1] - Fy[f * RST]);
+        }
+        if (k + 4 <= ke + 2) {
+            double *dst = win + ((k + 4) % pr::SL) * pr::SD;
+#pragma unroll
+            for (int q = 0; q < 3; q++) dst[l_off[q]] = pf[0][q];
+        }
+        if (k + 5 <= ke + 2) {
+            double *dst = win + ((k + 5) % pr::SL) * pr::SD;
+#pragma unroll
+            for (int q = 0; q < 3; q++) dst[l_off[q]] = pf[1][q];
+        }
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            pf[0][q] = k + 6 <= ke + 2 ? *src(q, k + 6) : 0.0;
+            pf[1][q] = k + 7 <= ke + 2 ? *src(q, k + 7) : 0.0;
+        }
+        lds_barrier();
+        par ^= 1;
+        k += 2;
+    }
+    if (chk != chk) bits |= HYDRO_STATUS_NONFINITE;
+    PairOut out;
+    out.amax = amax_l;
+    out.bits = bits;
+    return out;
+}
+
 // ---- the kernel ---------------------------------------------------------------
 
-// Scratch of the split and dynamic launch shapes (32-bit words): [0] next work
-// item, [1] workgroups done, [16, 16 + 2 n) per-subgrid running max of the
-// parts' face speeds (as 64-bit patterns of non-negative doubles), then n
-// status words and n arrival counts.  Every word is back at zero when the
-// launch ends (the last workgroup or part to finish clears what it used).
+// Scratch of a step (32-bit words): [0] next work item, [1] workgroups done,
+// [3] number of subgrids listed for the paired kernel, [16, 16 + 2 n)
+// per-subgrid running max of the parts' face speeds (as 64-bit patterns of
+// non-negative doubles), then n status words, n arrival counts and the list
+// of subgrids for the paired kernel.  Every counter is back at zero when the
+// step ends (the last workgroup or part to finish clears what it used); the
+// list is rewritten by every step.
 __device__ __forceinline__ unsigned long long *sc_amax(uint32_t *sc) {
     return reinterpret_cast<unsigned long long *>(sc + 16);
 }
 __device__ __forceinline__ uint32_t *sc_bits(uint32_t *sc, int n) { return sc + 16 + 2 * n; }
 __device__ __forceinline__ uint32_t *sc_count(uint32_t *sc, int n) { return sc + 16 + 3 * n; }
+__device__ __forceinline__ uint32_t *sc_list(uint32_t *sc, int n) { return sc + 16 + 4 * n; }
 
-template <bool VEL, bool CW, bool GATHER>
+template <bool VEL, bool CW, bool GATHER, bool PAIR = false>
 __global__ __launch_bounds__(NT, 2) void k_fused(FusedArgs a, const double *__restrict__ U,
                                                  double *Uo,
                                                  double *__restrict__ amax,
                                                  int32_t *__restrict__ status, int order) {
-    __shared__ double lds[LDS_D];
+    __shared__ double lds[PAIR ? pr::END : LDS_D];
+    __shared__ double red_pair[PAIR ? 8 : 1];
     __shared__ int red_bits[8];
+    __shared__ int last_out;         // this workgroup is the last to finish
     __shared__ int next_item[2];     // by parity of the iteration (no barrier between
                                      // one iteration's read and the next one's write)
     __shared__ int64_t g_toff[GATHER ? 27 : 1];    // ghost-map table of the current subgrid
@@ -1448,7 +1915,7 @@ __global__ __launch_bounds__(NT, 2) void k_fused(FusedArgs a, const double *__re
     double *zl = xch + XCH_D;          // z-face left partials carried between steps
     double *keep = zl + ZL_D;          // [0: F_z of the face below][1: dFx+dFy][11][64]
     double *run = keep + KEEP_D;       // ring lanes' normal velocity
-    double *red = run + RUN_D;
+    double *red = PAIR ? red_pair : run + RUN_D;
 
     // the role as a scalar: branches on it are then uniform branches, with no
     // exec-mask bookkeeping.  (The field-group test stays a vector compare: as
@@ -1465,21 +1932,30 @@ __global__ __launch_bounds__(NT, 2) void k_fused(FusedArgs a, const double *__re
     // interior planes each, part q of subgrid s is item s P + q), fetched in
     // a static stride or, in the dynamic form, from a counter in scratch
     const int lp = a.log_parts, P = 1 << lp, span = NSUB >> lp;
-    const int n_items = a.n_sub << lp;
     uint32_t *sc = a.scratch;
+    // The paired kernel takes the subgrids the other kernel of the step passed
+    // over and listed (subgrids without species, when a.pairing is set).
+    int n_list = a.n_sub;
+    if constexpr (PAIR) n_list = (int)__builtin_amdgcn_readfirstlane(sc[3]);
+    const int n_items = n_list << lp;
+    if (PAIR && n_items == 0) return;      // the same for every workgroup
 
     int parity = 0;
     for (int it = blockIdx.x; it < n_items; parity ^= 1) {
         const int s0 = it >> lp, q = it & (P - 1);
-        const int s = order ? (a.n_sub - 1 - s0) : s0;
+        const int i0 = order ? (n_list - 1 - s0) : s0;
+        const int s = PAIR ? (int)sc_list(sc, a.n_sub)[i0] : i0;
         const int kb = NG - 1 + q * span, ke = kb + span + 1;
         const int nspec = a.n_species[s];
         const int64_t off = a.offset[s];
         const int64_t ooff = a.out_offset ? a.out_offset[s] : off;
         const bool bad = nspec < 0 || nspec > 5 || off < 0 || (off & 1) || ooff < 0 || (ooff & 1);
+        // left to the paired kernel, and listed for it once (by part 0)
+        const bool defer = !PAIR && a.pairing && nspec == 0;
+        if (defer && q == 0 && tid == 0) sc_list(sc, a.n_sub)[atomicAdd(&sc[3], 1u)] = (uint32_t)s;
         double amax_l = 0.0;
         int bits = 0;
-        if (!bad) {
+        if (!bad && !defer) {
             const double dtv = a.clock ? a.clock[1] : a.dt;
             const double lam = rate ? 1.0 / a.h[s] : dtv / a.h[s];
             Stage stg;
@@ -1490,16 +1966,35 @@ __global__ __launch_bounds__(NT, 2) void k_fused(FusedArgs a, const double *__re
             const double *Us0 = U + off;
             double *Os0 = Uo + ooff;
             const int fst0 = a.fstride;
-            if (hyd)
+            if constexpr (PAIR) {
+                // a subgrid without species, swept in parts of at least two
+                // interior planes (the host pairs no other launch shape)
+                if (nspec != 0 || span < 2) {
+                    bits = HYDRO_STATUS_BADMETA;
+                } else {
+                    PairMeta pm;
+                    pm.gsrc = a.gsrc;
+                    pm.gmode = a.gmode;
+                    pm.n_species = a.n_species;
+                    pm.offset = a.offset;
+                    pm.n_sub = a.n_sub;
+                    const PairOut po = subgrid_pair<GATHER>(
+                        lds, tid, role, __builtin_amdgcn_readfirstlane(wave) >> 2, Us0, Os0, fst0,
+                        lam, rate, stg, sym, gamma, gm1, de, pm, s, U, g_toff, g_tmode, kb, ke);
+                    amax_l = po.amax;
+                    bits = po.bits;
+                }
+            } else if (hyd) {
                 subgrid_body<true, VEL, CW, GATHER>(win, xch, zl, keep, run, tid, role, nspec, Us0,
                                                     Os0, fst0, lam, rate, stg, sym, cwmode, gamma,
                                                     gm1, de, amax_l, bits, a, s, U, g_toff,
                                                     g_tmode, kb, ke);
-            else
+            } else {
                 subgrid_body<false, VEL, CW, GATHER>(win, xch, zl, keep, run, tid, role, nspec,
                                                      Us0, Os0, fst0, lam, rate, stg, sym, cwmode,
                                                      gamma, gm1, de, amax_l, bits, a, s, U, g_toff,
                                                      g_tmode, kb, ke);
+            }
 
             // ---- the part's speed and status
             for (int o = 32; o > 0; o >>= 1) {
@@ -1514,7 +2009,7 @@ __global__ __launch_bounds__(NT, 2) void k_fused(FusedArgs a, const double *__re
         if (a.dyn && tid == 0)
             next_item[parity] = (int)gridDim.x + (int)atomicAdd(&sc[0], 1u);
         lds_barrier();
-        if (tid == 0) {
+        if (tid == 0 && !defer) {
             double m = 0.0;
             int b = HYDRO_STATUS_BADMETA;
             if (!bad) {
@@ -1547,13 +2042,24 @@ __global__ __launch_bounds__(NT, 2) void k_fused(FusedArgs a, const double *__re
         }
         it = a.dyn ? next_item[parity] : it + (int)gridDim.x;
     }
-    if (a.dyn) {
-        // the last workgroup out clears the counters for the next launch
+    if (a.dyn || PAIR) {
+        // the last workgroup out clears the counters (and, after the paired
+        // kernel, the list) for the next step
         if (tid == 0) {
             __threadfence();
-            if (atomicAdd(&sc[1], 1u) == gridDim.x - 1) {
+            const bool last = atomicAdd(&sc[1], 1u) == gridDim.x - 1;
+            if (last) {
                 atomicExch(&sc[0], 0u);
                 atomicExch(&sc[1], 0u);
+            }
+            last_out = last;
+        }
+        if (PAIR) {
+            lds_barrier();
+            if (last_out) {
+                uint32_t *list = sc_list(sc, a.n_sub);
+                for (int i = tid; i < n_list; i += NT) list[i] = 0u;
+                if (tid == 0) atomicExch(&sc[3], 0u);
             }
         }
     }
@@ -1613,6 +2119,16 @@ FusedKernel fused_kernel(const StepArgs &a) {
     return a.gsrc ? fused_kernel_g<true>(a) : fused_kernel_g<false>(a);
 }
 
+FusedKernel paired_kernel(const StepArgs &a) {
+    return a.gsrc ? k_fused<false, false, true, true> : k_fused<false, false, false, true>;
+}
+
+// Whether a step in variant v runs its subgrids without species in the
+// paired kernel: the default options, and parts of at least two planes.
+bool pairs(const StepArgs &a, int v) {
+    return !a.vel && !a.steepen && !a.flatten && kVariants[v].log_parts < 3;
+}
+
 dim3 grid_of(const StepArgs &a, int v) {
     const Variant &V = kVariants[v];
     const int items = a.n_sub << V.log_parts;
@@ -1630,10 +2146,11 @@ const char *fused_variant_name(int v) {
 int fused_variant_order(int v) {
     return (v >= 0 && v < fused_variant_count()) ? kVariants[v].order : 0;
 }
-bool fused_variant_needs_scratch(int v) {
-    return v >= 0 && v < fused_variant_count() && (kVariants[v].log_parts > 0 || kVariants[v].dyn);
+bool fused_needs_scratch(const StepArgs &a, int v) {
+    return v >= 0 && v < fused_variant_count() &&
+           (kVariants[v].log_parts > 0 || kVariants[v].dyn || pairs(a, v));
 }
-int64_t fused_scratch_bytes(int n_sub) { return 64 + 16 * (int64_t)(n_sub > 0 ? n_sub : 0); }
+int64_t fused_scratch_bytes(int n_sub) { return fused_scratch_bytes_for(n_sub > 0 ? n_sub : 0); }
 
 int fused_default_variant(int n_sub) {
     // The launch of fewest rounds of work items, each round costing one
@@ -1666,24 +2183,17 @@ hipError_t launch_fused_step(const StepArgs &a0, const double *U_in, double *U_o
     if (a0.n_sub == 0) return hipSuccess;
     StepArgs a = a0;
     apply_variant(a, variant);
-    if ((a.log_parts || a.dyn) && !a.scratch) return hipErrorInvalidValue;
+    a.pairing = pairs(a, variant) ? 1 : 0;
+    if (fused_needs_scratch(a, variant) && !a.scratch) return hipErrorInvalidValue;
+    // the 11-field kernel, then the paired one over the subgrids it listed
     hipLaunchKernelGGL(fused_kernel(a), grid_of(a, variant), dim3(NT), 0, st, fused_args(a), U_in,
+                       U_out, amax, status, kVariants[variant].order);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !a.pairing) return e;
+    hipLaunchKernelGGL(paired_kernel(a), grid_of(a, variant), dim3(NT), 0, st, fused_args(a), U_in,
                        U_out, amax, status, kVariants[variant].order);
     return hipGetLastError();
 }
 
-hipError_t fused_kernel_node_params(const StepArgs &a, const double *U_in, double *U_out,
-                                    double *amax, int32_t *status, int variant,
-                                    hipKernelNodeParams *out, void **args) {
-    // args must point at storage for the kernel's arguments, filled by the caller
-    out->func = reinterpret_cast<void *>(fused_kernel(a));
-    out->gridDim = grid_of(a, variant);
-    out->blockDim = dim3(NT);
-    out->sharedMemBytes = 0;
-    out->kernelParams = args;
-    out->extra = nullptr;
-    (void)U_in; (void)U_out; (void)amax; (void)status;
-    return hipSuccess;
-}
 
 }  // namespace hydro

@@ -11,18 +11,13 @@ static_assert(NSUB != 8, "the 8^3 build links fused.hip");
 int fused_variant_count() { return 0; }
 const char *fused_variant_name(int) { return "?"; }
 int fused_variant_order(int) { return 0; }
-bool fused_variant_needs_scratch(int) { return false; }
+bool fused_needs_scratch(const StepArgs &, int) { return false; }
 int64_t fused_scratch_bytes(int) { return 0; }
 int fused_default_variant(int) { return 0; }
 void apply_variant(StepArgs &, int) {}
 
 hipError_t launch_fused_step(const StepArgs &, const double *, double *, double *, int32_t *,
                              int, hipStream_t) {
-    return hipErrorNotSupported;
-}
-
-hipError_t fused_kernel_node_params(const StepArgs &, const double *, double *, double *,
-                                    int32_t *, int, hipKernelNodeParams *, void **) {
     return hipErrorNotSupported;
 }
 
