@@ -1652,14 +1652,16 @@ __device__ __forceinline__ PairOut subgrid_pair(
         acc_zero(acc[0], true);
         acc_zero(acc[1], true);
         if (layer) {
-            // 3 rounds of group 0, as the 11-field face layers
+            // the 9 z lines of the face layer: lines 0-7 by the eight waves,
+            // then line 8; group 0's z owner sums them in line order
             const bool bottom = k == kb;
+            constexpr uint32_t zw = zline_wcodes();
 #pragma unroll 1
-            for (int r = 0; r < 3; r++) {
+            for (int r = 0; r < 2; r++) {
                 LANE_GEOMETRY();
-                const int t = role + 4 * r;
+                const int t = role + 4 * grp + 8 * r;
                 double *pp = xg + role * pr::SLOT + lane;
-                if (grp == 0 && t < 9) {
+                if (t < 9) {
                     const int dc = (int)(zline_dirs() >> (6 * t)) & 63;
                     const int dx = (dc & 3) - 1, dy = ((dc >> 2) & 3) - 1, dz = (dc >> 4) - 1;
                     const Line5 l = pr::line5(ci, cj, k, dx, dy, dz);
@@ -1672,16 +1674,20 @@ __device__ __forceinline__ PairOut subgrid_pair(
                 }
                 lds_barrier();
                 if (role == 2 && grp == 0) {
-                    constexpr uint32_t zw = zline_wcodes();
-                    HPt q[4];
+                    const int nw = r == 0 ? 2 : 1;          // groups of four lines
+#pragma unroll 1
+                    for (int g = 0; g < nw; g++) {
+                        const double *xs = lds + pr::X0 + g * pr::XG + lane;
+                        HPt q[4];
 #pragma unroll
-                    for (int w = 0; w < 4; w++) q[w] = load_h<pr::VX>(xg + w * pr::SLOT + lane, 2);
+                        for (int w = 0; w < 4; w++) q[w] = load_h<pr::VX>(xs + w * pr::SLOT, 2);
 #pragma unroll
-                    for (int w = 0; w < 4; w++) {
-                        const int t2 = w + 4 * r;
-                        if (t2 < 9)
-                            acc_h_vals(acc[0], q[w].V, q[w].un, q[w].p, q[w].cs,
-                                       simpson_wc((zw >> (2 * t2)) & 3));
+                        for (int w = 0; w < 4; w++) {
+                            const int t2 = w + 4 * g + 8 * r;
+                            if (t2 < 9)
+                                acc_h_vals(acc[0], q[w].V, q[w].un, q[w].p, q[w].cs,
+                                           simpson_wc((zw >> (2 * t2)) & 3));
+                        }
                     }
                 }
                 lds_barrier();
