@@ -687,7 +687,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tf / FP64_PEAK_TFLOPS,
                      "traffic": None if traffic is None else traffic["bytes"],
-                     "kernel": "k_fused<false, false, false>", "flops_per_launch": flops,
+                     "kernel": "k_fused<false, false, false, false>", "flops_per_launch": flops,
                      "kernel_ms": kern_ms},
         "hbm": {"achieved": achieved_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": achieved_gbps / HBM_PEAK_GBPS, "bytes_per_launch": nbytes,

@@ -30,8 +30,7 @@
  *    are DEVICE pointers owned by the caller; `params` and `batch` themselves
  *    are host pointers read during the call.  Nothing is retained after the
  *    call returns, except by hydro_plan_create and hydro_rk3_create (see
- *    there) and the scratch of the split launch shapes (see
- *    hydro_workspace_bytes).
+ *    there) and the fused step's scratch (see hydro_workspace_bytes).
  *  - Every call enqueues its kernels on `stream` (a hipStream_t; NULL means
  *    the default stream) and returns without synchronising.
  *  - Return value: HYDRO_OK, or a negative HYDRO_E* code; hydro_strerror()
@@ -187,7 +186,11 @@ int hydro_divergence(const hydro_params *params, const hydro_batch *batch,
  * kernel sums the Simpson-weighted terms in a different order).  Writes the
  * interior of U_out, amax[s] and status[s] (may be NULL).  U_out must not
  * alias U_in.  Uses the launch shape chosen by hydro_autotune() for this
- * kind of batch when one was tuned, else the default shape.
+ * kind of batch when one was tuned, else the default shape.  With the default
+ * options (no velocity reconstruction, steepening or flattening) the same
+ * launch sweeps the subgrids without species in a second body, which advances
+ * two planes per step on the waves that would carry species; its results are
+ * the same bits.
  */
 int hydro_step(const hydro_params *params, const hydro_batch *batch,
                const double *U_in, double *U_out, double *amax,
@@ -309,6 +312,9 @@ int hydro_selected_variant(int n_sub, int max_species);
  * shape is the one hydro_selected_variant gives at creation; a split or
  * dynamic shape gets scratch of its own (allocated here, freed by
  * hydro_plan_destroy), so replays of one plan must not overlap each other.
+ * Creation reads the species counts once (synchronously): when every subgrid
+ * has species the plan launches the kernel without the paired body (which
+ * sweeps any subgrid correctly, so counts rewritten later stay correct).
  */
 typedef struct hydro_plan hydro_plan;
 
@@ -440,7 +446,8 @@ int hydro_rk_stage(const hydro_params *params, const hydro_batch *batch, const d
  * dt = 0 and leave U unchanged.  The plan keeps every pointer (including
  * batch and map arrays) until destroyed; their contents may change between
  * replays.  A split or dynamic launch shape gets scratch of its own
- * (allocated before the capture, freed by hydro_rk3_destroy).
+ * (allocated before the capture, freed by hydro_rk3_destroy); the species
+ * counts are read once, as for hydro_plan_create.
  */
 typedef struct hydro_rk3 hydro_rk3;
 

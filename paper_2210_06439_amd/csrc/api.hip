@@ -10,6 +10,7 @@
 #include <string>
 #include <unordered_map>
 #include <utility>
+#include <vector>
 
 #include "hydro_internal.hpp"
 
@@ -235,6 +236,21 @@ struct hydro_rk3 {
 };
 
 namespace {
+
+// Whether the batch holds no subgrid without species, read once when a plan
+// or an RK3 graph is made: its steps then launch the 11-field kernel alone,
+// which sweeps every subgrid itself when it runs alone (so a later change of
+// the species counts stays correct).
+int batch_unpaired(const hydro_batch *b, int32_t *out) {
+    std::vector<int32_t> ns((size_t)b->n_sub);
+    hipError_t e = hipMemcpy(ns.data(), b->n_species, ns.size() * sizeof(int32_t),
+                             hipMemcpyDefault);
+    if (e != hipSuccess) return fail_hip(e);
+    *out = 1;
+    for (int32_t v : ns)
+        if (v == 0) *out = 0;
+    return HYDRO_OK;
+}
 
 // Record the plan's step (the fused kernels of its launch shape) into a graph
 // and make it the plan's: a new executable graph, or an update of the one the
@@ -492,6 +508,10 @@ int hydro_plan_create(const hydro_params *params, const hydro_batch *batch, cons
     p->status = status;
     p->variant = hydro_selected_variant(batch->n_sub, 5);
     apply_variant(p->args, p->variant);
+    if ((rc = batch_unpaired(batch, &p->args.unpaired))) {
+        delete p;
+        return rc;
+    }
     if (fused_needs_scratch(p->args, p->variant)) {
         rc = alloc_scratch(fused_scratch_bytes(batch->n_sub), &p->scratch);
         if (rc) {
@@ -665,6 +685,7 @@ int hydro_rk3_create(const hydro_params *params, const hydro_batch *batch,
     ra.gsrc = map->src;
     ra.gmode = map->mode;
     const int variant = hydro_selected_variant(batch->n_sub, 5);
+    if ((rc = batch_unpaired(batch, &ra.unpaired))) return rc;
     hydro_rk3 *p = new (std::nothrow) hydro_rk3();
     if (!p) return HYDRO_EINVAL;
     if (fused_needs_scratch(ra, variant)) {

@@ -1443,13 +1443,15 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
 // ---- subgrids without species: two planes at a time ---------------------------
 //
 // A subgrid without species leaves the species wave of every role idle.  The
-// paired kernel (an instance of its own, so that its registers do not weigh
-// on the 11-field body) splits the eight waves into two groups of four roles:
-// group 0 (the first wave of each role) runs the plane schedule above on
-// plane k, group 1 (the second wave) on plane k + 1, so every SIMD carries two
-// hydro waves, and a step advances two planes.  Each group's sums keep the
-// order of the 11-field plan and every formula rounds as there, so the
-// results are the same bits.  The LDS plan (in doubles):
+// paired body splits the eight waves into two groups of four roles: group 0
+// (the first wave of each role) runs the plane schedule above on plane k,
+// group 1 (the second wave) on plane k + 1, so every SIMD carries two hydro
+// waves, and a step advances two planes.  Each group's sums keep the order of
+// the 11-field plan and every formula rounds as there, so the results are the
+// same bits.  It lives in a kernel instance of its own, beside the 11-field
+// body for the other subgrids; batches known to hold no subgrid without
+// species get the instance without it, whose registers it would crowd.
+// The LDS plan (in doubles):
 //   a window of 6 planes of the 6 hydro fields (planes k-2 .. k+3), one
 //   exchange area per group with 11-double points (V[0..5], v, p, c) and the
 //   group's flux-phase arrays inside it, the z partial carried to the next
@@ -1457,10 +1459,11 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
 //   group 1), and each group's z fluxes and x/y differences, kept for two
 //   steps (by the step's parity).
 // A plane's cells are updated once both of its z fluxes exist: plane k-2 (all
-// of whose terms are the last step's) in the first flux phase, plane k-1 in
-// the second, by group 0's z owner, which has just formed its upper flux.
-// Nothing is carried in registers from one step to the next but the window's
-// prefetched planes.  The face layers are formed by group 0 alone.
+// of whose terms are the last step's) by group 1's z owner in the first flux
+// phase, plane k-1 by group 0's z owner in the second, right after it forms
+// that plane's upper flux.  Nothing is carried in registers from one step to
+// the next but the window's prefetched planes.  The 9 z lines of a face
+// layer are produced by all eight waves and summed by group 0's z owner.
 namespace pr {
 constexpr int SL = 6;                       // window planes
 constexpr int SD = 6 * NPLANE + 2;          // one window plane, + a dummy word
@@ -1889,29 +1892,30 @@ __device__ __forceinline__ PairOut subgrid_pair(
 
 // ---- the kernel ---------------------------------------------------------------
 
-// Scratch of a step (32-bit words): [0] next work item, [1] workgroups done,
-// [3] number of subgrids listed for the paired kernel, [16, 16 + 2 n)
-// per-subgrid running max of the parts' face speeds (as 64-bit patterns of
-// non-negative doubles), then n status words, n arrival counts and the list
-// of subgrids for the paired kernel.  Every counter is back at zero when the
-// step ends (the last workgroup or part to finish clears what it used); the
-// list is rewritten by every step.
+// Scratch of the split and dynamic launch shapes (32-bit words): [0] next work
+// item, [1] workgroups done, [16, 16 + 2 n) per-subgrid running max of the
+// parts' face speeds (as 64-bit patterns of non-negative doubles), then n
+// status words and n arrival counts.  Every word is back at zero when the
+// launch ends (the last workgroup or part to finish clears what it used).
 __device__ __forceinline__ unsigned long long *sc_amax(uint32_t *sc) {
     return reinterpret_cast<unsigned long long *>(sc + 16);
 }
 __device__ __forceinline__ uint32_t *sc_bits(uint32_t *sc, int n) { return sc + 16 + 2 * n; }
 __device__ __forceinline__ uint32_t *sc_count(uint32_t *sc, int n) { return sc + 16 + 3 * n; }
-__device__ __forceinline__ uint32_t *sc_list(uint32_t *sc, int n) { return sc + 16 + 4 * n; }
 
+// LDS of an instance: the paired body's plan is the larger
+constexpr int lds_doubles(bool pair) { return pair && pr::END > LDS_D ? pr::END : LDS_D; }
+
+// PAIR: the instance that also holds the paired body, which sweeps the
+// subgrids without species when their parts hold at least two planes.
 template <bool VEL, bool CW, bool GATHER, bool PAIR = false>
 __global__ __launch_bounds__(NT, 2) void k_fused(FusedArgs a, const double *__restrict__ U,
                                                  double *Uo,
                                                  double *__restrict__ amax,
                                                  int32_t *__restrict__ status, int order) {
-    __shared__ double lds[PAIR ? pr::END : LDS_D];
+    __shared__ double lds[lds_doubles(PAIR)];
     __shared__ double red_pair[PAIR ? 8 : 1];
     __shared__ int red_bits[8];
-    __shared__ int last_out;         // this workgroup is the last to finish
     __shared__ int next_item[2];     // by parity of the iteration (no barrier between
                                      // one iteration's read and the next one's write)
     __shared__ int64_t g_toff[GATHER ? 27 : 1];    // ghost-map table of the current subgrid
@@ -1938,30 +1942,21 @@ __global__ __launch_bounds__(NT, 2) void k_fused(FusedArgs a, const double *__re
     // interior planes each, part q of subgrid s is item s P + q), fetched in
     // a static stride or, in the dynamic form, from a counter in scratch
     const int lp = a.log_parts, P = 1 << lp, span = NSUB >> lp;
+    const int n_items = a.n_sub << lp;
     uint32_t *sc = a.scratch;
-    // The paired kernel takes the subgrids the other kernel of the step passed
-    // over and listed (subgrids without species, when a.pairing is set).
-    int n_list = a.n_sub;
-    if constexpr (PAIR) n_list = (int)__builtin_amdgcn_readfirstlane(sc[3]);
-    const int n_items = n_list << lp;
-    if (PAIR && n_items == 0) return;      // the same for every workgroup
 
     int parity = 0;
     for (int it = blockIdx.x; it < n_items; parity ^= 1) {
         const int s0 = it >> lp, q = it & (P - 1);
-        const int i0 = order ? (n_list - 1 - s0) : s0;
-        const int s = PAIR ? (int)sc_list(sc, a.n_sub)[i0] : i0;
+        const int s = order ? (a.n_sub - 1 - s0) : s0;
         const int kb = NG - 1 + q * span, ke = kb + span + 1;
         const int nspec = a.n_species[s];
         const int64_t off = a.offset[s];
         const int64_t ooff = a.out_offset ? a.out_offset[s] : off;
         const bool bad = nspec < 0 || nspec > 5 || off < 0 || (off & 1) || ooff < 0 || (ooff & 1);
-        // left to the paired kernel, and listed for it once (by part 0)
-        const bool defer = !PAIR && a.pairing && nspec == 0;
-        if (defer && q == 0 && tid == 0) sc_list(sc, a.n_sub)[atomicAdd(&sc[3], 1u)] = (uint32_t)s;
         double amax_l = 0.0;
         int bits = 0;
-        if (!bad && !defer) {
+        if (!bad) {
             const double dtv = a.clock ? a.clock[1] : a.dt;
             const double lam = rate ? 1.0 / a.h[s] : dtv / a.h[s];
             Stage stg;
@@ -1972,24 +1967,18 @@ __global__ __launch_bounds__(NT, 2) void k_fused(FusedArgs a, const double *__re
             const double *Us0 = U + off;
             double *Os0 = Uo + ooff;
             const int fst0 = a.fstride;
-            if constexpr (PAIR) {
-                // a subgrid without species, swept in parts of at least two
-                // interior planes (the host pairs no other launch shape)
-                if (nspec != 0 || span < 2) {
-                    bits = HYDRO_STATUS_BADMETA;
-                } else {
-                    PairMeta pm;
-                    pm.gsrc = a.gsrc;
-                    pm.gmode = a.gmode;
-                    pm.n_species = a.n_species;
-                    pm.offset = a.offset;
-                    pm.n_sub = a.n_sub;
-                    const PairOut po = subgrid_pair<GATHER>(
-                        lds, tid, role, __builtin_amdgcn_readfirstlane(wave) >> 2, Us0, Os0, fst0,
-                        lam, rate, stg, sym, gamma, gm1, de, pm, s, U, g_toff, g_tmode, kb, ke);
-                    amax_l = po.amax;
-                    bits = po.bits;
-                }
+            if (PAIR && nspec == 0 && span >= 2) {
+                PairMeta pm;
+                pm.gsrc = a.gsrc;
+                pm.gmode = a.gmode;
+                pm.n_species = a.n_species;
+                pm.offset = a.offset;
+                pm.n_sub = a.n_sub;
+                const PairOut po = subgrid_pair<GATHER>(
+                    lds, tid, role, __builtin_amdgcn_readfirstlane(wave) >> 2, Us0, Os0, fst0,
+                    lam, rate, stg, sym, gamma, gm1, de, pm, s, U, g_toff, g_tmode, kb, ke);
+                amax_l = po.amax;
+                bits = po.bits;
             } else if (hyd) {
                 subgrid_body<true, VEL, CW, GATHER>(win, xch, zl, keep, run, tid, role, nspec, Us0,
                                                     Os0, fst0, lam, rate, stg, sym, cwmode, gamma,
@@ -2015,7 +2004,7 @@ __global__ __launch_bounds__(NT, 2) void k_fused(FusedArgs a, const double *__re
         if (a.dyn && tid == 0)
             next_item[parity] = (int)gridDim.x + (int)atomicAdd(&sc[0], 1u);
         lds_barrier();
-        if (tid == 0 && !defer) {
+        if (tid == 0) {
             double m = 0.0;
             int b = HYDRO_STATUS_BADMETA;
             if (!bad) {
@@ -2048,24 +2037,13 @@ __global__ __launch_bounds__(NT, 2) void k_fused(FusedArgs a, const double *__re
         }
         it = a.dyn ? next_item[parity] : it + (int)gridDim.x;
     }
-    if (a.dyn || PAIR) {
-        // the last workgroup out clears the counters (and, after the paired
-        // kernel, the list) for the next step
+    if (a.dyn) {
+        // the last workgroup out clears the counters for the next launch
         if (tid == 0) {
             __threadfence();
-            const bool last = atomicAdd(&sc[1], 1u) == gridDim.x - 1;
-            if (last) {
+            if (atomicAdd(&sc[1], 1u) == gridDim.x - 1) {
                 atomicExch(&sc[0], 0u);
                 atomicExch(&sc[1], 0u);
-            }
-            last_out = last;
-        }
-        if (PAIR) {
-            lds_barrier();
-            if (last_out) {
-                uint32_t *list = sc_list(sc, a.n_sub);
-                for (int i = tid; i < n_list; i += NT) list[i] = 0u;
-                if (tid == 0) atomicExch(&sc[3], 0u);
             }
         }
     }
@@ -2114,25 +2092,24 @@ int device_cus() {
 // carries neither.
 using FusedKernel = void (*)(FusedArgs, const double *, double *, double *, int32_t *, int);
 
+// Whether a step in variant v sweeps its subgrids without species in the
+// paired body: the default options, parts of at least two planes, and a batch
+// not known to hold none (the instance with both bodies spills a few more
+// registers than the 11-field one).
+bool pairs(const StepArgs &a, int v) {
+    return !a.unpaired && !a.vel && !a.steepen && !a.flatten && kVariants[v].log_parts < 3;
+}
+
 template <bool GATHER>
-FusedKernel fused_kernel_g(const StepArgs &a) {
+FusedKernel fused_kernel_g(const StepArgs &a, int v) {
     const bool cw = a.steepen || a.flatten;
     if (a.vel) return cw ? k_fused<true, true, GATHER> : k_fused<true, false, GATHER>;
-    return cw ? k_fused<false, true, GATHER> : k_fused<false, false, GATHER>;
+    if (cw) return k_fused<false, true, GATHER>;
+    return pairs(a, v) ? k_fused<false, false, GATHER, true> : k_fused<false, false, GATHER>;
 }
 
-FusedKernel fused_kernel(const StepArgs &a) {
-    return a.gsrc ? fused_kernel_g<true>(a) : fused_kernel_g<false>(a);
-}
-
-FusedKernel paired_kernel(const StepArgs &a) {
-    return a.gsrc ? k_fused<false, false, true, true> : k_fused<false, false, false, true>;
-}
-
-// Whether a step in variant v runs its subgrids without species in the
-// paired kernel: the default options, and parts of at least two planes.
-bool pairs(const StepArgs &a, int v) {
-    return !a.vel && !a.steepen && !a.flatten && kVariants[v].log_parts < 3;
+FusedKernel fused_kernel(const StepArgs &a, int v) {
+    return a.gsrc ? fused_kernel_g<true>(a, v) : fused_kernel_g<false>(a, v);
 }
 
 dim3 grid_of(const StepArgs &a, int v) {
@@ -2152,9 +2129,8 @@ const char *fused_variant_name(int v) {
 int fused_variant_order(int v) {
     return (v >= 0 && v < fused_variant_count()) ? kVariants[v].order : 0;
 }
-bool fused_needs_scratch(const StepArgs &a, int v) {
-    return v >= 0 && v < fused_variant_count() &&
-           (kVariants[v].log_parts > 0 || kVariants[v].dyn || pairs(a, v));
+bool fused_needs_scratch(const StepArgs &, int v) {
+    return v >= 0 && v < fused_variant_count() && (kVariants[v].log_parts > 0 || kVariants[v].dyn);
 }
 int64_t fused_scratch_bytes(int n_sub) { return fused_scratch_bytes_for(n_sub > 0 ? n_sub : 0); }
 
@@ -2189,15 +2165,9 @@ hipError_t launch_fused_step(const StepArgs &a0, const double *U_in, double *U_o
     if (a0.n_sub == 0) return hipSuccess;
     StepArgs a = a0;
     apply_variant(a, variant);
-    a.pairing = pairs(a, variant) ? 1 : 0;
     if (fused_needs_scratch(a, variant) && !a.scratch) return hipErrorInvalidValue;
-    // the 11-field kernel, then the paired one over the subgrids it listed
-    hipLaunchKernelGGL(fused_kernel(a), grid_of(a, variant), dim3(NT), 0, st, fused_args(a), U_in,
-                       U_out, amax, status, kVariants[variant].order);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !a.pairing) return e;
-    hipLaunchKernelGGL(paired_kernel(a), grid_of(a, variant), dim3(NT), 0, st, fused_args(a), U_in,
-                       U_out, amax, status, kVariants[variant].order);
+    hipLaunchKernelGGL(fused_kernel(a, variant), grid_of(a, variant), dim3(NT), 0, st,
+                       fused_args(a), U_in, U_out, amax, status, kVariants[variant].order);
     return hipGetLastError();
 }
 

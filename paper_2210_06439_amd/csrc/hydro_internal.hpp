@@ -64,13 +64,13 @@ struct StepArgs {
     // neighbours' interiors instead of the block's own ghost layers
     const int32_t *gsrc, *gmode;
     // launch shape of the fused step: each subgrid's z sweep in 2^log_parts
-    // parts (workgroups), items fetched from a counter when dyn; pairing: the
-    // subgrids without species are left to the paired kernel, which follows.
-    // Each needs scratch (fused_scratch_bytes), its counters zero between
-    // steps.
+    // parts (workgroups), items fetched from a counter when dyn; both need
+    // scratch (fused_scratch_bytes), all zero between launches.  unpaired:
+    // the batch is known to hold no subgrid without species (the kernel
+    // without the paired body serves it)
     int32_t log_parts;
     int32_t dyn;
-    int32_t pairing;
+    int32_t unpaired;
     uint32_t *scratch;
 };
 
@@ -98,7 +98,6 @@ struct FusedArgs {
     const int32_t *gsrc, *gmode;
     int32_t log_parts;
     uint32_t dyn : 1;
-    uint32_t pairing : 1;
     uint32_t *scratch;
 };
 
@@ -126,7 +125,6 @@ inline FusedArgs fused_args(const StepArgs &a) {
     f.gmode = a.gmode;
     f.log_parts = a.log_parts;
     f.dyn = a.dyn ? 1 : 0;
-    f.pairing = a.pairing ? 1 : 0;
     f.scratch = a.scratch;
     return f;
 }
@@ -155,7 +153,7 @@ inline StepArgs make_args(const hydro_params *p, const hydro_batch *b) {
     a.gmode = nullptr;
     a.log_parts = 0;
     a.dyn = 0;
-    a.pairing = 0;
+    a.unpaired = 0;
     a.scratch = nullptr;
     return a;
 }
@@ -173,11 +171,11 @@ hipError_t launch_plain_divergence(const StepArgs &a, const double *F, const int
 int fused_variant_count();
 const char *fused_variant_name(int v);
 // whether a step with a's options in variant v needs scratch, and how many
-// bytes it needs for n_sub subgrids (zero-filled before first use; the step
-// leaves its counters zero)
+// bytes it needs for n_sub subgrids (zero-filled before first use; the kernel
+// leaves it zero)
 bool fused_needs_scratch(const StepArgs &a, int v);
 int64_t fused_scratch_bytes(int n_sub);
-constexpr int64_t fused_scratch_bytes_for(int64_t n_sub) { return 64 + 20 * n_sub; }
+constexpr int64_t fused_scratch_bytes_for(int64_t n_sub) { return 64 + 16 * n_sub; }
 // the launch shape for n_sub subgrids when no tuned choice exists
 int fused_default_variant(int n_sub);
 // the variant's launch-shape fields of a (log_parts, dyn)

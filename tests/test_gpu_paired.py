@@ -1,9 +1,9 @@
-"""The paired kernel: subgrids without species are swept two planes per step
-by a kernel instance of their own, after the 11-field kernel has listed them.
-Its results are the 11-field body's bits (that body still sweeps them in the
-split-8 shape, whose parts hold single planes), in every launch shape and in
-the rate and Runge-Kutta stage forms; a mixed batch hands each such subgrid
-to it exactly once; and the list it reads is left zero for the next step."""
+"""The paired body: subgrids without species are swept two planes per step by
+a second body in the same launch.  Its results are the 11-field body's bits
+(that body still sweeps them in the split-8 shape, whose parts hold single
+planes), in every launch shape and in the rate and Runge-Kutta stage forms;
+in a mixed batch every subgrid's result is its result alone; and steps of
+different sizes on one stream leave each other's scratch alone."""
 import numpy as np
 import pytest
 
@@ -43,9 +43,9 @@ def test_mixed_batch_hands_each_subgrid_over_once():
 
 
 def test_scratch_is_left_clean_for_a_larger_batch():
-    """The list lies after the split shapes' per-subgrid counters: a later
-    step with more subgrids on the same stream reads those words as
-    counters, so each step must leave them zero."""
+    """A later step with more subgrids on the same stream reads the split
+    shapes' per-subgrid counters at other words, so each step must leave all
+    the words it used zero."""
     small = inputs.random_batch(6, seed=79, species=(0, 0))
     big = inputs.random_batch(9, seed=80, species=(0, 5))
     want = gpu_step(big, variant=_variant("persistent-1x"))
@@ -57,8 +57,8 @@ def test_scratch_is_left_clean_for_a_larger_batch():
 
 
 def test_rate_and_stage_forms_alone_and_in_a_batch():
-    """40 subgrids take the split-4 shape (paired), one alone split-8 (the
-    11-field body): the rate and the stage combination agree bitwise."""
+    """40 subgrids take the split-4 shape (paired body), one alone the split-8
+    shape (11-field body): the rate and the stage combination agree bitwise."""
     T = torch()
     b = inputs.random_batch(40, seed=81, species=(0, 0))
     rng = np.random.default_rng(82)
