@@ -89,8 +89,10 @@ def traffic_probe():
     db = hydro.DeviceBatch.from_inputs(b)
     U_out = db.U.clone()
     amax = torch.zeros(db.n_sub, dtype=torch.float64, device="cuda")
-    hydro.step(hydro.params(dt=b.dt), db.struct, db.U, U_out, amax)
+    plan = hydro.Plan(hydro.params(dt=b.dt), db.struct, db.U, U_out, amax)
+    plan.launch()
     torch.cuda.synchronize()
+    plan.close()
     src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
     src.fill_(1.0)
     dst = torch.empty_like(src)
@@ -449,6 +451,43 @@ def config4_run(torch, hydro, inputs, costmodel, n_launches):
     return out
 
 
+def six_field_run(torch, hydro, inputs, costmodel, b, kern11_ms, steps, warmup):
+    """Subgrids without species (6 fields): the 128^3 binary-star batch with
+    its species removed and the 64^3 blast, each captured in a plan and timed
+    as config 3; per-subgrid kernel time against config 3's (11 fields)."""
+    out = {}
+    t0 = time.perf_counter()
+    bs = inputs.pack_blocks([np.array(b.block(s))[:6] for s in range(b.n_sub)], b.h, dt=b.dt,
+                            name="binary-star-6")
+    log(f"6-field binary star packed in {time.perf_counter() - t0:.1f} s")
+    sedov = inputs.sedov(64)
+    per11 = kern11_ms * 1e3 / b.n_sub
+    for name, bb in (("binary_star_6_fields", bs), ("sedov64", sedov)):
+        dt = bb.dt if bb.dt > 0.0 else 1e-4
+        d = hydro.DeviceBatch.from_inputs(bb)
+        U_out = d.U.clone()
+        am = torch.zeros(d.n_sub, dtype=torch.float64, device="cuda")
+        st = torch.zeros(d.n_sub, dtype=torch.int32, device="cuda")
+        plan = hydro.Plan(hydro.params(dt=dt), d.struct, d.U, U_out, am, st)
+        _, per = timed_plan(plan, steps, warmup, torch)
+        plan.close()
+        ms = float(np.mean(per))
+        flops = costmodel.cost(bb.n_species)[0]
+        out[name] = {"subgrids": bb.n_sub, "kernel_ms": ms,
+                     "per_subgrid_us": ms * 1e3 / bb.n_sub,
+                     "per_subgrid_vs_11_fields": ms * 1e3 / bb.n_sub / per11,
+                     "cell_updates_per_s": bb.cell_updates / (ms * 1e-3),
+                     "alu_frac": flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                     "variant": hydro.variant_name(hydro.selected_variant(bb.n_sub)),
+                     "nonzero_status": int(st.any().item())}
+        log(f"{name}: kernel {ms:.3f} ms, {out[name]['per_subgrid_us']:.3f} us per subgrid "
+            f"({out[name]['per_subgrid_vs_11_fields']:.3f} of config 3's)")
+        del d, U_out
+    out["config3_per_subgrid_us"] = per11
+    torch.cuda.empty_cache()
+    return out
+
+
 def single_subgrid_latency(torch, hydro, inputs, reps=200):
     """Config 1: one subgrid per launch, eager and replayed from a plan; HIP
     events around each launch."""
@@ -585,6 +624,10 @@ def main():
                     help="one fused step and a calibration copy, for counter runs")
     ap.add_argument("--only-config4", action="store_true",
                     help="the config-4 launches alone (for a kernel trace of them)")
+    ap.add_argument("--no-six-field", action="store_true")
+    ap.add_argument("--only-six-field", action="store_true",
+                    help="config 3, then its 6-field form and the 64^3 blast, timed alone "
+                         "(for a kernel trace of them)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the hydro stage is measured on a single "
@@ -629,6 +672,12 @@ def main():
         + f" -> {hydro.variant_name(best)}")
     plan = hydro.Plan(prm, db.struct, db.U, U_out, amax, status)
     wall, per = timed_plan(plan, args.steps, args.warmup, torch)
+    if args.only_six_field:
+        plan.close()
+        print(json.dumps({"six_field": six_field_run(torch, hydro, inputs, costmodel, b,
+                                                     float(np.mean(per)), args.steps,
+                                                     args.warmup)}), flush=True)
+        return
     st = status.cpu().numpy()
     if np.any(st != 0):
         log(f"WARNING: nonzero status words: {np.unique(st)}")
@@ -696,6 +745,9 @@ def main():
     }
     if variants is not None:
         result["variants"] = variants
+    if not args.no_six_field:
+        result["six_field"] = six_field_run(torch, hydro, inputs, costmodel, b, kern_ms,
+                                            max(20, args.steps // 4), args.warmup)
     if not args.no_plain:
         # the same comparison on the 128^3 batch (4096 subgrids), one timed pass
         result["per_subgrid_vs_batched_config3"] = per_subgrid_vs_batched(torch, hydro, b, db,
