@@ -2,8 +2,10 @@
 a second body in the same launch.  Its results are the 11-field body's bits
 (that body still sweeps them in the split-8 shape, whose parts hold single
 planes), in every launch shape and in the rate and Runge-Kutta stage forms;
-in a mixed batch every subgrid's result is its result alone; and steps of
-different sizes on one stream leave each other's scratch alone."""
+in a mixed batch every subgrid's result is its result alone; steps of
+different sizes on one stream leave each other's scratch alone; and plans,
+which pick their instance from the species counts at creation, replay the
+eager results, also after the counts change."""
 import numpy as np
 import pytest
 
@@ -83,3 +85,62 @@ def test_rate_and_stage_forms_alone_and_in_a_batch():
         R1, O1 = run(one, U0one)
         assert np.array_equal(one.interior(0, R1), b.interior(s, Rb)), s
         assert np.array_equal(one.interior(0, O1), b.interior(s, Ob)), s
+
+
+def _plan_run(T, db, dt, replays=2):
+    U_out = db.U.clone()
+    amax = T.zeros(db.n_sub, dtype=T.float64, device="cuda")
+    status = T.zeros(db.n_sub, dtype=T.int32, device="cuda")
+    plan = hydro.Plan(hydro.params(dt=dt), db.struct, db.U, U_out, amax, status)
+    outs = []
+    for _ in range(replays):
+        U_out.fill_(0.0)
+        plan.launch()
+        T.cuda.synchronize()
+        outs.append((U_out.cpu().numpy(), amax.cpu().numpy(), status.cpu().numpy()))
+    return plan, outs
+
+
+def test_plan_with_the_paired_body_matches_eager():
+    """140 subgrids, some without species: the plan takes the instance with
+    the paired body (the one-sweep shape), its replays equal the eager step."""
+    T = torch()
+    b = inputs.random_batch(140, seed=83, species=(0, 5))
+    assert (b.n_species == 0).any()
+    want = gpu_step(b)
+    plan, outs = _plan_run(T, device_batch(b), b.dt)
+    plan.close()
+    for got in outs:
+        for s in range(b.n_sub):
+            assert np.array_equal(b.interior(s, got[0]), b.interior(s, want[0])), s
+        assert np.array_equal(got[1], want[1]) and np.array_equal(got[2], want[2])
+
+
+def test_plan_without_the_paired_body_stays_correct_after_counts_change():
+    """A plan made while every subgrid had species takes the instance without
+    the paired body; species counts rewritten to 0 afterwards are swept by its
+    11-field body, with the same bits as an eager step on the new counts
+    (which pairs those subgrids)."""
+    T = torch()
+    b = inputs.random_batch(140, seed=84, species=(5,))
+    db = device_batch(b)
+    U_plan = db.U.clone()
+    am_p = T.zeros(db.n_sub, dtype=T.float64, device="cuda")
+    st_p = T.zeros(db.n_sub, dtype=T.int32, device="cuda")
+    plan = hydro.Plan(hydro.params(dt=b.dt), db.struct, db.U, U_plan, am_p, st_p)
+    ns = b.n_species.copy()
+    ns[::3] = 0
+    db.n_species.copy_(T.as_tensor(ns).cuda())
+    plan.launch()
+    T.cuda.synchronize()
+    plan.close()
+    U_e = db.U.clone()
+    am_e = T.zeros(db.n_sub, dtype=T.float64, device="cuda")
+    st_e = T.zeros(db.n_sub, dtype=T.int32, device="cuda")
+    hydro.step(hydro.params(dt=b.dt), db.struct, db.U, U_e, am_e, st_e)
+    T.cuda.synchronize()
+    got, want = U_plan.cpu().numpy(), U_e.cpu().numpy()
+    for s in range(b.n_sub):
+        assert np.array_equal(b.interior(s, got), b.interior(s, want)), s
+    assert np.array_equal(am_p.cpu().numpy(), am_e.cpu().numpy())
+    assert np.array_equal(st_p.cpu().numpy(), st_e.cpu().numpy())
