@@ -1655,16 +1655,19 @@ __device__ __forceinline__ PairOut subgrid_pair(
         acc_zero(acc[0], true);
         acc_zero(acc[1], true);
         if (layer) {
-            // the 9 z lines of the face layer: lines 0-7 by the eight waves,
-            // then line 8; group 0's z owner sums them in line order
+            // the 9 z lines of the face layer in one round: lines 0-7 by the
+            // eight waves, line 8 also by group 0's z owner (into a free slot
+            // of group 1's area), which then sums them in line order
             const bool bottom = k == kb;
             constexpr uint32_t zw = zline_wcodes();
-#pragma unroll 1
-            for (int r = 0; r < 2; r++) {
+            {
                 LANE_GEOMETRY();
-                const int t = role + 4 * grp + 8 * r;
-                double *pp = xg + role * pr::SLOT + lane;
-                if (t < 9) {
+                const bool zo = role == 2 && grp == 0;
+                double *x8 = lds + pr::X0 + pr::XG + 4 * pr::SLOT + lane;
+#pragma unroll 1
+                for (int u = 0; u < (zo ? 2 : 1); u++) {
+                    const int t = u == 0 ? role + 4 * grp : 8;
+                    double *pp = u == 0 ? xg + role * pr::SLOT + lane : x8;
                     const int dc = (int)(zline_dirs() >> (6 * t)) & 63;
                     const int dx = (dc & 3) - 1, dy = ((dc >> 2) & 3) - 1, dz = (dc >> 4) - 1;
                     const Line5 l = pr::line5(ci, cj, k, dx, dy, dz);
@@ -1676,24 +1679,21 @@ __device__ __forceinline__ PairOut subgrid_pair(
                             win, l, pp, pp, gamma, gm1, de, bits, cw0);
                 }
                 lds_barrier();
-                if (role == 2 && grp == 0) {
-                    const int nw = r == 0 ? 2 : 1;          // groups of four lines
+                if (zo) {
 #pragma unroll 1
-                    for (int g = 0; g < nw; g++) {
+                    for (int g = 0; g < 2; g++) {
                         const double *xs = lds + pr::X0 + g * pr::XG + lane;
                         HPt q[4];
 #pragma unroll
                         for (int w = 0; w < 4; w++) q[w] = load_h<pr::VX>(xs + w * pr::SLOT, 2);
 #pragma unroll
-                        for (int w = 0; w < 4; w++) {
-                            const int t2 = w + 4 * g + 8 * r;
-                            if (t2 < 9)
-                                acc_h_vals(acc[0], q[w].V, q[w].un, q[w].p, q[w].cs,
-                                           simpson_wc((zw >> (2 * t2)) & 3));
-                        }
+                        for (int w = 0; w < 4; w++)
+                            acc_h_vals(acc[0], q[w].V, q[w].un, q[w].p, q[w].cs,
+                                       simpson_wc((zw >> (2 * (w + 4 * g))) & 3));
                     }
+                    const HPt q8 = load_h<pr::VX>(x8, 2);
+                    acc_h_vals(acc[0], q8.V, q8.un, q8.p, q8.cs, simpson_wc((zw >> 16) & 3));
                 }
-                lds_barrier();
             }
             LANE_GEOMETRY();
             if (bottom) {
