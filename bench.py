@@ -16,6 +16,7 @@ Prints ONE JSON line.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -202,7 +203,27 @@ def subgrid16_plain(torch, hydro, inputs, reps=5):
     out["cell_updates_per_s"] = db.n_sub * 16 ** 3 / (total * 1e-3)
     log(f"plain stages at 16^3: {total:.3f} ms per stage "
         f"({out['cell_updates_per_s']:.3e} cell-updates/s)")
-    del Q, F, U_out, db
+    # the fused step of the 16^3 build: each subgrid's eight 8^3 tiles
+    # gathered, stepped by the 8^3 fused kernel and scattered back
+    L = hydro.lib(16)
+    status = torch.zeros(db.n_sub, dtype=torch.int32, device="cuda")
+    fused = lambda: L.hydro_step(ctypes.byref(prm), ctypes.byref(db.struct), hydro._ptr(db.U),
+                                 hydro._ptr(U_out), hydro._ptr(amax), hydro._ptr(status), None)
+    assert fused() == 0
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fused()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fms = e0.elapsed_time(e1) / reps
+    out["fused_ms"] = fms
+    out["fused_cell_updates_per_s"] = db.n_sub * 16 ** 3 / (fms * 1e-3)
+    out["fused_nonzero_status"] = int(status.any().item())
+    log(f"fused step at 16^3 (8^3 tiles): {fms:.3f} ms ({out['fused_cell_updates_per_s']:.3e} "
+        f"cell-updates/s)")
+    del Q, F, U_out, db, status
     torch.cuda.empty_cache()
     return out
 

@@ -1,7 +1,8 @@
 """Build the gfx950 hydro library for both subgrid sizes:
 hipcc -> paper_2210_06439_amd/libhydro.so (8^3 subgrids, every entry point)
-and paper_2210_06439_amd/libhydro_n16.so (16^3 subgrids: the plain stages and
-the time-integration helpers; the fused kernel is written for 8^3).
+and paper_2210_06439_amd/libhydro_n16.so (16^3 subgrids: the plain stages,
+the time-integration helpers, and the fused step run on the eight 8^3 tiles of
+each subgrid, with the fused kernel compiled for 8^3 in that library too).
 
 Usage: python -m paper_2210_06439_amd.build  (always recompiles)
 """
@@ -16,8 +17,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libhydro.so")
+# a source given as (file, n) is compiled for subgrid size n in that library
 SIZES = {8: ["api.hip", "plain.hip", "fused.hip", "evolve.hip"],
-         16: ["api.hip", "plain.hip", "evolve.hip", "fused_absent.hip"]}
+         16: ["api.hip", "plain.hip", "evolve.hip", "tiles.hip", ("fused.hip", 8)]}
 SOURCES = SIZES[8]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -41,9 +43,10 @@ def build(verbose: bool = False) -> str:
         bdir = os.path.join(BUILD, f"n{n}")
         os.makedirs(bdir, exist_ok=True)
         objs = []
-        for src in sources:
+        for entry in sources:
+            src, sn = (entry, n) if isinstance(entry, str) else entry
             obj = os.path.join(bdir, src.replace(".hip", ".o"))
-            cmd = [HIPCC, *FLAGS, f"-DHYDRO_SUBGRID_N={n}", "-c", os.path.join(CSRC, src),
+            cmd = [HIPCC, *FLAGS, f"-DHYDRO_SUBGRID_N={sn}", "-c", os.path.join(CSRC, src),
                    "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)

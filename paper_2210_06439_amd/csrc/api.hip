@@ -297,6 +297,7 @@ int64_t hydro_workspace_bytes(void) {
     int64_t total = 0;
     for (auto &kv : g_ws)
         if (kv.first.first == dev) total += kv.second.bytes;
+    if constexpr (NSUB == 16) total += tiled_work_bytes(dev);
     return total;
 }
 int hydro_subgrid_n(void) { return NSUB; }
@@ -382,8 +383,21 @@ int hydro_selected_variant(int n_sub, int max_species) {
 int hydro_step(const hydro_params *params, const hydro_batch *batch, const double *U_in,
                double *U_out, double *amax, int32_t *status, void *stream) {
     if (!batch) return HYDRO_EINVAL;
-    return hydro_step_variant(params, batch, U_in, U_out, amax, status,
-                              hydro_selected_variant(batch->n_sub, 5), stream);
+    if constexpr (NSUB == 16) {
+        // the eight 8^3 tiles of every subgrid through the 8^3 fused kernel
+        int rc = check_common(params, batch);
+        if (rc) return rc;
+        if (batch->n_sub == 0) return HYDRO_OK;
+        if (!U_in || !U_out || !amax || U_in == U_out || !aligned8(U_in) || !aligned8(U_out))
+            return HYDRO_EINVAL;
+        if ((rc = check_device())) return rc;
+        hipError_t e = launch_tiled_step(make_args(params, batch), U_in, U_out, amax, status,
+                                         stream);
+        return e == hipSuccess ? HYDRO_OK : fail_hip(e);
+    } else {
+        return hydro_step_variant(params, batch, U_in, U_out, amax, status,
+                                  hydro_selected_variant(batch->n_sub, 5), stream);
+    }
 }
 
 int hydro_step_noalloc(const hydro_params *params, const hydro_batch *batch,

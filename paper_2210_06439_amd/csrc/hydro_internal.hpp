@@ -182,6 +182,12 @@ int fused_default_variant(int n_sub);
 void apply_variant(StepArgs &a, int v);
 hipError_t launch_fused_step(const StepArgs &a, const double *U_in, double *U_out,
                              double *amax, int32_t *status, int variant, hipStream_t st);
+// The fused step of the 16^3 build (tiles.hip): each subgrid's eight 8^3 tiles
+// gathered into work buffers of the stream, stepped by the 8^3 fused kernel
+// (compiled into that library for 8^3) and scattered back.
+hipError_t launch_tiled_step(const StepArgs &a, const double *U_in, double *U_out, double *amax,
+                             int32_t *status, void *stream);
+int64_t tiled_work_bytes(int dev);   // work buffers held on device dev
 // Device-resident time integration (evolve.hip).
 hipError_t launch_fill_ghosts(int n_sub, int fstride, const int64_t *offset,
                               const int32_t *n_species, const int32_t *src, const int32_t *mode,

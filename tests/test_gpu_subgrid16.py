@@ -1,16 +1,19 @@
 """The library built for 16^3 subgrids (libhydro_n16.so; the subgrid size is
 a compile-time choice, Sec. II "Data-Structure") against the oracle built for
 the same size: the plain stages bitwise, with every method option; the
-entropy-tracer re-sync, the ghost fill and the stage combination; and the
-refusal of the fused entry points, whose kernel is written for 8^3."""
+fused step, which runs each subgrid's eight 8^3 tiles through the 8^3 fused
+kernel (bitwise the 8^3 library on those tiles, and within the parity
+tolerance of the 16^3 oracle); the entropy-tracer re-sync, the ghost fill and
+the stage combination; and the refusal of the other fused entry points."""
 import ctypes
 
 import numpy as np
 import pytest
 
 import oracle
-from gpu_util import torch
-from paper_2210_06439_amd import hydro
+from gpu_util import gpu_step, torch
+from metrics import max_err_step
+from paper_2210_06439_amd import hydro, inputs
 from test_oracle_subgrid16 import _interior, _pack, _padded_field
 
 pytestmark = pytest.mark.gpu
@@ -73,7 +76,59 @@ def test_plain_stages_bitwise(flags):
     assert np.array_equal(ag, ar)
 
 
-def test_fused_entry_points_refuse_the_16_build():
+def _fused16(db, dt, flags=0):
+    T = torch()
+    L = hydro.lib(N)
+    out = db.U.clone()
+    amax = T.zeros(db.n_sub, dtype=T.float64, device="cuda")
+    status = T.zeros(db.n_sub, dtype=T.int32, device="cuda")
+    prm = hydro.params(dt=dt, flags=flags)
+    assert L.hydro_step(ctypes.byref(prm), ctypes.byref(db.struct), hydro._ptr(db.U),
+                        hydro._ptr(out), hydro._ptr(amax), hydro._ptr(status), None) == 0
+    T.cuda.synchronize()
+    return out.cpu().numpy(), amax.cpu().numpy(), status.cpu().numpy()
+
+
+@pytest.mark.parametrize("flags", [0, SYM | VEL, ST | FL])
+def test_fused_step_16_is_its_tiles_step(flags):
+    """The 16^3 fused step against the 8^3 library on the eight tiles of each
+    subgrid (bitwise: interiors, the largest speed over the tiles, status),
+    and against the 16^3 oracle within the parity tolerance."""
+    U, off, h, ns, fs = _batch()
+    dt = 2e-4
+    Ug, ag, sg = _fused16(_device(U, off, h, ns, fs), dt, flags)
+    tiles, th = [], []
+    for s in range(len(off)):
+        nf = 6 + int(ns[s])
+        blk = np.stack([U[off[s] + f * fs:off[s] + f * fs + NB ** 3].reshape(NB, NB, NB)
+                        for f in range(nf)])
+        for bz in (0, 1):
+            for by in (0, 1):
+                for bx in (0, 1):
+                    tiles.append(blk[:, bz * 8:bz * 8 + 14, by * 8:by * 8 + 14,
+                                     bx * 8:bx * 8 + 14].copy())
+                    th.append(h[s])
+    tb = inputs.pack_blocks(tiles, th, dt=dt)
+    Ut, at, st = gpu_step(tb, flags=flags)
+    Ur, ar, sr = oracle.step(U, off, h, ns, fs, dt, flags=flags, n=N)
+    Urt, art, srt = oracle.step(tb.U, tb.offset, tb.h, tb.n_species, tb.fstride, dt, flags=flags)
+    for s in range(len(off)):
+        nf = 6 + int(ns[s])
+        g = _interior(Ug, off, fs, nf, N, s)
+        r = _interior(Ur, off, fs, nf, N, s)
+        for q in range(8):
+            bz, by, bx = q >> 2, (q >> 1) & 1, q & 1
+            sl = np.s_[:, bz * 8:bz * 8 + 8, by * 8:by * 8 + 8, bx * 8:bx * 8 + 8]
+            assert np.array_equal(g[sl], tb.interior(8 * s + q, Ut)), (s, q)
+            # the 16^3 oracle is its tiles' 8^3 oracle (the locality pin)
+            assert np.array_equal(r[sl], tb.interior(8 * s + q, Urt)), (s, q)
+        assert ag[s] == np.max(at[8 * s:8 * s + 8])
+        assert sg[s] == np.bitwise_or.reduce(st[8 * s:8 * s + 8])
+    assert max_err_step(tb, Ut, Urt) <= 1e-12
+    assert np.max(np.abs(ag - ar) / ar) <= 1e-13 and np.array_equal(sg, sr)
+
+
+def test_other_fused_entry_points_refuse_the_16_build():
     T = torch()
     U, off, h, ns, fs = _batch()
     db = _device(U, off, h, ns, fs)
@@ -81,11 +136,10 @@ def test_fused_entry_points_refuse_the_16_build():
     out = db.U.clone()
     amax = T.zeros(db.n_sub, dtype=T.float64, device="cuda")
     prm = hydro.params(dt=1e-4)
-    assert L.hydro_step(ctypes.byref(prm), ctypes.byref(db.struct), hydro._ptr(db.U),
-                        hydro._ptr(out), hydro._ptr(amax), None, None) == EINVAL
+    assert L.hydro_step_variant(ctypes.byref(prm), ctypes.byref(db.struct), hydro._ptr(db.U),
+                                hydro._ptr(out), hydro._ptr(amax), None, 1, None) == EINVAL
     assert L.hydro_rate(ctypes.byref(prm), ctypes.byref(db.struct), hydro._ptr(db.U),
                         hydro._ptr(out), hydro._ptr(amax), None, None) == EINVAL
-    assert L.hydro_variant_count() == 0
     T.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy(), U)
 
