@@ -1480,8 +1480,13 @@ constexpr int ZX = ZL + NH * 64;            // [NH][64]
 constexpr int FZ = ZX + NH * 64;            // [parity][group][6][64] z fluxes
 constexpr int KP = FZ + 4 * 6 * 64;         // [parity][group][6][64] x/y differences
 constexpr int END = KP + 4 * 6 * 64;
-__device__ __forceinline__ int fz(int par, int g, int f) { return FZ + ((par * 2 + g) * 6 + f) * 64; }
-__device__ __forceinline__ int kp(int par, int g, int f) { return KP + ((par * 2 + g) * 6 + f) * 64; }
+// offsets of field f of group g's z fluxes and x/y differences of step parity par
+__device__ __forceinline__ int fz(int par, int g, int f) {
+    return FZ + ((par * 2 + g) * 6 + f) * 64;
+}
+__device__ __forceinline__ int kp(int par, int g, int f) {
+    return KP + ((par * 2 + g) * 6 + f) * 64;
+}
 static_assert(LL + 2 * RST <= XF && XF + 6 * RST <= XG, "a group's flux arrays");
 static_assert(4 * SLOT <= XF, "round 0 writes below the face fluxes (slots of roles 0 and 1)");
 static_assert(END * 8 + 512 <= 163840, "paired LDS plan");
@@ -1497,25 +1502,6 @@ __device__ __forceinline__ Line5 line5(int i, int j, int k, int dx, int dy, int 
     return l;
 }
 
-// the cell update from the summed flux difference (as update_cell_sum, with
-// the cell's old values given); plane kc of the window, its x/y difference at
-// d, its upper and lower z fluxes at fu (or in Fu) and fl
-__device__ __forceinline__ void update(const double *u, const double *dsum, int kc, int ci, int cj,
-                                       double lam, bool rate, const Stage &stg, double *Os,
-                                       int fst, double &chk) {
-    const int cidx = opaque_v(kc * NPLANE + cj * NB + ci);
-    const int fs = fst;
-#pragma unroll
-    for (int f = 0; f < 6; f++) {
-        double v = (rate ? 0.0 : u[f]) - lam * dsum[f];
-        if (stg.U0) {
-            const double u0 = stg.U0[f * fs + cidx];
-            v = stg.identity ? u0 : fma(stg.c0, u0, stg.c1 * v);
-        }
-        chk = fma(v, 0.0, chk);
-        Os[f * fs + cidx] = v;
-    }
-}
 // The update of plane kc's cell (ci, cj) of the window: its x/y difference at
 // lds + d, the upper z fluxes Fu and the lower at lds + fl (fields 64 apart),
 // summed in the order of the 11-field plan.
@@ -1561,8 +1547,8 @@ __device__ __forceinline__ PairOut subgrid_pair(
     double *lds, int tid, int role, int grp, const double *Us0, double *Os0, int fst0, double lam,
     bool rate, Stage stg, bool sym, double gamma, double gm1, double de, PairMeta a, int s,
     const double *Ug, int64_t *toff, int *tmode, int kb_, int ke_) {
-    // uniform values as scalars (the subgrid index comes from a list load),
-    // so that branches and addresses derived from them stay scalar
+    // uniform values as scalars, so that branches and addresses derived from
+    // them stay scalar
     role = __builtin_amdgcn_readfirstlane(role);
     grp = __builtin_amdgcn_readfirstlane(grp);
     fst0 = __builtin_amdgcn_readfirstlane(fst0);
