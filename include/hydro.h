@@ -250,8 +250,10 @@ const char *hydro_strerror(int code);
  * hydro_step_variant, hydro_step_io, hydro_step_gather, hydro_rate,
  * hydro_rk_stage, hydro_autotune) use one such buffer per (device, stream),
  * allocated (hipMalloc, synchronously zero-filled) the first time a launch on
- * that stream needs it and grown when a larger batch needs more, so that
- * first call must not be made while the stream is being captured; launches
+ * that stream needs it, for at least 65536 subgrids (about 1 MiB), and grown
+ * (to at least twice its size, after synchronizing the stream) only when a
+ * larger batch needs more, so that first call must not be made while the
+ * stream is being captured; launches
  * on one stream run in order and share it.  Plans and RK3 graphs allocate
  * their own at creation and free it when destroyed.  Every other buffer
  * (the unfused form's Q and F, the time integration's work buffers) belongs

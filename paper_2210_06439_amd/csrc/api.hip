@@ -113,10 +113,14 @@ void tune_save_locked() {
 // ---- scratch of the split and dynamic launch shapes -----------------------
 //
 // The library keeps one scratch buffer per (device, stream) for the eager
-// calls, grown on demand and zero-filled when allocated (the kernel leaves it
-// zero after every launch).  Plans and RK3 graphs own their own.  The first
-// call that needs scratch on a stream allocates it, so that call must not be
-// made while the stream is being captured.
+// calls, zero-filled when allocated (the kernel leaves it zero after every
+// launch).  Plans and RK3 graphs own their own.  The first call that needs
+// scratch on a stream allocates it, so that call must not be made while the
+// stream is being captured.  That first buffer covers kScratchMinSub
+// subgrids (about 1 MiB), so a stream whose batch sizes vary (a serving
+// loop's ticks) does not grow it: growing synchronizes the stream and frees
+// the old buffer, a stall of the whole loop.  Beyond that it grows to at
+// least twice its size.
 
 struct Scratch {
     uint32_t *ptr = nullptr;
@@ -125,6 +129,7 @@ struct Scratch {
 
 std::mutex g_ws_mu;
 std::map<std::pair<int, void *>, Scratch> g_ws;
+constexpr int kScratchMinSub = 65536;
 
 int alloc_scratch(int64_t bytes, uint32_t **out) {
     void *p = nullptr;
@@ -155,7 +160,10 @@ int stream_scratch(void *stream, int n_sub, uint32_t **out) {
             w.ptr = nullptr;
             w.bytes = 0;
         }
-        int64_t bytes = need < 4096 ? 4096 : need;
+        const int64_t old = w.bytes;
+        int64_t bytes = fused_scratch_bytes(kScratchMinSub);
+        if (bytes < 2 * old) bytes = 2 * old;
+        if (bytes < need) bytes = need;
         int rc = alloc_scratch(bytes, &w.ptr);
         if (rc) return rc;
         w.bytes = bytes;

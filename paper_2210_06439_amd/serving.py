@@ -302,6 +302,8 @@ class GpuBackend:
     every tick (hydro_params.flags).
     """
 
+    IDX_RING = 8
+
     def __init__(self, n_slots: int, catalogue=None, gamma=5.0 / 3.0, de_switch=1e-3,
                  nf_max: int = NF_MAX, fstride: int = FSTRIDE, flags: int = 0,
                  max_lanes: int = 2):
@@ -328,11 +330,17 @@ class GpuBackend:
         self.copy = torch.cuda.Stream()
         self._load_ev = None
         self.tick_log = []      # per retired tick: (subgrids, GPU start s, GPU end s)
-        # pinned staging for the gather indices of one load call (catalogue
-        # rows, then the two copies' slot rows) and its device twin
-        self._idx_h = torch.empty(3 * self.n_slots, dtype=torch.int64, pin_memory=True)
+        # pinned staging for the gather indices of a load call (catalogue
+        # rows, then the two copies' slot rows), a ring of them, and their
+        # device twin.  A load call reuses the oldest pinned buffer once its
+        # copy has run; the copy stream's gathers wait for CUs that a tick's
+        # persistent kernel holds, so with a single buffer the host would
+        # wait for a whole tick there, launching and retiring nothing.
+        self._idx_h = [torch.empty(3 * self.n_slots, dtype=torch.int64, pin_memory=True)
+                       for _ in range(self.IDX_RING)]
+        self._idx_ev = [None] * self.IDX_RING
+        self._idx_next = 0
         self._idx_d = torch.empty(3 * self.n_slots, dtype=torch.int64, device=dev)
-        self._idx_ev = None
         # ring of metadata buffers: two ticks in flight per lane, one being filled
         n = 2 * self.n_slots
         self.ring = []
@@ -407,19 +415,23 @@ class GpuBackend:
                                            and s.req.source.dtype.kind == "f")]
         with torch.cuda.stream(self.copy):
             if cat:
-                if self._idx_ev is not None:
-                    self._idx_ev.synchronize()          # the pinned index buffer is free
+                q = self._idx_next
+                self._idx_next = (q + 1) % self.IDX_RING
+                if self._idx_ev[q] is not None:
+                    self._idx_ev[q].synchronize()       # this pinned index buffer is free
                 m = int(sum(s.req.n for s in cat))
-                ih = self._idx_h.numpy()
+                ih = self._idx_h[q].numpy()
                 np.concatenate([np.asarray(s.req.source, dtype=np.int64) for s in cat],
                                out=ih[:m])
                 slots = np.concatenate([s.slots for s in cat])
                 ih[m:2 * m] = slots
                 ih[2 * m:3 * m] = slots + self.n_slots
                 idx = self._idx_d[:3 * m]
-                idx.copy_(self._idx_h[:3 * m], non_blocking=True)
-                self._idx_ev = torch.cuda.Event()
-                self._idx_ev.record(self.copy)
+                # the device twin is rewritten by the next call's copy, behind
+                # this call's gathers on the same stream
+                idx.copy_(self._idx_h[q][:3 * m], non_blocking=True)
+                self._idx_ev[q] = torch.cuda.Event()
+                self._idx_ev[q].record(self.copy)
                 blk = self.catalogue.U.view(-1, self.slot_elems).index_select(0, idx[:m])
                 rows.index_copy_(0, idx[m:2 * m], blk)
                 rows.index_copy_(0, idx[2 * m:3 * m], blk)
