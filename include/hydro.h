@@ -232,6 +232,26 @@ int hydro_step_io(const hydro_params *params, const hydro_batch *batch,
                   const int64_t *out_offset, const double *U_in, double *U_out,
                   double *amax, int32_t *status, void *stream);
 
+/*
+ * hydro_copy_blocks -- n row copies between device buffers whose rows are
+ * row_elems doubles each: row src_row[i] of src (a buffer of src_rows rows)
+ * is read once and written to row dst_row0[i] and, when dst_row1 is not
+ * NULL, row dst_row1[i] of dst (dst_rows rows).  This is how a serving loop
+ * moves new requests' subgrid blocks (Sec. II, "Data-Structure": a subgrid
+ * with its ghost layers is one contiguous block) from a resident catalogue
+ * into both copies of their pool slots.  src_row, dst_row0 and dst_row1 are
+ * device arrays of n int64.  A pair whose source index lies outside
+ * [0, src_rows) writes nothing; a destination index outside [0, dst_rows) is
+ * not written.  Destination rows must not overlap source rows and no two
+ * pairs may write the same row (neither is checked).  HYDRO_EINVAL for
+ * n < 0, row_elems < 1, negative row counts, n * ceil(row_elems / 2048) above
+ * 2^31 - 1, or a null src, dst, src_row or dst_row0 when n > 0.  Asynchronous
+ * on `stream`.
+ */
+int hydro_copy_blocks(const double *src, int64_t src_rows, const int64_t *src_row,
+                      double *dst, int64_t dst_rows, const int64_t *dst_row0,
+                      const int64_t *dst_row1, int n, int64_t row_elems, void *stream);
+
 /* Element counts of one subgrid's Q and F regions: 26*nf*1000 and 3*nf*576
  * (26*nf*(N+2)^3 and 3*nf*(N+1)*N*N for subgrid size N). */
 int64_t hydro_q_elems(int n_species);

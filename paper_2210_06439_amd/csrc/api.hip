@@ -210,6 +210,45 @@ __global__ void k_clear_words(uint32_t *p, int64_t n) {
         p[i] = 0u;
 }
 
+// ---- block copies (hydro_copy_blocks) ---------------------------------------
+//
+// Workgroup g copies chunk g % chunks of pair g / chunks: one read of the
+// source row's chunk, written to one or two destination rows.  vec2: rows and
+// buffers 16-byte aligned, so the chunk moves as double2.
+constexpr int kCopyThreads = 256;
+constexpr int64_t kCopyChunk = 2048;      // doubles per workgroup
+
+__global__ __launch_bounds__(kCopyThreads) void k_copy_blocks(
+    const double *__restrict__ src, int64_t src_rows, const int64_t *__restrict__ src_row,
+    double *__restrict__ dst, int64_t dst_rows, const int64_t *__restrict__ d0,
+    const int64_t *__restrict__ d1, int64_t row_elems, int chunks, int vec2) {
+    const int64_t i = blockIdx.x / chunks;
+    const int64_t c = blockIdx.x % chunks;
+    const int64_t r = src_row[i], a = d0[i], b = d1 ? d1[i] : -1;
+    if (r < 0 || r >= src_rows) return;
+    const bool wa = a >= 0 && a < dst_rows, wb = b >= 0 && b < dst_rows;
+    if (!wa && !wb) return;
+    const int64_t lo = c * kCopyChunk;
+    const int64_t hi = lo + kCopyChunk < row_elems ? lo + kCopyChunk : row_elems;
+    const double *s = src + r * row_elems;
+    double *da = dst + (wa ? a : 0) * row_elems, *db = dst + (wb ? b : 0) * row_elems;
+    if (vec2) {
+        const double2 *s2 = reinterpret_cast<const double2 *>(s);
+        double2 *da2 = reinterpret_cast<double2 *>(da), *db2 = reinterpret_cast<double2 *>(db);
+        for (int64_t e = lo / 2 + threadIdx.x; e < hi / 2; e += kCopyThreads) {
+            const double2 v = s2[e];
+            if (wa) da2[e] = v;
+            if (wb) db2[e] = v;
+        }
+    } else {
+        for (int64_t e = lo + threadIdx.x; e < hi; e += kCopyThreads) {
+            const double v = s[e];
+            if (wa) da[e] = v;
+            if (wb) db[e] = v;
+        }
+    }
+}
+
 // Launch the fused step in `variant`, attaching the stream's scratch when
 // the step needs it.
 int launch_step(StepArgs a, const double *U_in, double *U_out, double *amax, int32_t *status,
@@ -762,6 +801,25 @@ int hydro_rk3_destroy(hydro_rk3 *plan) {
     if (plan->scratch) hipFree(plan->scratch);
     delete plan;
     return HYDRO_OK;
+}
+
+int hydro_copy_blocks(const double *src, int64_t src_rows, const int64_t *src_row, double *dst,
+                      int64_t dst_rows, const int64_t *dst_row0, const int64_t *dst_row1, int n,
+                      int64_t row_elems, void *stream) {
+    if (n < 0 || row_elems < 1 || src_rows < 0 || dst_rows < 0) return HYDRO_EINVAL;
+    if (n == 0) return HYDRO_OK;
+    if (!src || !dst || !src_row || !dst_row0) return HYDRO_EINVAL;
+    const int64_t chunks = (row_elems + kCopyChunk - 1) / kCopyChunk;
+    if ((int64_t)n * chunks > INT32_MAX) return HYDRO_EINVAL;
+    int rc = check_device();
+    if (rc) return rc;
+    const int vec2 = row_elems % 2 == 0 && reinterpret_cast<uintptr_t>(src) % 16 == 0 &&
+                     reinterpret_cast<uintptr_t>(dst) % 16 == 0;
+    hipLaunchKernelGGL(k_copy_blocks, dim3((unsigned)(n * chunks)), dim3(kCopyThreads), 0,
+                       static_cast<hipStream_t>(stream), src, src_rows, src_row, dst, dst_rows,
+                       dst_row0, dst_row1, row_elems, (int)chunks, vec2);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? HYDRO_OK : fail_hip(e);
 }
 
 }  // extern "C"

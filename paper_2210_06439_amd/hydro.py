@@ -23,7 +23,7 @@ EXPORTS = [
     "hydro_fill_ghosts", "hydro_rate", "hydro_cfl_dt", "hydro_rk_update",
     "hydro_rk3_create", "hydro_rk3_launch", "hydro_rk3_destroy", "hydro_tau_resync",
     "hydro_rk_stage", "hydro_step_io", "hydro_workspace_bytes", "hydro_subgrid_n",
-    "hydro_step_gather", "hydro_step_noalloc",
+    "hydro_step_gather", "hydro_step_noalloc", "hydro_copy_blocks",
 ]
 
 STATUS_RHO, STATUS_P, STATUS_NONFINITE, STATUS_BADMETA = 1, 2, 4, 8
@@ -110,6 +110,7 @@ def lib(n: int = 8):
         L.hydro_rk_stage.argtypes = [P, B, vp, vp, vp, dbl, dbl, vp, vp, vp, vp]
         L.hydro_step_io.argtypes = [P, B, vp, vp, vp, vp, vp, vp]
         L.hydro_step_gather.argtypes = [P, B, G, vp, vp, vp, vp, vp]
+        L.hydro_copy_blocks.argtypes = [vp, i64, vp, vp, i64, vp, vp, ctypes.c_int, i64, vp]
         if L.hydro_subgrid_n() != n:
             raise HydroError(f"{path} reports subgrid size {L.hydro_subgrid_n()}, not {n}")
         _libs[n] = L
@@ -242,6 +243,21 @@ def step_io(prm: Params, batch: Batch, out_offset, U_in, U_out, amax, status=Non
     check(lib().hydro_step_io(ctypes.byref(prm), ctypes.byref(batch), _ptr(out_offset),
                               _ptr(U_in), _ptr(U_out), _ptr(amax), _ptr(status),
                               _stream(stream)))
+
+
+def copy_blocks(src, src_row, dst, dst_row0, dst_row1=None, row_elems=None, stream=None):
+    """Rows src_row[i] of src (row_elems doubles each) into rows dst_row0[i]
+    and dst_row1[i] of dst; src and dst are flat float64 device tensors, the
+    row indices int64 device tensors of one length."""
+    n = int(src_row.numel())
+    if row_elems is None:
+        raise HydroError("row_elems is required")
+    for t in (dst_row0, dst_row1):
+        if t is not None and int(t.numel()) != n:
+            raise HydroError("row index arrays differ in length")
+    check(lib().hydro_copy_blocks(_ptr(src), int(src.numel()) // int(row_elems), _ptr(src_row),
+                                  _ptr(dst), int(dst.numel()) // int(row_elems), _ptr(dst_row0),
+                                  _ptr(dst_row1), n, int(row_elems), _stream(stream)))
 
 
 def autotune(prm: Params, batch: Batch, U_in, U_out, amax, status=None, reps=3, stream=None):

@@ -432,9 +432,10 @@ class GpuBackend:
                 idx.copy_(self._idx_h[q][:3 * m], non_blocking=True)
                 self._idx_ev[q] = torch.cuda.Event()
                 self._idx_ev[q].record(self.copy)
-                blk = self.catalogue.U.view(-1, self.slot_elems).index_select(0, idx[:m])
-                rows.index_copy_(0, idx[m:2 * m], blk)
-                rows.index_copy_(0, idx[2 * m:3 * m], blk)
+                # each catalogue block read once, written to both copies
+                self.hydro.copy_blocks(self.catalogue.U, idx[:m], self.pool, idx[m:2 * m],
+                                       idx[2 * m:3 * m], row_elems=self.slot_elems,
+                                       stream=self.copy)
             for s in host:
                 q = torch.as_tensor(np.concatenate([s.slots, s.slots + self.n_slots]),
                                     device="cuda")

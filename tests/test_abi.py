@@ -55,3 +55,17 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
         hydro.lib()
     with pytest.raises(hydro.HydroError):
         hydro.lib(12)
+
+
+def test_copy_blocks_checks_its_arguments_before_the_device():
+    if not os.path.exists(hydro.lib_path(8)):
+        pytest.skip("library not built")
+    L = hydro.lib()
+    p = ctypes.c_void_p(16)      # never dereferenced: every call below returns first
+    assert L.hydro_copy_blocks(p, 4, p, p, 4, p, None, -1, 8, None) == -1
+    assert L.hydro_copy_blocks(p, 4, p, p, 4, p, None, 1, 0, None) == -1
+    assert L.hydro_copy_blocks(p, -1, p, p, 4, p, None, 1, 8, None) == -1
+    assert L.hydro_copy_blocks(None, 4, p, p, 4, p, None, 1, 8, None) == -1
+    assert L.hydro_copy_blocks(p, 4, p, p, 4, None, None, 1, 8, None) == -1
+    assert L.hydro_copy_blocks(p, 4, p, p, 4, p, None, 2 ** 30, 2 ** 20, None) == -1
+    assert L.hydro_copy_blocks(None, 0, None, None, 0, None, None, 0, 8, None) == 0
