@@ -20,12 +20,14 @@
  * box of (N+1) x N x N.  The N = 16 library provides the plain stages, the
  * entropy-tracer re-sync, the ghost fill, the CFL step size, the stage
  * combination and hydro_step.  The fused kernel maps the 8 x 8 cells of a
- * plane onto one 64-lane wave, so there hydro_step cuts each subgrid into the
- * eight 8^3 subgrids that tile it (14^3 blocks with their ghosts; the step is
- * local, so their interiors, largest speed and status are the subgrid's),
- * steps them with the 8^3 fused kernel and writes their interiors back, in
- * work buffers of its own per (device, stream): 3.9 MB per subgrid, counted
- * by hydro_workspace_bytes.  Its other fused entry points (hydro_step_variant,
+ * plane onto one 64-lane wave, so there hydro_step steps each subgrid as the
+ * eight 8^3 subgrids that tile it (14^3 windows of the block with their
+ * ghosts; the step is local, so their interiors, largest speed and status
+ * are the subgrid's): the 8^3 fused kernel, compiled into that library for
+ * the 16^3 block's row pitch, reads each window in place and writes its
+ * interior into the output block.  The tiles' metadata and per-tile results
+ * live in buffers of its own per (device, stream), 256 bytes per subgrid,
+ * counted by hydro_workspace_bytes.  Its other fused entry points (hydro_step_variant,
  * hydro_step_io, hydro_step_noalloc, hydro_autotune, hydro_plan_create,
  * hydro_rate, hydro_rk_stage, hydro_rk3_create) return HYDRO_EINVAL.
  *

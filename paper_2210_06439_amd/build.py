@@ -2,7 +2,8 @@
 hipcc -> paper_2210_06439_amd/libhydro.so (8^3 subgrids, every entry point)
 and paper_2210_06439_amd/libhydro_n16.so (16^3 subgrids: the plain stages,
 the time-integration helpers, and the fused step run on the eight 8^3 tiles of
-each subgrid, with the fused kernel compiled for 8^3 in that library too).
+each subgrid, with the fused kernel compiled in that library for 8^3 tiles
+read in place from 22^3 blocks).
 
 Usage: python -m paper_2210_06439_amd.build  (always recompiles)
 """
@@ -17,9 +18,11 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libhydro.so")
-# a source given as (file, n) is compiled for subgrid size n in that library
+# a source given as (file, n, defines) is compiled for subgrid size n, with
+# those defines, in that library
 SIZES = {8: ["api.hip", "plain.hip", "fused.hip", "evolve.hip"],
-         16: ["api.hip", "plain.hip", "evolve.hip", "tiles.hip", ("fused.hip", 8)]}
+         16: ["api.hip", "plain.hip", "evolve.hip", "tiles.hip",
+              ("fused.hip", 8, ["-DHYDRO_FUSED_GNB=22"])]}
 SOURCES = SIZES[8]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -44,10 +47,10 @@ def build(verbose: bool = False) -> str:
         os.makedirs(bdir, exist_ok=True)
         objs = []
         for entry in sources:
-            src, sn = (entry, n) if isinstance(entry, str) else entry
+            src, sn, defs = (entry, n, []) if isinstance(entry, str) else entry
             obj = os.path.join(bdir, src.replace(".hip", ".o"))
-            cmd = [HIPCC, *FLAGS, f"-DHYDRO_SUBGRID_N={sn}", "-c", os.path.join(CSRC, src),
-                   "-o", obj]
+            cmd = [HIPCC, *FLAGS, f"-DHYDRO_SUBGRID_N={sn}", *defs, "-c",
+                   os.path.join(CSRC, src), "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
             jobs.append((f"{src} (N={n})",

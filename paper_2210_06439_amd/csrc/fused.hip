@@ -33,6 +33,21 @@ static_assert(NSUB == 8, "the fused kernel maps the 8x8 cells of a plane onto a 
 
 namespace {
 
+// Row pitch of the blocks in global memory (GNB) and the global offset,
+// within a plane, of window cell c = j NB + i.  The LDS window always holds
+// NB-double rows; a library that steps the 8^3 tiles of larger blocks in
+// place (the 16^3 build) compiles this file with HYDRO_FUSED_GNB set to that
+// block's edge.
+#ifdef HYDRO_FUSED_GNB
+constexpr int GNB = HYDRO_FUSED_GNB;
+#define GCELL(c) (((c) / NB) * GNB + (c) % NB)
+#else
+constexpr int GNB = NB;
+#define GCELL(c) (c)
+#endif
+constexpr int GNP = GNB * GNB;
+static_assert(GNB >= NB, "a block row holds the tile's row");
+
 constexpr int NT = 512;                 // 8 waves
 constexpr int SLOTS = 5;                // window planes
 constexpr int PT = 16;                  // doubles per exchanged point
@@ -889,7 +904,7 @@ __device__ __forceinline__ void update_cell(const double *win, const double *kee
                                             const double *Fz, double lam, bool rate,
                                             const Stage &stg, const double *Us, double *Os,
                                             int fst, double &chk) {
-    const int cidx = opaque_v(kc * NPLANE + cj * NB + ci);
+    const int cidx = opaque_v(kc * GNP + cj * GNB + ci);
     const int fs = opaque_s(fst);
     const int f1x = f0 == 0 ? 6 : NF_MAX;
     double vv[NF_MAX];
@@ -926,7 +941,7 @@ __device__ __forceinline__ void update_cell_sum(const double *win, int kc, int c
                                                 int f0, int f1, const double *dsum, double lam,
                                                 bool rate, const Stage &stg, const double *Us,
                                                 double *Os, int fst, double &chk) {
-    const int cidx = opaque_v(kc * NPLANE + cj * NB + ci);
+    const int cidx = opaque_v(kc * GNP + cj * GNB + ci);
     const int fs = opaque_s(fst);
     const int f1x = f0 == 0 ? 6 : NF_MAX;
     double vv[NF_MAX];
@@ -984,7 +999,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
         const int f = e / NPLANE, c = e - f * NPLANE;
         const bool ok = e < nf * NPLANE;
         if (!GATHER) {
-            g_off[q] = ok ? f * fst0 + c : 0;
+            g_off[q] = ok ? f * fst0 + GCELL(c) : 0;
         } else {
             // the element's block cell, its ghost direction in x and y, and
             // its field, packed (lanes without an element: an interior cell
@@ -997,7 +1012,7 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
         l_off[q] = ok ? f * NPLANE + c : NF_MAX * NPLANE;
         if (q < 2) {
             mom[q] = VEL && ok && f >= 1 && f <= 3;
-            r_off[q] = c;
+            r_off[q] = GCELL(c);
         }
     }
     // source of element q of plane pk, and of the density of the same cell.
@@ -1008,11 +1023,11 @@ __device__ __forceinline__ void subgrid_body(double *win, double *xch, double *z
         return gather_ptr(Ug, toff, tmode, field ? (g >> 12) * fst0 : 0, g, pk);
     };
     auto src = [&](int q, int pk) -> const double * {
-        if (!GATHER) return Us0 + (g_off[q] + pk * NPLANE);   // one 64-bit add, as an index
+        if (!GATHER) return Us0 + (g_off[q] + pk * GNP);   // one 64-bit add, as an index
         return gsrc_of(q, pk, true);
     };
     auto src_rho = [&](int q, int pk) -> const double * {
-        if (!GATHER) return Us0 + (r_off[q] + pk * NPLANE);
+        if (!GATHER) return Us0 + (r_off[q] + pk * GNP);
         return gsrc_of(q, pk, false);
     };
 
@@ -1508,7 +1523,7 @@ __device__ __forceinline__ Line5 line5(int i, int j, int k, int dx, int dy, int 
 __device__ __forceinline__ void update_w(const double *lds, int kc, int ci, int cj, int lane,
                                          int d, const double *Fu, int fl, double lam, bool rate,
                                          const Stage &stg, double *Os, int fst, double &chk) {
-    const int cidx = opaque_v(kc * NPLANE + cj * NB + ci);
+    const int cidx = opaque_v(kc * GNP + cj * GNB + ci);
     double vv[6];
 #pragma unroll
     for (int f = 0; f < 6; f++) {
@@ -1569,7 +1584,7 @@ __device__ __forceinline__ PairOut subgrid_pair(
         const int f = e / NPLANE, c = e - f * NPLANE;
         const bool ok = e < 6 * NPLANE;
         if (!GATHER) {
-            g_off[q] = ok ? f * fst0 + c : 0;
+            g_off[q] = ok ? f * fst0 + GCELL(c) : 0;
         } else {
             const int i = ok ? c % NB : NG, j = ok ? c / NB : NG;
             const int dx = i < NG ? -1 : (i >= NG + NSUB ? 1 : 0);
@@ -1579,7 +1594,7 @@ __device__ __forceinline__ PairOut subgrid_pair(
         l_off[q] = ok ? f * NPLANE + c : 6 * NPLANE;
     }
     auto src = [&](int q, int pk) -> const double * {
-        if (!GATHER) return Us0 + (g_off[q] + pk * NPLANE);
+        if (!GATHER) return Us0 + (g_off[q] + pk * GNP);
         const int g = opaque_v(g_off[q]);
         return gather_ptr(Ug, toff, tmode, (g >> 12) * fst0, g, pk);
     };
@@ -2149,6 +2164,8 @@ void apply_variant(StepArgs &a, int v) {
 hipError_t launch_fused_step(const StepArgs &a0, const double *U_in, double *U_out,
                              double *amax, int32_t *status, int variant, hipStream_t st) {
     if (a0.n_sub == 0) return hipSuccess;
+    // the ghost map addresses NB-pitched blocks
+    if (GNB != NB && a0.gsrc) return hipErrorInvalidValue;
     StepArgs a = a0;
     apply_variant(a, variant);
     if (fused_needs_scratch(a, variant) && !a.scratch) return hipErrorInvalidValue;
@@ -2157,5 +2174,6 @@ hipError_t launch_fused_step(const StepArgs &a0, const double *U_in, double *U_o
     return hipGetLastError();
 }
 
+int fused_global_pitch() { return GNB; }
 
 }  // namespace hydro

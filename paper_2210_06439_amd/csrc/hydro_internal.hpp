@@ -182,9 +182,13 @@ int fused_default_variant(int n_sub);
 void apply_variant(StepArgs &a, int v);
 hipError_t launch_fused_step(const StepArgs &a, const double *U_in, double *U_out,
                              double *amax, int32_t *status, int variant, hipStream_t st);
-// The fused step of the 16^3 build (tiles.hip): each subgrid's eight 8^3 tiles
-// gathered into work buffers of the stream, stepped by the 8^3 fused kernel
-// (compiled into that library for 8^3) and scattered back.
+// Row pitch of the blocks the fused kernel reads and writes (its window's NB
+// unless the library steps the 8^3 tiles of larger blocks in place).
+int fused_global_pitch();
+// The fused step of the 16^3 build (tiles.hip): the 8^3 fused kernel
+// (compiled into that library for 8^3 tiles of 16^3 blocks) steps each
+// subgrid's eight 8^3 tiles in place, reading their 14^3 windows from the
+// block and writing their interiors into the output block.
 hipError_t launch_tiled_step(const StepArgs &a, const double *U_in, double *U_out, double *amax,
                              int32_t *status, void *stream);
 int64_t tiled_work_bytes(int dev);   // work buffers held on device dev

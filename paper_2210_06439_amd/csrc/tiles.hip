@@ -5,10 +5,11 @@
 // so a 16^3 subgrid and the eight 8^3 subgrids that tile it, cut with their
 // ghosts from the same (16+6)^3 block, have the same interiors, the same
 // largest face speed and the same status bits.  The fused kernel is written
-// for 8^3 subgrids (one 64-lane wave per 8 x 8 plane); this file gathers the
-// eight 14^3 tiles of every subgrid into a work buffer, runs that kernel over
-// them as one batch, scatters the tiles' interiors back and reduces their
-// speeds and status words per subgrid.
+// for 8^3 subgrids (one 64-lane wave per 8 x 8 plane); this library compiles
+// it with the 16^3 block's row pitch, so it reads each tile's 14^3 window
+// straight from the block and writes the tile's interior into the output
+// block.  This file lists the tiles and reduces their speeds and status
+// words per subgrid.
 #include <map>
 #include <mutex>
 #include <utility>
@@ -22,19 +23,15 @@ static_assert(NSUB == 16, "the tiled fused step serves the 16^3 build");
 namespace {
 
 constexpr int TN = 8;                    // tile interior
-constexpr int TB = TN + 2 * NG;          // 14: tile block incl. ghosts
-constexpr int TCELL = TB * TB * TB;
-constexpr int64_t kTileFs = 2752;        // field stride of a tile: 14^3 rounded up to 16
-constexpr int64_t kTileElems = NF_MAX * kTileFs;
 
 __device__ __forceinline__ bool meta_bad(int nsp, int64_t o) {
     return nsp < 0 || nsp > 5 || o < 0 || (o & 1);
 }
 
 // Tile t of subgrid s = t / 8 lies at (8 tx, 8 ty, 8 tz) of its block, with
-// t % 8 = 4 tz + 2 ty + tx; its metadata: a fixed slot of 11 fields, the
-// subgrid's h and species count (-1 when the subgrid's metadata is invalid,
-// which the fused kernel reports as such).
+// t % 8 = 4 tz + 2 ty + tx; its metadata: the offset of its 14^3 window in
+// the block, the subgrid's h and species count (-1 when the subgrid's
+// metadata is invalid, which the fused kernel reports as such).
 __global__ void k_tile_meta(int n, const int64_t *__restrict__ off, const double *__restrict__ h,
                             const int32_t *__restrict__ ns, int64_t *toff, double *th,
                             int32_t *tns) {
@@ -42,41 +39,12 @@ __global__ void k_tile_meta(int n, const int64_t *__restrict__ off, const double
     if (t >= 8 * n) return;
     const int s = t >> 3;
     const int nsp = ns[s];
-    toff[t] = (int64_t)t * kTileElems;
+    const int64_t o = off[s];
+    const int tx = t & 1, ty = (t >> 1) & 1, tz = (t >> 2) & 1;
+    const bool bad = meta_bad(nsp, o);
+    toff[t] = bad ? 0 : o + ((TN * tz) * NB + TN * ty) * NB + TN * tx;
     th[t] = h[s];
-    tns[t] = meta_bad(nsp, off[s]) ? -1 : nsp;
-}
-
-// One workgroup per (tile, field): the tile's 14^3 cells from the block.
-__global__ void k_tile_gather(const int64_t *__restrict__ off, const int32_t *__restrict__ ns,
-                              int fs, const double *__restrict__ U, double *__restrict__ T) {
-    const int t = blockIdx.x, f = blockIdx.y, s = t >> 3;
-    const int nsp = ns[s];
-    const int64_t o = off[s];
-    if (meta_bad(nsp, o) || f >= 6 + nsp) return;
-    const int tx = t & 1, ty = (t >> 1) & 1, tz = (t >> 2) & 1;
-    const double *src = U + o + (int64_t)f * fs + ((TN * tz) * NB + TN * ty) * NB + TN * tx;
-    double *dst = T + (int64_t)t * kTileElems + (int64_t)f * kTileFs;
-    for (int c = threadIdx.x; c < TCELL; c += blockDim.x) {
-        const int i = c % TB, j = (c / TB) % TB, k = c / (TB * TB);
-        dst[c] = src[(k * NB + j) * NB + i];
-    }
-}
-
-// One workgroup per (tile, field): the tile's 8^3 interior into the subgrid's.
-__global__ void k_tile_scatter(const int64_t *__restrict__ off, const int32_t *__restrict__ ns,
-                               int fs, const double *__restrict__ T, double *__restrict__ Uo) {
-    const int t = blockIdx.x, f = blockIdx.y, s = t >> 3;
-    const int nsp = ns[s];
-    const int64_t o = off[s];
-    if (meta_bad(nsp, o) || f >= 6 + nsp) return;
-    const int tx = t & 1, ty = (t >> 1) & 1, tz = (t >> 2) & 1;
-    const double *src = T + (int64_t)t * kTileElems + (int64_t)f * kTileFs + (NG * TB + NG) * TB + NG;
-    double *dst = Uo + o + (int64_t)f * fs + ((NG + TN * tz) * NB + NG + TN * ty) * NB + NG + TN * tx;
-    for (int c = threadIdx.x; c < TN * TN * TN; c += blockDim.x) {
-        const int i = c & 7, j = (c >> 3) & 7, k = c >> 6;
-        dst[(k * NB + j) * NB + i] = src[(k * TB + j) * TB + i];
-    }
+    tns[t] = bad ? -1 : nsp;
 }
 
 // The subgrid's largest face speed and status word from its eight tiles'
@@ -95,10 +63,10 @@ __global__ void k_tile_reduce(int n, const double *__restrict__ tam,
     if (status) status[s] = b;
 }
 
-// Work buffers per (device, stream), grown on demand.
+// Tile metadata and per-tile results per (device, stream), grown on demand.
 struct TileWork {
     int cap = 0;                 // subgrids
-    double *tin = nullptr, *tout = nullptr, *th = nullptr, *tam = nullptr;
+    double *th = nullptr, *tam = nullptr;
     int64_t *toff = nullptr;
     int32_t *tns = nullptr, *tst = nullptr;
 };
@@ -106,8 +74,6 @@ std::mutex g_tw_mu;
 std::map<std::pair<int, void *>, TileWork> g_tw;
 
 void tile_free(TileWork &w) {
-    hipFree(w.tin);
-    hipFree(w.tout);
     hipFree(w.th);
     hipFree(w.tam);
     hipFree(w.toff);
@@ -129,9 +95,7 @@ hipError_t tile_work(void *stream, int n, TileWork **out) {
             tile_free(w);
         }
         const size_t nt = (size_t)8 * n;
-        const size_t fb = nt * (size_t)kTileElems * sizeof(double);
-        if ((e = hipMalloc(&w.tin, fb)) == hipSuccess && (e = hipMalloc(&w.tout, fb)) == hipSuccess &&
-            (e = hipMalloc(&w.th, nt * sizeof(double))) == hipSuccess &&
+        if ((e = hipMalloc(&w.th, nt * sizeof(double))) == hipSuccess &&
             (e = hipMalloc(&w.tam, nt * sizeof(double))) == hipSuccess &&
             (e = hipMalloc(&w.toff, nt * sizeof(int64_t))) == hipSuccess &&
             (e = hipMalloc(&w.tns, nt * sizeof(int32_t))) == hipSuccess &&
@@ -154,8 +118,7 @@ int64_t tiled_work_bytes(int dev) {
     for (auto &kv : g_tw)
         if (kv.first.first == dev)
             b += (int64_t)kv.second.cap * 8 *
-                 (2 * kTileElems * (int64_t)sizeof(double) + 2 * sizeof(double) +
-                  sizeof(int64_t) + 2 * sizeof(int32_t));
+                 (2 * sizeof(double) + sizeof(int64_t) + 2 * sizeof(int32_t));
     return b;
 }
 
@@ -163,6 +126,7 @@ hipError_t launch_tiled_step(const StepArgs &a, const double *U_in, double *U_ou
                              int32_t *status, void *stream) {
     const int n = a.n_sub;
     if (n == 0) return hipSuccess;
+    if (fused_global_pitch() != NB) return hipErrorInvalidValue;   // built for other blocks
     TileWork *w = nullptr;
     hipError_t e = tile_work(stream, n, &w);
     if (e != hipSuccess) return e;
@@ -170,20 +134,17 @@ hipError_t launch_tiled_step(const StepArgs &a, const double *U_in, double *U_ou
     const int nt = 8 * n;
     hipLaunchKernelGGL(k_tile_meta, dim3((nt + 255) / 256), dim3(256), 0, st, n, a.offset, a.h,
                        a.n_species, w->toff, w->th, w->tns);
-    hipLaunchKernelGGL(k_tile_gather, dim3(nt, NF_MAX), dim3(256), 0, st, a.offset, a.n_species,
-                       a.fstride, U_in, w->tin);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    // the tiles as a batch of 8^3 subgrids, in the one-sweep shape (no scratch)
+    // the tiles as a batch of 8^3 subgrids in the blocks' layout (the output
+    // at the same offsets of U_out), in the one-sweep shape (no scratch)
     StepArgs ta = a;
     ta.n_sub = nt;
-    ta.fstride = (int32_t)kTileFs;
     ta.offset = w->toff;
+    ta.out_offset = nullptr;
     ta.h = w->th;
     ta.n_species = w->tns;
     ta.scratch = nullptr;
-    if ((e = launch_fused_step(ta, w->tin, w->tout, w->tam, w->tst, 1, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tile_scatter, dim3(nt, NF_MAX), dim3(256), 0, st, a.offset, a.n_species,
-                       a.fstride, w->tout, U_out);
+    if ((e = launch_fused_step(ta, U_in, U_out, w->tam, w->tst, 1, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_tile_reduce, dim3((n + 255) / 256), dim3(256), 0, st, n, w->tam, w->tst,
                        amax, status);
     return hipGetLastError();

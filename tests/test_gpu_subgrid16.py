@@ -128,6 +128,29 @@ def test_fused_step_16_is_its_tiles_step(flags):
     assert np.max(np.abs(ag - ar) / ar) <= 1e-13 and np.array_equal(sg, sr)
 
 
+def test_fused_step_16_flags_each_subgrid_alone():
+    """Invalid metadata in one subgrid: its status is the bad-metadata bit and
+    its output block is left as it was.  A NaN in another's interior: that
+    subgrid gets the 16^3 oracle's status word (the non-finite bit among
+    them).  The clean subgrid's results are those it has alone."""
+    T = torch()
+    U, off, h, ns, fs = _batch(seeds=(80, 81, 82), species=(5, 0, 5))
+    U = U.copy()
+    U[off[2] + (5 * NB + 7) * NB + 9] = np.nan       # density of interior cell (9, 7, 5)
+    dt = 2e-4
+    db = _device(U, off, h, ns, fs)
+    db.n_species[1] = 9
+    Ug, ag, sg = _fused16(db, dt)
+    assert sg[1] == hydro.STATUS_BADMETA
+    assert np.array_equal(Ug[off[1]:off[2]], U[off[1]:off[2]])
+    Ur, ar, sr = oracle.step(U, off, h, ns, fs, dt, n=N)
+    assert sg[2] == sr[2] and sg[2] & hydro.STATUS_NONFINITE
+    Ua, aa, sa = _fused16(_device(U[:off[1]].copy(), off[:1], h[:1], ns[:1], fs), dt)
+    assert np.array_equal(_interior(Ug, off, fs, 11, N, 0), _interior(Ua, off[:1], fs, 11, N, 0))
+    assert ag[0] == aa[0] and sg[0] == sa[0] == 0 == sr[0]
+    T.cuda.synchronize()
+
+
 def test_other_fused_entry_points_refuse_the_16_build():
     T = torch()
     U, off, h, ns, fs = _batch()
