@@ -10,6 +10,7 @@
 // straight from the block and writes the tile's interior into the output
 // block.  This file lists the tiles and reduces their speeds and status
 // words per subgrid.
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <utility>
@@ -110,6 +111,18 @@ hipError_t tile_work(void *stream, int n, TileWork **out) {
     return hipSuccess;
 }
 
+// The launch shape of the tile batch: one sweep per tile (the split and
+// dynamic shapes need scratch), persistent with one workgroup per CU and the
+// tiles in reverse order, the fastest such shape on thousands of 8^3 blocks.
+int tile_variant() {
+    static const int v = [] {
+        for (int i = 0; i < fused_variant_count(); i++)
+            if (!std::strcmp(fused_variant_name(i), "persistent-1x-rev")) return i;
+        return 1;
+    }();
+    return v;
+}
+
 }  // namespace
 
 int64_t tiled_work_bytes(int dev) {
@@ -136,7 +149,7 @@ hipError_t launch_tiled_step(const StepArgs &a, const double *U_in, double *U_ou
                        a.n_species, w->toff, w->th, w->tns);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // the tiles as a batch of 8^3 subgrids in the blocks' layout (the output
-    // at the same offsets of U_out), in the one-sweep shape (no scratch)
+    // at the same offsets of U_out), in a one-sweep shape (no scratch)
     StepArgs ta = a;
     ta.n_sub = nt;
     ta.offset = w->toff;
@@ -144,7 +157,8 @@ hipError_t launch_tiled_step(const StepArgs &a, const double *U_in, double *U_ou
     ta.h = w->th;
     ta.n_species = w->tns;
     ta.scratch = nullptr;
-    if ((e = launch_fused_step(ta, U_in, U_out, w->tam, w->tst, 1, st)) != hipSuccess) return e;
+    if ((e = launch_fused_step(ta, U_in, U_out, w->tam, w->tst, tile_variant(), st)) != hipSuccess)
+        return e;
     hipLaunchKernelGGL(k_tile_reduce, dim3((n + 255) / 256), dim3(256), 0, st, n, w->tam, w->tst,
                        amax, status);
     return hipGetLastError();
