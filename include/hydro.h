@@ -239,9 +239,9 @@ int hydro_step_io(const hydro_params *params, const hydro_batch *batch,
  * row_elems doubles each: row src_row[i] of src (a buffer of src_rows rows)
  * is read once and written to row dst_row0[i] and, when dst_row1 is not
  * NULL, row dst_row1[i] of dst (dst_rows rows).  This is how a serving loop
- * moves new requests' subgrid blocks (Sec. II, "Data-Structure": a subgrid
- * with its ghost layers is one contiguous block) from a resident catalogue
- * into both copies of their pool slots.  src_row, dst_row0 and dst_row1 are
+ * moves new requests' subgrids (Sec. II, "Data-Structure": subgrids with
+ * their ghost layers; in this library's layout each is one contiguous block)
+ * from a resident catalogue into both copies of their pool slots.  src_row, dst_row0 and dst_row1 are
  * device arrays of n int64.  A pair whose source index lies outside
  * [0, src_rows) writes nothing; a destination index outside [0, dst_rows) is
  * not written.  Destination rows must not overlap source rows and no two
